@@ -1,0 +1,383 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own code: numpy brute force,
+closed forms, textbook special cases, library routines (np.quantile,
+np.lexsort, np.searchsorted) and hand-derived values under tests/golden/.
+Each is chosen so that a plausible mistake in the oracle (a dropped term, a
+wrong sign or index, a transposed operand, a wrong nibble order or tie rule)
+fails at least one of them.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _unpack(codes, M):
+    """Nibble unpacking written independently: byte t = sub 2t (low) | sub 2t+1 (high)."""
+    lo = codes & 0x0F
+    hi = codes >> 4
+    out = np.empty((codes.shape[0], M), dtype=np.int64)
+    out[:, 0::2] = lo
+    out[:, 1::2] = hi
+    return out
+
+
+def _brute_codes_f64(X, C, M):
+    sub = X.shape[1] // M
+    Xs = X.astype(np.float64).reshape(X.shape[0], M, 1, sub)
+    d = ((Xs - C.astype(np.float64)[None]) ** 2).sum(-1)      # [N, M, 16]
+    return np.argmin(d, axis=-1), d
+
+
+def _reconstruct(codes_unpacked, C):
+    M = C.shape[0]
+    return np.concatenate([C[m][codes_unpacked[:, m]] for m in range(M)], axis=1).astype(np.float64)
+
+
+# ---------------------------------------------------------------- golden
+
+def test_golden_hand_example():
+    g = json.load(open(os.path.join(GOLDEN, "hand_example.json")))
+    M, J = g["M"], g["J"]
+    C = np.zeros((2, 16, 2), dtype=np.float32)
+    C[0, :, 0] = np.arange(16)
+    C[1, :, 1] = 2 * np.arange(16)
+    x = np.array([g["x"]], dtype=np.float32)
+    q = np.array([g["q"]], dtype=np.float32)
+    codes = oracle.encode(x, C, M)
+    assert codes[0, 0] == g["codes_byte"]
+    _, _, l8 = oracle.luts(q, C, M, "l2", 1.0, np.zeros(M, np.float32))
+    assert l8[0].tolist() == g["lut_l2"]
+    _, _, d8 = oracle.luts(q, C, M, "dot", 1.0, np.zeros(M, np.float32))
+    assert d8[0].tolist() == g["lut_dot"]
+    assert int(oracle.scan(codes, l8)[0, 0]) == g["sum_l2"]
+    assert int(oracle.scan(codes, d8)[0, 0]) == g["sum_dot"]
+
+
+def test_golden_paper_numbers():
+    """Byte accounting of the codes against the compression ratios and encode
+    rate the paper states (Sec. 4.3, Sec. 4.6)."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_numbers.json")))
+    for case in g["compression"]["cases"]:
+        M = 2 * case["code_bytes"]              # 4-bit codes: M subspaces -> M/2 bytes
+        J = case["J"]
+        Jp = -(-J // M) * M                     # the paper's MNIST row keeps J = 784
+        X = np.zeros((1, Jp), dtype=np.float32)
+        C = np.zeros((M, 16, Jp // M), dtype=np.float32)
+        codes = oracle.encode(X, C, M)
+        ratio = (4 * J) / codes.shape[1]
+        assert ratio == case["ratio"], case
+    e = g["encode_rate"]
+    rate = e["vectors_per_s"] * e["J"] * 4
+    assert abs(rate - e["bytes_per_s_approx"]) / e["bytes_per_s_approx"] < 0.03
+    assert abs(1e6 / e["vectors_per_s"] - e["sift1m_s"]) < 1e-12
+    assert abs(1e9 / e["vectors_per_s"] - e["sift1b_s"]) < 1e-9
+    assert g["codebook_size"]["pq_K"] // g["codebook_size"]["K"] == 16
+    assert 2 ** g["codebook_size"]["bits"] == g["codebook_size"]["K"]
+    assert list(oracle.ALPHAS) == g["alpha_grid"]["values"]
+
+
+# ---------------------------------------------------------------- encode
+
+@pytest.mark.parametrize("J,M", [(32, 8), (16, 16), (64, 8), (24, 2), (128, 32)])
+def test_encode_matches_exhaustive_argmin(J, M):
+    X = synth.normal(11 + J + M, (300, J))
+    C = synth.normal(12 + J + M, (M, 16, J // M))
+    codes, d32 = oracle.encode(X, C, M, want_dists=True)
+    ref, d64 = _brute_codes_f64(X, C, M)
+    got = _unpack(codes, M)
+    mism = got != ref
+    # fp32 and fp64 decisions may only differ on near-ties
+    if mism.any():
+        n, m = np.nonzero(mism)
+        gap = (d64[n, m, got[n, m]] - d64[n, m, ref[n, m]]) / np.maximum(d64[n, m, ref[n, m]], 1e-38)
+        assert (gap <= 1e-6).all()
+    assert mism.mean() < 1e-3
+    # the fp32 distances agree with the exact ones to fp32 accuracy
+    np.testing.assert_allclose(d32, d64, rtol=1e-5, atol=1e-6)
+
+
+def test_encode_exact_centroid_and_ties():
+    M, J = 4, 8
+    C = synth.normal(21, (M, 16, 2)).astype(np.float32)
+    # subvector equal to a centroid -> that centroid's index
+    rng = np.random.default_rng(0)
+    pick = rng.integers(0, 16, size=(50, M))
+    X = np.concatenate([C[m][pick[:, m]] for m in range(M)], axis=1)
+    assert (_unpack(oracle.encode(X, C, M), M) == pick).all()
+    # duplicate centroids: the lower index wins
+    C2 = C.copy()
+    C2[:, 9] = C2[:, 4]
+    X2 = np.concatenate([C2[m][np.full(50, 9)] for m in range(M)], axis=1)
+    assert (_unpack(oracle.encode(X2, C2, M), M) == 4).all()
+
+
+def test_encode_scalar_quantizer_special_case():
+    """J/M = 1: each subspace is a 16-level scalar quantiser; the nearest level
+    is found by binary search over the midpoints of the sorted levels."""
+    M = 8
+    levels = np.sort(synth.normal(31, (M, 16)), axis=1)
+    C = levels[:, :, None].astype(np.float32)
+    X = synth.normal(32, (500, M))
+    got = _unpack(oracle.encode(X, C, M), M)
+    for m in range(M):
+        mids = (levels[m, 1:].astype(np.float64) + levels[m, :-1]) / 2
+        ref = np.searchsorted(mids, X[:, m].astype(np.float64), side="left")
+        near = np.abs(X[:, m][:, None] - mids[None]).min(1) < 1e-6
+        assert (got[~near, m] == ref[~near]).all()
+
+
+def test_encode_m1_is_vector_quantisation():
+    """M = 1 (oracle-only): plain k-means vector quantisation, Sec. 3.1."""
+    C = synth.normal(41, (1, 16, 6))
+    X = synth.normal(42, (200, 6))
+    # M=1 is odd; pad a second empty-weight subspace by duplicating the space
+    X2 = np.concatenate([X, X], axis=1)
+    C2 = np.concatenate([C, C], axis=0)
+    got = _unpack(oracle.encode(X2, C2, 2), 2)
+    ref = np.argmin(((X[:, None, :].astype(np.float64) - C[0][None]) ** 2).sum(-1), axis=1)
+    assert (got[:, 0] == ref).mean() > 0.999
+    assert (got[:, 0] == got[:, 1]).all()
+
+
+# ---------------------------------------------------------------- LUTs
+
+@pytest.mark.parametrize("J,M", [(32, 8), (64, 16), (128, 32), (16, 2)])
+def test_lut_closed_form_reconstruction(J, M):
+    """Sum of the fp64 table entries selected by h(x) equals the distance to the
+    reconstruction x_hat (Sec. 3.1 sum of table entries; Sec. 3.3 Definition)."""
+    X = synth.normal(51 + J, (64, J))
+    Qv = synth.normal(52 + J, (8, J))
+    C = synth.normal(53 + J, (M, 16, J // M))
+    codes = oracle.encode(X, C, M)
+    cu = _unpack(codes, M)
+    xh = _reconstruct(cu, C)
+    l64, _, _ = oracle.luts(Qv, C, M, "l2")
+    d64, _, _ = oracle.luts(Qv, C, M, "dot")
+    q64 = Qv.astype(np.float64)
+    for q in range(len(Qv)):
+        s_l2 = l64[q][np.arange(M)[None, :], cu].sum(1)
+        s_dot = d64[q][np.arange(M)[None, :], cu].sum(1)
+        ref_l2 = ((q64[q][None] - xh) ** 2).sum(1)
+        ref_dot = xh @ q64[q]
+        np.testing.assert_allclose(s_l2, ref_l2, rtol=1e-12)
+        np.testing.assert_allclose(s_dot, ref_dot, rtol=1e-12, atol=1e-12 * np.abs(xh).sum())
+
+
+def test_lut_l2_dot_identity_and_fp32():
+    J, M = 64, 16
+    Qv = synth.normal(61, (10, J))
+    C = synth.normal(62, (M, 16, J // M))
+    l64, l32, _ = oracle.luts(Qv, C, M, "l2")
+    d64, d32, _ = oracle.luts(Qv, C, M, "dot")
+    sub = J // M
+    qn = (Qv.astype(np.float64).reshape(10, M, sub) ** 2).sum(-1)          # ||q^(m)||^2
+    cn = (C.astype(np.float64) ** 2).sum(-1)                                # ||c_i^(m)||^2
+    np.testing.assert_allclose(l64, qn[:, :, None] - 2 * d64 + cn[None], rtol=1e-12, atol=1e-12)
+    # the fp32 canonical tables match the exact ones to 1e-5 relative
+    assert (np.abs(l32 - l64) <= 1e-5 * l64 + 1e-30).all()
+    scale = (np.abs(Qv.astype(np.float64).reshape(10, M, 1, sub)) * np.abs(C[None])).sum(-1)
+    assert (np.abs(d32 - d64) <= 1e-5 * scale).all()
+
+
+def test_lut_u8_formula_exact():
+    """beta = clamp(floor(fma(a, y, -b')), 0, 255) (Sec. 3.2), checked with exact
+    rational arithmetic and round-to-nearest-even to fp32."""
+    J, M = 32, 8
+    Qv = synth.normal(71, (6, J))
+    C = synth.normal(72, (M, 16, J // M))
+    offs = synth.uniform(73, (M,), -3.0, 40.0)
+    a = np.float32(5.37)
+    _, l32, l8 = oracle.luts(Qv, C, M, "l2", float(a), offs)
+    for e in np.ndindex(l32.shape):
+        exact = Fraction(float(a)) * Fraction(float(l32[e])) - Fraction(float(offs[e[1]]))
+        r = np.float32(float(exact))            # float(Fraction) rounds to nearest double
+        # float(Fraction) -> double -> fp32 can double-round; re-round exactly when close
+        lo = np.nextafter(r, np.float32(-np.inf))
+        hi = np.nextafter(r, np.float32(np.inf))
+        cands = [lo, r, hi]
+        r = min(cands, key=lambda c: (abs(Fraction(float(c)) - exact),
+                                       int(np.float32(c).view(np.uint32)) & 1))
+        ref = min(max(int(np.floor(r)), 0), 255)
+        assert int(l8[e]) == ref, (e, float(l32[e]))
+
+
+def test_lut_u8_monotone_clamp_and_lemma1():
+    """Monotone, clamped, and inside the learned range the reconstruction error
+    satisfies 0 <= y - y_hat < 1/a (Sec. 3.3 Lemma 1, with the step 1/a)."""
+    J, M = 32, 8
+    Qv = synth.normal(81, (40, J))
+    C = synth.normal(82, (M, 16, J // M))
+    a = np.float32(3.0)
+    b = np.linspace(0.5, 4.0, M).astype(np.float64)
+    offs = (a * b).astype(np.float32)
+    _, l32, l8 = oracle.luts(Qv, C, M, "l2", float(a), offs)
+    for m in range(M):
+        y = l32[:, m, :].ravel().astype(np.float64)
+        beta = l8[:, m, :].ravel().astype(np.float64)
+        order = np.argsort(y, kind="stable")
+        assert (np.diff(beta[order]) >= 0).all()
+        lo = offs[m] / a
+        hi = lo + 255.0 / a
+        yh = (beta + offs[m]) / a
+        inside = (y >= lo) & (y < hi)
+        err = y - yh
+        slack = 1e-5 * np.maximum(np.abs(y), 1)
+        assert (err[inside] >= -slack[inside]).all()
+        assert (err[inside] < 1.0 / a + slack[inside]).all()
+        assert (beta[y < lo - 1e-6] == 0).all()
+        assert (beta[y >= hi + 1e-3] == 255).all()
+
+
+# ---------------------------------------------------------------- scan
+
+@pytest.mark.parametrize("M", [2, 8, 16, 32, 64, 256])
+def test_scan_brute_force(M):
+    codes = synth.random_codes(91 + M, 257, M)
+    lut = synth.random_luts(92 + M, 5, M)
+    S = oracle.scan(codes, lut)
+    cu = _unpack(codes, M)
+    ref = lut[:, np.arange(M)[None, :], cu].astype(np.int64).sum(-1)   # [Q, N]
+    assert (S.astype(np.int64) == ref).all()
+    assert ref.max() < 65536
+
+
+def test_scan_identity_constant_onehot_permutation():
+    M, N = 16, 300
+    codes = synth.random_codes(101, N, M)
+    cu = _unpack(codes, M)
+    # identity table on one subspace extracts that subspace's code
+    for m in (0, 1, 7, 14, 15):
+        lut = np.zeros((1, M, 16), np.uint8)
+        lut[0, m] = np.arange(16)
+        assert (oracle.scan(codes, lut)[0] == cu[:, m]).all()
+    # constant 255 tables -> 255*M everywhere
+    lut = np.full((1, M, 16), 255, np.uint8)
+    assert (oracle.scan(codes, lut)[0] == 255 * M).all()
+    # one-hot on code value v -> number of subspaces whose code is v
+    for v in (0, 5, 15):
+        lut = np.zeros((1, M, 16), np.uint8)
+        lut[0, :, v] = 1
+        assert (oracle.scan(codes, lut)[0] == (cu == v).sum(1)).all()
+    # permuting rows permutes outputs
+    lut = synth.random_luts(102, 3, M)
+    perm = np.random.default_rng(1).permutation(N)
+    assert (oracle.scan(codes[perm], lut) == oracle.scan(codes, lut)[:, perm]).all()
+    # pairs agree with the full scan
+    qs = np.array([0, 2, 1, 2]); ns = np.array([5, 0, 299, 17])
+    assert (oracle.scan_pairs(codes, lut, qs, ns) == oracle.scan(codes, lut)[qs, ns]).all()
+
+
+# ---------------------------------------------------------------- top-k
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_topk_lexsort(largest):
+    d = synth.integers(111, 0, 40, (7, 500)).astype(np.uint16)   # many ties
+    k = 25
+    vals, idx = oracle.topk(d, k, largest)
+    for q in range(7):
+        key = (-d[q].astype(np.int64)) if largest else d[q].astype(np.int64)
+        order = np.lexsort((np.arange(500), key))[:k]
+        assert (idx[q] == order).all()
+        assert (vals[q] == d[q][order]).all()
+
+
+def test_topk_pad_and_constant():
+    d = np.full((2, 5), 77, np.uint16)
+    vals, idx = oracle.topk(d, 8, False)
+    assert idx[0].tolist() == [0, 1, 2, 3, 4, -1, -1, -1]
+    assert vals[0].tolist() == [77] * 5 + [65535] * 3
+    vals, idx = oracle.topk(d, 8, True)
+    assert vals[1].tolist() == [77] * 5 + [0] * 3
+
+
+# ---------------------------------------------------------------- rescale and AMM bound
+
+def test_rescale_f32_matches_numpy_single():
+    S = synth.integers(121, 0, 65535, (1000,)).astype(np.uint16)
+    bias, scale = np.float32(-123.456), np.float32(1 / 7.77)
+    got = oracle.rescale_f32(S, float(bias), float(scale))
+    ref = (S.astype(np.float32) + bias) * scale
+    assert (got.view(np.uint32) == ref.view(np.uint32)).all()
+
+
+def test_amm_error_bound_lemma3_plus_lemma1():
+    """|q.x - S_hat| <= ||q|| ||x - x_hat|| + M/a when no entry is clipped
+    (Sec. 3.3 Lemma 3 for the codebook error plus Lemma 1, step 1/a, per table)."""
+    J, M = 64, 16
+    X = synth.normal(131, (400, J))
+    Qv = synth.normal(132, (12, J))
+    init = synth.permutation_prefix(133, 400, 16)
+    C, _ = oracle.kmeans(X, M, 5, init)
+    codes = oracle.encode(X, C, M)
+    cu = _unpack(codes, M)
+    xh = _reconstruct(cu, C)
+    d64, d32, _ = oracle.luts(Qv, C, M, "dot")
+    b = d64.min(axis=(0, 2))                                  # per-table minimum: no clipping at 0
+    a = np.float32(250.0 / (d64.max(axis=(0, 2)) - b).max())  # no clipping at 255
+    offs = (a * b).astype(np.float32)
+    _, _, l8 = oracle.luts(Qv, C, M, "dot", float(a), offs)
+    S = oracle.scan(codes, l8)
+    Sh = oracle.rescale_f64(S, float(a), offs)
+    exact = Qv.astype(np.float64) @ X.astype(np.float64).T
+    bound = (np.linalg.norm(Qv.astype(np.float64), axis=1)[:, None] *
+             np.linalg.norm(X.astype(np.float64) - xh, axis=1)[None] + M / float(a) * 1.0001)
+    assert (np.abs(exact - Sh) <= bound).all()
+    # Lemma 4 (triangle inequality) for the L2 side
+    for q in range(len(Qv)):
+        lhs = np.abs(np.linalg.norm(Qv[q] - X, axis=1) - np.linalg.norm(Qv[q] - xh, axis=1))
+        assert (lhs <= np.linalg.norm(X - xh, axis=1) + 1e-9).all()
+
+
+# ---------------------------------------------------------------- training (parity unpinned; invariants)
+
+def test_kmeans_invariants():
+    J, M = 32, 8
+    X = synth.normal(141, (3000, J))
+    init = synth.permutation_prefix(142, 3000, 16)
+    C, obj = oracle.kmeans(X, M, 8, init)
+    assert (np.diff(obj) <= 1e-9 * obj[0]).all()               # Lloyd never increases the objective
+    # well-separated clusters, one initial row in each: the centroids become
+    # the cluster means
+    centers = np.array([[0, 0], [10, 0], [0, 10], [10, 10]] * 4, dtype=np.float32) \
+        + np.repeat(np.arange(4), 4)[:, None] * 40
+    pts = np.repeat(centers, 30, axis=0) + synth.normal(143, (16 * 30, 2)) * 0.1
+    init2 = np.arange(0, 16 * 30, 30)
+    C2, _ = oracle.kmeans(np.concatenate([pts, pts], 1), 2, 3, init2)
+    np.testing.assert_allclose(np.sort(C2[0, :, 0]), np.sort(centers[:, 0]), atol=0.1)
+
+
+def test_quantizer_learning_matches_expanded_quantiles():
+    """The weighted quantiles equal np.quantile (linear, type 7) of the expanded
+    sample of y = D_m[h(x)_m](q) over all (query, vector) pairs, and the chosen
+    alpha is the grid argmin of the loss (Sec. 3.2)."""
+    J, M = 16, 4
+    X = synth.normal(151, (60, J))
+    init = synth.permutation_prefix(152, 60, 16)
+    C, _ = oracle.kmeans(X, M, 3, init)
+    codes = oracle.encode(X, C, M)
+    Qt = synth.normal(153, (7, J))
+    a, offs, best, losses = oracle.learn_quantizer(Qt, codes, C, "l2")
+    assert best == int(np.argmin(losses))
+    alpha = oracle.ALPHAS[best]
+    l64, _, _ = oracle.luts(Qt, C, M, "l2")
+    cu = _unpack(codes, M)
+    Y = np.stack([l64[:, m, :][:, cu[:, m]].ravel() for m in range(M)])    # [M, nq*n]
+    b = np.quantile(Y, alpha, axis=1)
+    pool = (Y - b[:, None]).ravel()
+    top = np.quantile(pool, 1 - alpha)
+    a_ref = np.float32(255.0 / top)
+    assert a == pytest.approx(float(a_ref), rel=1e-6)
+    np.testing.assert_allclose(offs, (np.float64(a_ref) * b).astype(np.float32), rtol=1e-5, atol=1e-4)
+    # loss of the chosen alpha recomputed from the expanded sample
+    beta = np.clip(np.floor(np.float64(a) * Y - offs[:, None].astype(np.float64)), 0, 255)
+    yh = (beta + offs[:, None]) / np.float64(a)
+    assert losses[best] == pytest.approx(((yh - Y) ** 2).mean(), rel=1e-9)
