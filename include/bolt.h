@@ -1,0 +1,221 @@
+/*
+ * bolt.h -- C ABI of the MI355X (gfx950) Bolt hot path.
+ *
+ * Bolt (Blalock & Guttag, KDD 2017) approximates a distance or similarity
+ * that is a sum over dimensions (Sec. 1.1) with three functions: h encodes
+ * database vectors to M 4-bit codes, g turns a query into M lookup tables of
+ * 16 entries quantised to uint8, and d_hat sums one entry per table for each
+ * encoded vector (Sec. 3.1, Sec. 3.2).  This library implements h, g and
+ * d_hat, plus top-k retrieval (Sec. 1.2), as HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers: every array argument is a caller-owned DEVICE pointer unless the
+ *   entry point says "host".  The library never takes ownership.  Outputs
+ *   must not alias inputs.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *   stream).  Calls validate their arguments on the host, then enqueue work
+ *   on the stream and return without waiting.  A kernel fault is reported by
+ *   the HIP runtime at the next synchronisation or call (BOLT_ERR_DEVICE).
+ * Workspace: entry points that need scratch memory take `ws`/`ws_bytes`
+ *   (device memory owned by the caller); the matching *_ws_bytes() function
+ *   gives the size.  Too small a workspace returns BOLT_ERR_NOMEM.
+ * Shapes: J % M == 0, M even and 2 <= M <= 256 (codes pack two 4-bit codes
+ *   per byte, and M <= 256 keeps every sum below 65536).  N and Q may be 0
+ *   (nothing is enqueued).  N <= 2^31 - 1 per database.
+ * Inputs must be finite (NaN and Inf are not supported).
+ * Errors: every call returns a bolt_status; bolt_last_error() gives a
+ *   message for the calling thread's last failure.
+ *
+ * Layouts (canonical; the paper fixes none of them)
+ *   X, Qv      fp32 [rows][ld], the first J columns used
+ *   centroids  fp32 [M][16][J/M]: codebook m, centroid i, sub-dimension.
+ *              Subspace m covers dimensions [m*J/M, (m+1)*J/M) (Sec. 3.1:
+ *              consecutive indices).
+ *   codes      uint8 [N][M/2]: byte t holds the code of subspace 2t in bits
+ *              0-3 and of subspace 2t+1 in bits 4-7.
+ *   luts       [Q][M][16]: table m of query q, entry i.
+ */
+#ifndef BOLT_H
+#define BOLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bolt_status {
+    BOLT_OK = 0,
+    BOLT_ERR_INVALID = -1,     /* null pointer with size > 0, bad k, bad ld, misalignment */
+    BOLT_ERR_SHAPE = -2,       /* J % M != 0, M odd, M outside [2, 256], N too large */
+    BOLT_ERR_UNSUPPORTED = -3, /* a valid request this build does not handle (e.g. k > 2048) */
+    BOLT_ERR_DEVICE = -4,      /* the HIP runtime reported an error */
+    BOLT_ERR_NOMEM = -5        /* workspace too small */
+} bolt_status;
+
+enum { BOLT_METRIC_L2 = 0, BOLT_METRIC_DOT = 1 };
+
+enum { BOLT_TOPK_MAX_K = 2048 };
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char *bolt_last_error(void);
+
+/* Library version string. */
+const char *bolt_version(void);
+
+/*
+ * Data encoding h (Sec. 3.1, definition of h; K = 16 centroids per
+ * codebook, Sec. 3.2).  For each row n and subspace m, codes receives the
+ * index of the centroid of codebook m nearest to x_n^(m) in squared
+ * Euclidean distance (whatever the task metric), ties to the lowest index.
+ * Distances are computed in fp32 in the order
+ *     acc = 0; for j ascending: t = x_j - c_j; acc = fma(t, t, acc).
+ *
+ *   X          device fp32 [N][ldx], ldx >= J
+ *   N          rows (0 allowed)
+ *   J          dimensions, J % M == 0
+ *   ldx        row stride of X in elements
+ *   centroids  device fp32 [M][16][J/M]
+ *   M          subspaces (even, 2..256)
+ *   codes      device uint8 [N][M/2], written completely
+ */
+int bolt_encode(const float *X, int64_t N, int32_t J, int64_t ldx,
+                const float *centroids, int32_t M, uint8_t *codes, void *stream);
+
+/*
+ * Query encoding g with the learned uint8 quantisation (Sec. 3.1,
+ * definition of D; Sec. 3.2, beta_m).  For query q, table m, entry i:
+ *     D = sum over j in subspace m of delta(q_j, c_ij), in fp32, j ascending,
+ *         squared L2: t = q_j - c_ij; acc = fma(t, t, acc)
+ *         dot:        acc = fma(q_j, c_ij, acc)
+ *     beta = clamp(floor(fma(a, D, -offsets[m])), 0, 255)
+ * offsets[m] is the table offset in quantised units, b'_m = a * F_m^-1(alpha),
+ * so that the learned lower quantile maps to 0 (Sec. 3.2).
+ *
+ *   Qv         device fp32 [Q][ldq]
+ *   metric     BOLT_METRIC_L2 or BOLT_METRIC_DOT
+ *   a          shared scale (> 0), host scalar
+ *   offsets    device fp32 [M]
+ *   luts_f32   device fp32 [Q][M][16] or NULL (the unquantised D)
+ *   luts_u8    device uint8 [Q][M][16] or NULL
+ */
+int bolt_build_luts(const float *Qv, int64_t Q, int32_t J, int64_t ldq,
+                    const float *centroids, int32_t M, int32_t metric, float a,
+                    const float *offsets, float *luts_f32, uint8_t *luts_u8,
+                    void *stream);
+
+/*
+ * The scan d_hat (Sec. 3.1, approximate distance as the sum of the table
+ * entries selected by the codes; vectorised lookups, Sec. 3.2):
+ *     out[q][n] = sum over m of luts_u8[q][m][code(n, m)]
+ * an exact integer (below 65536 since M <= 256).  The monotone outer f of
+ * the distance form (Sec. 1.1) is not applied.  The two entry points do the
+ * same arithmetic; they exist so that callers name the metric the tables
+ * were built for.
+ *
+ *   codes      device uint8 [N][M/2]
+ *   luts_u8    device uint8 [Q][M][16]
+ *   out        device uint16 [Q][ldo], ldo >= N
+ */
+int bolt_scan_l2(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                 int64_t Q, uint16_t *out, int64_t ldo, void *stream);
+int bolt_scan_dot(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                  int64_t Q, uint16_t *out, int64_t ldo, void *stream);
+
+/*
+ * Top-k retrieval (Sec. 1.2, the k closest vectors; Sec. 4.5 ranks by the
+ * smallest approximate distance).  For each of the Q rows of dists, the k
+ * smallest values (largest = 0, squared L2) or the k largest (largest = 1,
+ * dot product / maximum inner product search), ordered by value and, among
+ * equal values, by ascending index.  If k > N the tail is padded with
+ * vals = 65535 (largest = 0) or 0 (largest = 1) and idx = -1.
+ *
+ *   dists      device uint16 [Q][ldd]
+ *   k          1 .. BOLT_TOPK_MAX_K
+ *   vals       device uint16 [Q][k]
+ *   idx        device int32 [Q][k]
+ *   ws         device workspace of bolt_topk_ws_bytes(Q, N, k) bytes
+ */
+size_t bolt_topk_ws_bytes(int64_t Q, int64_t N, int32_t k);
+int bolt_topk(const uint16_t *dists, int64_t Q, int64_t N, int64_t ldd, int32_t k,
+              int32_t largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
+              void *stream);
+
+/*
+ * Scan followed by top-k without materialising the [Q][N] sums: the same
+ * result as bolt_scan_* then bolt_topk with largest = (metric == DOT).
+ *
+ *   metric     BOLT_METRIC_L2 (k smallest) or BOLT_METRIC_DOT (k largest)
+ *   ws         device workspace of bolt_scan_topk_ws_bytes(N, M, Q, k) bytes
+ */
+size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k);
+int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                   int64_t Q, int32_t metric, int32_t k, uint16_t *vals, int32_t *idx,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Approximate matrix product (Sec. 4.4: rows of the first matrix are the
+ * database, columns of the second are the queries).  With dot-product
+ * tables for the K query columns, the product entry is the scan sum S
+ * rescaled to the original units (Sec. 3.2: y_hat = (beta + b) / a, the
+ * per-table offsets adding up to one bias):
+ *     out = fp32( fp32(S + bias) * scale ),  bias = sum_m offsets[m], scale = 1/a
+ * with both roundings as written.
+ *
+ *   codes      device uint8 [N][M/2]   (the encoded first matrix, N rows)
+ *   luts_u8    device uint8 [K][M][16] (dot tables of the K columns)
+ *   bias       host fp32 scalar
+ *   scale      host fp32 scalar
+ *   out        device fp32; transpose = 0: [K][ldo] (ldo >= N),
+ *              transpose = 1: [N][ldo] (ldo >= K)
+ */
+int bolt_amm(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+             int64_t K, float bias, float scale, float *out, int64_t ldo,
+             int32_t transpose, void *stream);
+
+/*
+ * Offline phase (Sec. 1.2), on the HOST: codebooks by k-means with K = 16
+ * per subspace (Sec. 3.1, 3.2), then the quantiser of Sec. 3.2 for one
+ * metric.  All pointers are HOST pointers.  Random choices are inputs:
+ * init_rows holds the 16 training rows that seed every codebook.
+ *
+ *   X          host fp32 [n][ldx] training vectors
+ *   iters      Lloyd iterations (assignment ties to the lowest index; an empty
+ *              cluster keeps its centroid)
+ *   init_rows  host int64 [16], distinct rows of X
+ *   Qt         host fp32 [nq][ldq] training queries
+ *   metric     metric the tables will be built for
+ *   alphas     host fp64 [nalpha] grid of tail fractions
+ *   centroids  host fp32 [M][16][J/M] (output)
+ *   a          host fp32 (output): shared scale
+ *   offsets    host fp32 [M] (output): b'_m = a * F_m^-1(alpha)
+ *   alpha_idx  host int32 (output, may be NULL): the chosen grid index
+ * The distribution of table m is the multiset of D_m[h(x)_m](q) over all
+ * (training query, training vector) pairs; b_m is its alpha-quantile, a =
+ * 255 / (1-alpha)-quantile of (y - b_m) pooled over all tables (1 if that
+ * is not positive), quantiles by linear interpolation between order
+ * statistics; the alpha with the smallest mean squared reconstruction error
+ * wins, ties to the smaller alpha.
+ */
+int bolt_train_host(const float *X, int64_t n, int32_t J, int64_t ldx, int32_t M,
+                    int32_t iters, const int64_t *init_rows, const float *Qt, int64_t nq,
+                    int64_t ldq, int32_t metric, const double *alphas, int32_t nalpha,
+                    float *centroids, float *a, float *offsets, int32_t *alpha_idx);
+
+/*
+ * Quantiser only (the second half of bolt_train_host) for already learned
+ * centroids: lets one set of codebooks serve both metrics.  HOST pointers;
+ * codes are the packed codes of the n training vectors.
+ */
+int bolt_learn_quantizer_host(const float *Qt, int64_t nq, int32_t J, int64_t ldq,
+                              const uint8_t *codes, int64_t n, const float *centroids,
+                              int32_t M, int32_t metric, const double *alphas,
+                              int32_t nalpha, float *a, float *offsets, int32_t *alpha_idx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BOLT_H */

@@ -1,0 +1,286 @@
+"""Python binding of libbolt.so: the same entry points as include/bolt.h.
+
+Only argument marshalling happens here (torch tensors -> device pointers,
+the current HIP stream); every step of the hot path runs in the HIP
+kernels.  The library must be built (``python -m paper_1706_10283_amd.build``
+or ``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbolt.so")
+
+BOLT_OK = 0
+BOLT_ERR_INVALID = -1
+BOLT_ERR_SHAPE = -2
+BOLT_ERR_UNSUPPORTED = -3
+BOLT_ERR_DEVICE = -4
+BOLT_ERR_NOMEM = -5
+METRIC_L2 = 0
+METRIC_DOT = 1
+TOPK_MAX_K = 2048
+ALPHAS = (0.0, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1)
+
+_STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "SHAPE", -3: "UNSUPPORTED", -4: "DEVICE", -5: "NOMEM"}
+
+
+class BoltError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("bolt status %d (%s): %s" % (status, _STATUS_NAMES.get(status, "?"), message))
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libbolt.so is not built: run `python -m paper_1706_10283_amd.build` "
+                      "(the HIP library is required; there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_F32 = ctypes.c_float
+_SZ = ctypes.c_size_t
+
+_SIGS = {
+    "bolt_last_error": ([], ctypes.c_char_p),
+    "bolt_version": ([], ctypes.c_char_p),
+    "bolt_encode": ([_P, _I64, _I32, _I64, _P, _I32, _P, _P], ctypes.c_int),
+    "bolt_build_luts": ([_P, _I64, _I32, _I64, _P, _I32, _I32, _F32, _P, _P, _P, _P], ctypes.c_int),
+    "bolt_scan_l2": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
+    "bolt_scan_dot": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
+    "bolt_topk_ws_bytes": ([_I64, _I64, _I32], _SZ),
+    "bolt_topk": ([_P, _I64, _I64, _I64, _I32, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "bolt_scan_topk_ws_bytes": ([_I64, _I32, _I64, _I32], _SZ),
+    "bolt_scan_topk": ([_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "bolt_amm": ([_P, _I64, _I32, _P, _I64, _F32, _F32, _P, _I64, _I32, _P], ctypes.c_int),
+    "bolt_train_host": ([_P, _I64, _I32, _I64, _I32, _I32, _P, _P, _I64, _I64, _I32, _P, _I32,
+                         _P, _P, _P, _P], ctypes.c_int),
+    "bolt_learn_quantizer_host": ([_P, _I64, _I32, _I64, _P, _I64, _P, _I32, _I32, _P, _I32,
+                                   _P, _P, _P], ctypes.c_int),
+    "bolt_debug_force_scan_kernel": ([_I32], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+def lib():
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.bolt_last_error().decode()
+
+
+def version() -> str:
+    return _lib.bolt_version().decode()
+
+
+def _check(status):
+    if status != BOLT_OK:
+        raise BoltError(status, last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        return _P(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _P(stream)
+    return _P(stream.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    return t
+
+
+def _ptr(t):
+    return _P(t.data_ptr()) if t is not None else _P(0)
+
+
+def _rows(t, name):
+    """(rows, cols, row stride) of a 2-D tensor with unit column stride."""
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if t.numel() == 0:
+        return t.shape[0], t.shape[1], t.shape[1]
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError("%s must have contiguous rows" % name)
+    return t.shape[0], t.shape[1], max(t.stride(0), t.shape[1])
+
+
+def metric_id(metric):
+    if metric in (METRIC_L2, METRIC_DOT):
+        return int(metric)
+    return {"l2": METRIC_L2, "dot": METRIC_DOT}[metric]
+
+
+# ------------------------------------------------------------------ hot path
+
+def bolt_encode(X, centroids, M, codes=None, stream=None):
+    """codes uint8 [N, M/2] of fp32 rows X [N, J] (nearest centroid per subspace)."""
+    _dev(X, torch.float32, "X")
+    _dev(centroids, torch.float32, "centroids")
+    N, J, ldx = _rows(X, "X")
+    if not centroids.is_contiguous() or centroids.numel() != 16 * J:
+        raise ValueError("centroids must be contiguous [M, 16, J/M]")
+    if codes is None:
+        codes = torch.empty((N, M // 2), dtype=torch.uint8, device=X.device)
+    _dev(codes, torch.uint8, "codes")
+    _check(_lib.bolt_encode(_ptr(X), N, J, ldx, _ptr(centroids), M, _ptr(codes), _stream(stream)))
+    return codes
+
+
+def bolt_build_luts(Qv, centroids, M, metric, a, offsets, luts_u8=None, luts_f32=None,
+                    want_f32=False, want_u8=True, stream=None):
+    """uint8 tables [Q, M, 16] (and fp32 tables if asked) of the queries Qv [Q, J]."""
+    _dev(Qv, torch.float32, "Qv")
+    _dev(centroids, torch.float32, "centroids")
+    Q, J, ldq = _rows(Qv, "Qv")
+    if offsets is not None:
+        _dev(offsets, torch.float32, "offsets")
+    if want_u8 and luts_u8 is None:
+        luts_u8 = torch.empty((Q, M, 16), dtype=torch.uint8, device=Qv.device)
+    if want_f32 and luts_f32 is None:
+        luts_f32 = torch.empty((Q, M, 16), dtype=torch.float32, device=Qv.device)
+    _check(_lib.bolt_build_luts(_ptr(Qv), Q, J, ldq, _ptr(centroids), M, metric_id(metric),
+                                float(a), _ptr(offsets), _ptr(luts_f32), _ptr(luts_u8),
+                                _stream(stream)))
+    if want_f32 and want_u8:
+        return luts_u8, luts_f32
+    return luts_u8 if want_u8 else luts_f32
+
+
+def _scan(fn, codes, luts_u8, out, stream):
+    _dev(codes, torch.uint8, "codes")
+    _dev(luts_u8, torch.uint8, "luts_u8")
+    N = codes.shape[0]
+    Q, M = luts_u8.shape[0], luts_u8.shape[1]
+    if codes.dim() != 2 or codes.shape[1] != M // 2 or not codes.is_contiguous():
+        raise ValueError("codes must be contiguous [N, M/2]")
+    if out is None:
+        out = torch.empty((Q, N), dtype=torch.uint16, device=codes.device)
+    _dev(out, torch.uint16, "out")
+    ldo = out.stride(0) if Q > 0 else N
+    _check(fn(_ptr(codes), N, M, _ptr(luts_u8), Q, _ptr(out), max(ldo, N), _stream(stream)))
+    return out
+
+
+def bolt_scan_l2(codes, luts_u8, out=None, stream=None):
+    """uint16 sums [Q, N] = sum_m luts[q, m, code(n, m)]."""
+    return _scan(_lib.bolt_scan_l2, codes, luts_u8, out, stream)
+
+
+def bolt_scan_dot(codes, luts_u8, out=None, stream=None):
+    return _scan(_lib.bolt_scan_dot, codes, luts_u8, out, stream)
+
+
+def bolt_topk(dists, k, largest=False, vals=None, idx=None, stream=None):
+    """(vals uint16 [Q, k], idx int32 [Q, k]) of each row of dists [Q, N]."""
+    _dev(dists, torch.uint16, "dists")
+    Q, N, ldd = _rows(dists, "dists")
+    if vals is None:
+        vals = torch.empty((Q, k), dtype=torch.uint16, device=dists.device)
+    if idx is None:
+        idx = torch.empty((Q, k), dtype=torch.int32, device=dists.device)
+    nws = _lib.bolt_topk_ws_bytes(Q, N, k)
+    ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dists.device)
+    _check(_lib.bolt_topk(_ptr(dists), Q, N, ldd, k, 1 if largest else 0, _ptr(vals), _ptr(idx),
+                          _ptr(ws), nws, _stream(stream)))
+    return vals, idx
+
+
+def bolt_scan_topk_ws_bytes(N, M, Q, k):
+    return int(_lib.bolt_scan_topk_ws_bytes(N, M, Q, k))
+
+
+def bolt_scan_topk(codes, luts_u8, metric, k, vals=None, idx=None, ws=None, stream=None):
+    """Fused scan + top-k: (vals, idx) as bolt_topk(bolt_scan(...)) with largest = dot."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(luts_u8, torch.uint8, "luts_u8")
+    N = codes.shape[0]
+    Q, M = luts_u8.shape[0], luts_u8.shape[1]
+    if vals is None:
+        vals = torch.empty((Q, k), dtype=torch.uint16, device=codes.device)
+    if idx is None:
+        idx = torch.empty((Q, k), dtype=torch.int32, device=codes.device)
+    nws = bolt_scan_topk_ws_bytes(N, M, Q, k)
+    if ws is None:
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=codes.device)
+    wsb = ws.numel() * ws.element_size()
+    _check(_lib.bolt_scan_topk(_ptr(codes), N, M, _ptr(luts_u8), Q, metric_id(metric), k,
+                               _ptr(vals), _ptr(idx), _ptr(ws), wsb, _stream(stream)))
+    return vals, idx
+
+
+def bolt_amm(codes, luts_u8, bias, scale, out=None, transpose=False, stream=None):
+    """Approximate product: fp32 (S + bias) * scale, [K, N] or [N, K] if transpose."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(luts_u8, torch.uint8, "luts_u8")
+    N = codes.shape[0]
+    K, M = luts_u8.shape[0], luts_u8.shape[1]
+    if out is None:
+        shape = (N, K) if transpose else (K, N)
+        out = torch.empty(shape, dtype=torch.float32, device=codes.device)
+    _dev(out, torch.float32, "out")
+    ldo = out.stride(0) if out.shape[0] > 0 else (K if transpose else N)
+    _check(_lib.bolt_amm(_ptr(codes), N, M, _ptr(luts_u8), K, float(bias), float(scale),
+                         _ptr(out), ldo, 1 if transpose else 0, _stream(stream)))
+    return out
+
+
+# ------------------------------------------------------------------ host training
+
+def _np_ptr(a):
+    return _P(a.ctypes.data) if a is not None else _P(0)
+
+
+def bolt_train_host(X, M, iters, init_rows, Qt, metric, alphas=ALPHAS):
+    """Offline phase on the host: (centroids [M,16,J/M], a, offsets [M], alpha index)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Qt = np.ascontiguousarray(Qt, dtype=np.float32)
+    init_rows = np.ascontiguousarray(init_rows, dtype=np.int64)
+    alphas = np.ascontiguousarray(alphas, dtype=np.float64)
+    n, J = X.shape
+    C = np.zeros((M, 16, J // M), dtype=np.float32)
+    a = np.zeros(1, dtype=np.float32)
+    offs = np.zeros(M, dtype=np.float32)
+    ai = np.zeros(1, dtype=np.int32)
+    _check(_lib.bolt_train_host(_np_ptr(X), n, J, J, M, iters, _np_ptr(init_rows), _np_ptr(Qt),
+                                Qt.shape[0], J, metric_id(metric), _np_ptr(alphas), len(alphas),
+                                _np_ptr(C), _np_ptr(a), _np_ptr(offs), _np_ptr(ai)))
+    return C, float(a[0]), offs, int(ai[0])
+
+
+def bolt_learn_quantizer_host(Qt, codes, centroids, metric, alphas=ALPHAS):
+    """Quantiser for existing codebooks: (a, offsets [M], alpha index)."""
+    Qt = np.ascontiguousarray(Qt, dtype=np.float32)
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    C = np.ascontiguousarray(centroids, dtype=np.float32)
+    alphas = np.ascontiguousarray(alphas, dtype=np.float64)
+    M = C.shape[0]
+    J = Qt.shape[1]
+    a = np.zeros(1, dtype=np.float32)
+    offs = np.zeros(M, dtype=np.float32)
+    ai = np.zeros(1, dtype=np.int32)
+    _check(_lib.bolt_learn_quantizer_host(_np_ptr(Qt), Qt.shape[0], J, J, _np_ptr(codes),
+                                          codes.shape[0], _np_ptr(C), M, metric_id(metric),
+                                          _np_ptr(alphas), len(alphas), _np_ptr(a), _np_ptr(offs),
+                                          _np_ptr(ai)))
+    return float(a[0]), offs, int(ai[0])
+
+
+def debug_force_scan_kernel(kind: int):
+    """Test hook: -1 automatic, 0 generic, 1 few-query, 2 grouped."""
+    _check(_lib.bolt_debug_force_scan_kernel(kind))

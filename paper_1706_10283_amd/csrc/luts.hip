@@ -1,0 +1,74 @@
+// Query encoding g and its uint8 quantisation for gfx950 (Sec. 3.1, the
+// matrix D of a query; Sec. 3.2, the learned quantiser beta_m).
+//
+// One thread per table entry (query q, table m, entry i).  The 16 threads of
+// one table read the same query subvector (a broadcast) and neighbouring
+// centroids.  Each entry is accumulated sequentially in ascending dimension
+// order with fma, and quantised with a single fma, floor and clamp, so the
+// uint8 value is reproducible bit for bit.  The work is Theta(K J) per query
+// (Sec. 3.1) and tiny next to the scan.
+#include "common.hpp"
+
+namespace {
+
+__global__ __launch_bounds__(256) void luts_kernel(
+    const float *__restrict__ Qv, int64_t Q, int64_t ldq, const float *__restrict__ C, int M,
+    int sub, int metric, float a, const float *__restrict__ offsets, float *__restrict__ lf,
+    uint8_t *__restrict__ l8)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= Q * M * bolt::kCentroids)
+        return;
+    const int i = (int)(e & 15);
+    const int64_t qm = e >> 4;
+    const int64_t q = qm / M;
+    const int m = (int)(qm - q * M);
+    const float *qv = Qv + q * ldq + (int64_t)m * sub;
+    const float *c = C + ((int64_t)m * bolt::kCentroids + i) * sub;
+    float acc = 0.0f;
+    if (metric == BOLT_METRIC_L2) {
+        for (int j = 0; j < sub; ++j) {
+            float t = qv[j] - c[j];
+            acc = __builtin_fmaf(t, t, acc);
+        }
+    } else {
+        for (int j = 0; j < sub; ++j)
+            acc = __builtin_fmaf(qv[j], c[j], acc);
+    }
+    if (lf)
+        lf[e] = acc;
+    if (l8) {
+        float y = __builtin_fmaf(a, acc, -offsets[m]);
+        float f = __builtin_floorf(y);
+        f = f > 0.0f ? f : 0.0f;
+        f = f < 255.0f ? f : 255.0f;
+        l8[e] = (uint8_t)f;
+    }
+}
+
+}  // namespace
+
+extern "C" int bolt_build_luts(const float *Qv, int64_t Q, int32_t J, int64_t ldq,
+                               const float *centroids, int32_t M, int32_t metric, float a,
+                               const float *offsets, float *luts_f32, uint8_t *luts_u8,
+                               void *stream)
+{
+    using namespace bolt;
+    BOLT_TRY(check_JM(J, M));
+    BOLT_TRY(check_N(Q, "Q"));
+    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT)
+        return fail(BOLT_ERR_INVALID, "metric must be 0 (L2) or 1 (dot), got %d", metric);
+    if (ldq < J)
+        return fail(BOLT_ERR_INVALID, "ldq (%lld) < J (%d)", (long long)ldq, J);
+    if (luts_u8 && !(a > 0.0f))
+        return fail(BOLT_ERR_INVALID, "scale a must be positive (got %g)", (double)a);
+    if (Q == 0)
+        return BOLT_OK;
+    if (!Qv || !centroids || (luts_u8 && !offsets))
+        return fail(BOLT_ERR_INVALID, "bolt_build_luts: null pointer");
+    const int64_t work = Q * M * kCentroids;
+    hipLaunchKernelGGL(luts_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
+                       as_stream(stream), Qv, Q, ldq, centroids, M, J / M, metric, a, offsets,
+                       luts_f32, luts_u8);
+    return check_launch("bolt_build_luts");
+}

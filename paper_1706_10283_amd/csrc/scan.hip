@@ -1,0 +1,406 @@
+// The scan d_hat for gfx950 (Sec. 3.1: the approximate distance is the sum
+// of the table entries selected by the codes; Sec. 3.2: lookups vectorised
+// over many encoded vectors at once).
+//
+//   out[q][n] = sum over m of lut[q][m][code(n, m)]       (exact integer)
+//
+// Three kernels, chosen by the number of queries:
+//
+// * scan_grouped<MM, NG> (many queries).  The tables of 8*NG queries are
+//   re-laid out in LDS so that one table entry (m, c) holds the 8 queries of
+//   a group as 8 uint16 lanes (16 bytes).  A lane owns one encoded vector:
+//   it computes the LDS byte address (m*16 + c_m)*16 once per subspace and
+//   then, for every group g, one 16-byte LDS read at immediate offset
+//   g*MM*256 returns that vector's entries for 8 queries, already widened to
+//   16 bits.  Two subspaces are folded per add3, so the VALU cost is about a
+//   quarter of an instruction per lookup and the kernel runs at the LDS read
+//   bandwidth (2 bytes per lookup).  A uint16 lane cannot carry into its
+//   neighbour because 255 * M < 65536.
+// * scan_small<MM> (1..7 queries, the HBM-bound case).  Tables stay 16 bytes
+//   each; one ds_read_u8 per lookup, 4 consecutive rows per lane in flight.
+//   All 64 lanes of a wave read the same 16-byte table, i.e. 4 banks, so the
+//   reads are conflict-free.
+// * scan_generic (any even M): the plain per-row loop, used for widths
+//   without a tuned kernel.
+//
+// Output modes: uint16 sums [Q][ldo]; fp32 rescaled sums [Q][ldo] or
+// [N][ldo] for the approximate matrix product (out = (S + bias) * scale).
+#include "common.hpp"
+#include "scan_common.hpp"
+
+namespace {
+
+using bolt::OutMode;
+
+template <OutMode OUT>
+__device__ __forceinline__ void emit(uint32_t s, int64_t q, int64_t n, uint16_t *__restrict__ out,
+                                     float *__restrict__ outf, int64_t ldo, float bias, float scale)
+{
+    if (OUT == OutMode::U16) {
+        out[q * ldo + n] = (uint16_t)s;
+    } else {
+        float t = (float)s + bias;
+        float v = t * scale;
+        if (OUT == OutMode::F32)
+            outf[q * ldo + n] = v;
+        else
+            outf[n * ldo + q] = v;
+    }
+}
+
+// Load the M/2 code bytes of one row into dwords (MM/8 of them).
+template <int MM>
+__device__ __forceinline__ void load_row(const uint8_t *__restrict__ codes, int64_t n, uint32_t *cw)
+{
+    const uint8_t *p = codes + n * (MM / 2);
+    if constexpr (MM / 2 >= 16) {
+#pragma unroll
+        for (int v = 0; v < MM / 32; ++v) {
+            uint4 t = reinterpret_cast<const uint4 *>(p)[v];
+            cw[4 * v + 0] = t.x;
+            cw[4 * v + 1] = t.y;
+            cw[4 * v + 2] = t.z;
+            cw[4 * v + 3] = t.w;
+        }
+    } else if constexpr (MM / 2 == 8) {
+        uint2 t = *reinterpret_cast<const uint2 *>(p);
+        cw[0] = t.x;
+        cw[1] = t.y;
+    } else {
+        static_assert(MM / 2 == 4, "rows of 4, 8 or a multiple of 16 bytes");
+        cw[0] = *reinterpret_cast<const uint32_t *>(p);
+    }
+}
+
+template <int MM>
+__device__ __forceinline__ uint32_t code_at(const uint32_t *cw, int m)
+{
+    return (cw[m >> 3] >> (4 * (m & 7))) & 15u;
+}
+
+// ---------------------------------------------------------------- many queries
+
+template <int MM, int NG, OutMode OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void scan_grouped_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
+    int64_t rows_per_block, uint16_t *__restrict__ out, float *__restrict__ outf, int64_t ldo,
+    float bias, float scale)
+{
+    constexpr int QG = 8;               // queries per group (uint16 lanes of a 16-byte read)
+    constexpr int QB = QG * NG;         // queries per workgroup
+    constexpr int GROUP_BYTES = MM * 16 * QG * 2;
+    static_assert(NG * GROUP_BYTES <= 65536, "immediate LDS offsets are 16 bits");
+    __shared__ uint4 tab[NG * GROUP_BYTES / 16];
+
+    const int64_t q0 = (int64_t)blockIdx.y * QB;
+    const int nq = (int)((Q - q0) < QB ? (Q - q0) : QB);
+    // stage: tab[g][m][c][qq] = lut[q0 + 8g + qq][m][c]  (0 for missing queries)
+    uint16_t *tab16 = reinterpret_cast<uint16_t *>(tab);
+    for (int e = threadIdx.x; e < NG * MM * 16 * QG; e += 256) {
+        const int qq = e & 7, c = (e >> 3) & 15;
+        const int m = (e >> 7) % MM, g = (e >> 7) / MM;
+        const int q = g * QG + qq;
+        tab16[e] = q < nq ? luts[(q0 + q) * MM * 16 + m * 16 + c] : (uint16_t)0;
+    }
+    __syncthreads();
+
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = (r0 + rows_per_block) < N ? (r0 + rows_per_block) : N;
+    const char *tabb = reinterpret_cast<const char *>(tab);
+    constexpr int GU = NG >= 2 ? 2 : 1;   // groups per pass: the second one at an immediate offset
+    constexpr int NW = MM / 8;            // code dwords per row (8 subspaces each)
+    for (int64_t n = r0 + threadIdx.x; n < r1; n += 256) {
+        uint32_t cw[NW];
+        load_row<MM>(codes, n, cw);
+#pragma unroll 1
+        for (int g = 0; g < NG; g += GU) {
+            if (g * QG >= nq)
+                break;
+            const char *tg = tabb + g * GROUP_BYTES;
+            uint32_t acc[GU][4];
+#pragma unroll
+            for (int u = 0; u < GU; ++u)
+                acc[u][0] = acc[u][1] = acc[u][2] = acc[u][3] = 0;
+            // one code dword (8 subspaces) per step keeps 8*GU reads in flight
+#pragma unroll 1
+            for (int t = 0; t < NW; ++t) {
+                uint32_t w = cw[0];
+#pragma unroll
+                for (int v = 1; v < NW; ++v)
+                    w = (t == v) ? cw[v] : w;
+                const char *tt = tg + t * 8 * 256;
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) {
+                    const uint32_t am = (uint32_t)(k * 256) + (((w >> (4 * k)) & 15u) << 4);
+                    const uint32_t am1 = (uint32_t)((k + 1) * 256) + (((w >> (4 * k + 4)) & 15u) << 4);
+#pragma unroll
+                    for (int u = 0; u < GU; ++u) {
+                        const uint4 a = *reinterpret_cast<const uint4 *>(tt + am + u * GROUP_BYTES);
+                        const uint4 b = *reinterpret_cast<const uint4 *>(tt + am1 + u * GROUP_BYTES);
+                        acc[u][0] += a.x + b.x;
+                        acc[u][1] += a.y + b.y;
+                        acc[u][2] += a.z + b.z;
+                        acc[u][3] += a.w + b.w;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < GU; ++u)
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int q = (g + u) * QG + 2 * d + h;
+                        if (q < nq)
+                            emit<OUT>((acc[u][d] >> (16 * h)) & 0xFFFFu, q0 + q, n, out, outf, ldo,
+                                      bias, scale);
+                    }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- few queries
+
+template <int MM, OutMode OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void scan_small_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int nq,
+    int64_t rows_per_block, uint16_t *__restrict__ out, float *__restrict__ outf, int64_t ldo,
+    float bias, float scale)
+{
+    constexpr int R = (128 / MM) < 1 ? 1 : ((128 / MM) > 4 ? 4 : (128 / MM));   // rows per lane in flight
+    __shared__ uint4 tab[bolt::kSmallQ * MM];   // [q][m][16] bytes
+    const uint4 *src = reinterpret_cast<const uint4 *>(luts);
+    for (int e = threadIdx.x; e < nq * MM; e += 256)
+        tab[e] = src[e];
+    __syncthreads();
+    const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
+
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = (r0 + rows_per_block) < N ? (r0 + rows_per_block) : N;
+    for (int64_t nb = r0 + threadIdx.x; nb < r1; nb += 256 * R) {
+        uint32_t cw[R][MM / 8];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t n = nb + 256 * r;
+            if (n < r1)
+                load_row<MM>(codes, n, cw[r]);
+            else
+#pragma unroll
+                for (int v = 0; v < MM / 8; ++v)
+                    cw[r][v] = 0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t n = nb + 256 * r;
+            for (int q = 0; q < nq; ++q) {
+                const uint8_t *tq = tb + q * MM * 16;
+                uint32_t s = 0;
+#pragma unroll
+                for (int m = 0; m < MM; m += 2)
+                    s += (uint32_t)tq[m * 16 + code_at<MM>(cw[r], m)] +
+                         (uint32_t)tq[(m + 1) * 16 + code_at<MM>(cw[r], m + 1)];
+                if (n < r1)
+                    emit<OUT>(s, q, n, out, outf, ldo, bias, scale);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- any even M
+
+template <OutMode OUT>
+__global__ __launch_bounds__(256) void scan_generic_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, int M, const uint8_t *__restrict__ luts,
+    int64_t Q, int qb, int64_t rows_per_block, uint16_t *__restrict__ out,
+    float *__restrict__ outf, int64_t ldo, float bias, float scale)
+{
+    extern __shared__ uint8_t tabg[];   // [qb][M][16]
+    const int64_t q0 = (int64_t)blockIdx.y * qb;
+    const int nq = (int)((Q - q0) < qb ? (Q - q0) : qb);
+    for (int e = threadIdx.x; e < nq * M * 16; e += 256)
+        tabg[e] = luts[q0 * M * 16 + e];
+    __syncthreads();
+    const int bpr = M / 2;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = (r0 + rows_per_block) < N ? (r0 + rows_per_block) : N;
+    for (int64_t n = r0 + threadIdx.x; n < r1; n += 256) {
+        const uint8_t *row = codes + n * bpr;
+        for (int q = 0; q < nq; ++q) {
+            uint32_t s = 0;
+            for (int t = 0; t < bpr; ++t) {
+                const uint32_t byte = row[t];
+                s += tabg[(q * M + 2 * t) * 16 + (byte & 15u)];
+                s += tabg[(q * M + 2 * t + 1) * 16 + (byte >> 4)];
+            }
+            emit<OUT>(s, q0 + q, n, out, outf, ldo, bias, scale);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+int64_t rows_per_block_for(int64_t N, int64_t n_qblocks, int64_t target_blocks)
+{
+    int64_t want = (N * n_qblocks + target_blocks - 1) / target_blocks;
+    want = (want + 255) / 256 * 256;
+    if (want < 256)
+        want = 256;
+    return want;
+}
+
+template <int MM, int NG, OutMode OUT>
+void launch_grouped(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, uint16_t *out,
+                    float *outf, int64_t ldo, float bias, float scale, hipStream_t s)
+{
+    const int64_t qblocks = (Q + 8 * NG - 1) / (8 * NG);
+    const int64_t rpb = rows_per_block_for(N, qblocks, 4096);
+    dim3 grid((unsigned)((N + rpb - 1) / rpb), (unsigned)qblocks);
+    hipLaunchKernelGGL((scan_grouped_kernel<MM, NG, OUT>), grid, dim3(256), 0, s, codes, N, luts, Q,
+                       rpb, out, outf, ldo, bias, scale);
+}
+
+template <int MM, OutMode OUT>
+void launch_small(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, uint16_t *out,
+                  float *outf, int64_t ldo, float bias, float scale, hipStream_t s)
+{
+    const int64_t rpb = rows_per_block_for(N, 1, 2048) < 1024 ? 1024 : rows_per_block_for(N, 1, 2048);
+    dim3 grid((unsigned)((N + rpb - 1) / rpb));
+    hipLaunchKernelGGL((scan_small_kernel<MM, OUT>), grid, dim3(256), 0, s, codes, N, luts, (int)Q,
+                       rpb, out, outf, ldo, bias, scale);
+}
+
+template <OutMode OUT>
+int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q,
+                  uint16_t *out, float *outf, int64_t ldo, float bias, float scale, hipStream_t s,
+                  int force_kernel)
+{
+    // grid.y is at most 65535 query blocks: split very large query counts
+    constexpr int64_t kMaxQ = 65535LL * 8;
+    if (Q > kMaxQ) {
+        for (int64_t q0 = 0; q0 < Q; q0 += kMaxQ) {
+            const int64_t nq = (Q - q0) < kMaxQ ? (Q - q0) : kMaxQ;
+            int st = scan_dispatch<OUT>(codes, N, M, luts + q0 * M * 16, nq,
+                                        OUT == OutMode::U16 ? out + q0 * ldo : out,
+                                        OUT == OutMode::F32 ? outf + q0 * ldo
+                                                            : (OUT == OutMode::F32T ? outf + q0 : outf),
+                                        ldo, bias, scale, s, force_kernel);
+            if (st)
+                return st;
+        }
+        return BOLT_OK;
+    }
+    const bool vec_ok = bolt::aligned(codes, 16) && bolt::aligned(luts, 16);
+    // force_kernel: -1 automatic, 0 generic, 1 small, 2 grouped (tests)
+    int kind = force_kernel;
+    const bool tuned_M = (M == 8 || M == 16 || M == 32 || M == 64 || M == 128 || M == 256);
+    if (kind < 0)
+        kind = (!tuned_M || !vec_ok) ? 0 : (Q < bolt::kSmallQ ? 1 : 2);
+    if ((kind == 1 || kind == 2) && (!tuned_M || !vec_ok))
+        return bolt::fail(BOLT_ERR_UNSUPPORTED, "tuned scan kernels need M in {8..256, power of 2} and 16-byte aligned codes/tables");
+    if (kind == 1 && Q >= bolt::kSmallQ)
+        return bolt::fail(BOLT_ERR_UNSUPPORTED, "small-Q scan handles at most %d queries", bolt::kSmallQ - 1);
+    if (kind == 0) {
+        int qb = 16384 / (M * 16);
+        if (qb < 1)
+            qb = 1;
+        const int64_t qblocks = (Q + qb - 1) / qb;
+        const int64_t rpb = rows_per_block_for(N, qblocks, 4096);
+        dim3 grid((unsigned)((N + rpb - 1) / rpb), (unsigned)qblocks);
+        hipLaunchKernelGGL(scan_generic_kernel<OUT>, grid, dim3(256), qb * M * 16, s, codes, N, M,
+                           luts, Q, qb, rpb, out, outf, ldo, bias, scale);
+    } else if (kind == 1) {
+        switch (M) {
+        case 8: launch_small<8, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 16: launch_small<16, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 32: launch_small<32, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 64: launch_small<64, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 128: launch_small<128, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 256: launch_small<256, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        }
+    } else {
+        switch (M) {
+        case 8: launch_grouped<8, 16, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 16: launch_grouped<16, 8, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 32: launch_grouped<32, 4, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 64: launch_grouped<64, 2, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 128: launch_grouped<128, 1, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 256: launch_grouped<256, 1, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        }
+    }
+    return bolt::check_launch("bolt scan");
+}
+
+int scan_common(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8, int64_t Q,
+                uint16_t *out, int64_t ldo, void *stream)
+{
+    using namespace bolt;
+    BOLT_TRY(check_M(M));
+    BOLT_TRY(check_N(N, "N"));
+    BOLT_TRY(check_N(Q, "Q"));
+    if (ldo < N)
+        return fail(BOLT_ERR_INVALID, "ldo (%lld) < N (%lld)", (long long)ldo, (long long)N);
+    if (N == 0 || Q == 0)
+        return BOLT_OK;
+    if (!codes || !luts_u8 || !out)
+        return fail(BOLT_ERR_INVALID, "bolt_scan: null pointer");
+    return scan_dispatch<OutMode::U16>(codes, N, M, luts_u8, Q, out, nullptr, ldo, 0.f, 0.f,
+                                       as_stream(stream), g_force_scan_kernel);
+}
+
+}  // namespace
+
+namespace bolt {
+int g_force_scan_kernel = -1;
+
+int scan_u16(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, uint16_t *out,
+             int64_t ldo, hipStream_t s)
+{
+    return scan_dispatch<OutMode::U16>(codes, N, M, luts, Q, out, nullptr, ldo, 0.f, 0.f, s,
+                                       g_force_scan_kernel);
+}
+}  // namespace bolt
+
+extern "C" int bolt_scan_l2(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                            int64_t Q, uint16_t *out, int64_t ldo, void *stream)
+{
+    return scan_common(codes, N, M, luts_u8, Q, out, ldo, stream);
+}
+
+extern "C" int bolt_scan_dot(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                             int64_t Q, uint16_t *out, int64_t ldo, void *stream)
+{
+    return scan_common(codes, N, M, luts_u8, Q, out, ldo, stream);
+}
+
+extern "C" int bolt_amm(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                        int64_t K, float bias, float scale, float *out, int64_t ldo,
+                        int32_t transpose, void *stream)
+{
+    using namespace bolt;
+    BOLT_TRY(check_M(M));
+    BOLT_TRY(check_N(N, "N"));
+    BOLT_TRY(check_N(K, "K"));
+    if (transpose != 0 && transpose != 1)
+        return fail(BOLT_ERR_INVALID, "transpose must be 0 or 1");
+    if ((transpose == 0 && ldo < N) || (transpose == 1 && ldo < K))
+        return fail(BOLT_ERR_INVALID, "ldo too small (%lld)", (long long)ldo);
+    if (N == 0 || K == 0)
+        return BOLT_OK;
+    if (!codes || !luts_u8 || !out)
+        return fail(BOLT_ERR_INVALID, "bolt_amm: null pointer");
+    hipStream_t s = as_stream(stream);
+    if (transpose)
+        return scan_dispatch<OutMode::F32T>(codes, N, M, luts_u8, K, nullptr, out, ldo, bias, scale,
+                                            s, g_force_scan_kernel);
+    return scan_dispatch<OutMode::F32>(codes, N, M, luts_u8, K, nullptr, out, ldo, bias, scale, s,
+                                       g_force_scan_kernel);
+}
+
+// Test hook: pin the scan kernel choice (-1 automatic, 0 generic, 1 few-query, 2 grouped).
+extern "C" int bolt_debug_force_scan_kernel(int32_t kind)
+{
+    if (kind < -1 || kind > 2)
+        return bolt::fail(BOLT_ERR_INVALID, "kind must be -1..2");
+    bolt::g_force_scan_kernel = kind;
+    return BOLT_OK;
+}

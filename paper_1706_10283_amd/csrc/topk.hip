@@ -1,0 +1,295 @@
+// Top-k retrieval over uint16 sums for gfx950 (Sec. 1.2: the k closest
+// vectors; Sec. 4.5: ranking by the smallest approximate distance; the dot
+// product ranks by the largest, i.e. maximum inner product search).
+//
+// The answer is made unique by ordering on the key (value, index): among
+// equal values the lower index comes first.  Because the values are 16-bit
+// integers the k-th smallest value T is found exactly by a two-level radix
+// select (a 256-bin histogram of the high byte, then of the low byte inside
+// the selected bucket).  Every value below T is taken; of the values equal
+// to T, the ones with the lowest indices are taken, in index order, by a
+// block-wide prefix sum over contiguous per-thread runs.  The k survivors are
+// sorted by key with a bitonic network in LDS.  One workgroup per row.
+// For the largest-k direction every value v is replaced by 65535 - v.
+#include "common.hpp"
+#include "scan_common.hpp"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kE = 8;   // contiguous values per thread per chunk (one 16-byte load)
+
+__device__ __forceinline__ void load8(const uint16_t *__restrict__ row, int64_t i0, int64_t N,
+                                      int vec, uint32_t *v)
+{
+    if (vec && i0 + kE <= N) {
+        uint4 t = *reinterpret_cast<const uint4 *>(row + i0);
+        v[0] = t.x & 0xFFFFu; v[1] = t.x >> 16;
+        v[2] = t.y & 0xFFFFu; v[3] = t.y >> 16;
+        v[4] = t.z & 0xFFFFu; v[5] = t.z >> 16;
+        v[6] = t.w & 0xFFFFu; v[7] = t.w >> 16;
+    } else {
+#pragma unroll
+        for (int e = 0; e < kE; ++e)
+            v[e] = (i0 + e < N) ? (uint32_t)row[i0 + e] : 0xFFFFFFFFu;   // 0xFFFFFFFF = absent
+    }
+}
+
+// Exclusive prefix sum over the 256 threads; returns the total in *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *wave_sums,
+                                                         uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off)
+            incl += y;
+    }
+    if (lane == 63)
+        wave_sums[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        uint32_t s = wave_sums[w];
+        before += (w < wave) ? s : 0;
+        all += s;
+    }
+    *total = all;
+    return before + incl - x;
+}
+
+__global__ __launch_bounds__(kThreads) void topk_rows_kernel(
+    const uint16_t *__restrict__ d, int64_t N, int64_t ldd, int k, uint32_t flip,
+    uint16_t *__restrict__ vals, int32_t *__restrict__ idx, int vec)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t sel[BOLT_TOPK_MAX_K];
+    __shared__ uint32_t wave_sums[kThreads / 64];
+    __shared__ uint32_t sh_T, sh_lt, sh_nlt;
+    const int tid = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const uint16_t *row = d + q * ldd;
+    const int kk = ((int64_t)k < N) ? k : (int)N;
+
+    uint32_t T, count_lt, need_eq;
+    if ((int64_t)kk == N) {
+        T = 0x10000u;          // every value is below: take all N
+        count_lt = (uint32_t)N;
+        need_eq = 0;
+    } else {
+        // level 1: high byte
+        hist[tid] = 0;
+        __syncthreads();
+        for (int64_t i0 = (int64_t)tid * kE; i0 < N; i0 += (int64_t)kThreads * kE) {
+            uint32_t v[kE];
+            load8(row, i0, N, vec, v);
+#pragma unroll
+            for (int e = 0; e < kE; ++e)
+                if (v[e] != 0xFFFFFFFFu)
+                    atomicAdd(&hist[(v[e] ^ flip) >> 8], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t cum = 0;
+            int B = 0;
+            for (; B < 255; ++B) {
+                if (cum + hist[B] >= (uint32_t)k)
+                    break;
+                cum += hist[B];
+            }
+            sh_T = (uint32_t)B;
+            sh_lt = cum;
+        }
+        __syncthreads();
+        const uint32_t B = sh_T, lt_B = sh_lt;
+        hist[tid] = 0;
+        __syncthreads();
+        // level 2: low byte inside bucket B
+        for (int64_t i0 = (int64_t)tid * kE; i0 < N; i0 += (int64_t)kThreads * kE) {
+            uint32_t v[kE];
+            load8(row, i0, N, vec, v);
+#pragma unroll
+            for (int e = 0; e < kE; ++e)
+                if (v[e] != 0xFFFFFFFFu && ((v[e] ^ flip) >> 8) == B)
+                    atomicAdd(&hist[(v[e] ^ flip) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t cum = lt_B;
+            int L = 0;
+            for (; L < 255; ++L) {
+                if (cum + hist[L] >= (uint32_t)k)
+                    break;
+                cum += hist[L];
+            }
+            sh_T = (B << 8) | (uint32_t)L;
+            sh_lt = cum;
+        }
+        __syncthreads();
+        T = sh_T;
+        count_lt = sh_lt;
+        need_eq = (uint32_t)k - count_lt;
+    }
+
+    // collect: all values < T, and the first need_eq values == T in index order
+    if (tid == 0)
+        sh_nlt = 0;
+    __syncthreads();
+    uint32_t eq_base = 0;
+    for (int64_t c0 = 0; c0 < N; c0 += (int64_t)kThreads * kE) {
+        const int64_t i0 = c0 + (int64_t)tid * kE;
+        uint32_t v[kE];
+        load8(row, i0, N, vec, v);
+        uint32_t my_eq = 0;
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            if (v[e] == 0xFFFFFFFFu)
+                continue;
+            const uint32_t w = v[e] ^ flip;
+            if (w < T) {
+                uint32_t pos = atomicAdd(&sh_nlt, 1u);
+                sel[pos] = ((uint64_t)w << 32) | (uint64_t)(i0 + e);
+            } else if (w == T) {
+                ++my_eq;
+            }
+        }
+        uint32_t total;
+        uint32_t r = eq_base + block_exclusive_scan(my_eq, wave_sums, &total);
+        if (my_eq) {
+#pragma unroll
+            for (int e = 0; e < kE; ++e) {
+                if (v[e] != 0xFFFFFFFFu && (v[e] ^ flip) == T) {
+                    if (r < need_eq)
+                        sel[count_lt + r] = ((uint64_t)T << 32) | (uint64_t)(i0 + e);
+                    ++r;
+                }
+            }
+        }
+        eq_base += total;
+        __syncthreads();
+        if (eq_base >= need_eq && sh_nlt == count_lt)
+            break;
+    }
+    __syncthreads();
+
+    // bitonic sort of sel[0 .. P), P = next power of two >= kk
+    int P = 1;
+    while (P < kk)
+        P <<= 1;
+    for (int i = kk + tid; i < P; i += kThreads)
+        sel[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < P / 2; t += kThreads) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool asc = (i & size) == 0;
+                const uint64_t a = sel[i], b = sel[j];
+                if ((a > b) == asc) {
+                    sel[i] = b;
+                    sel[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = tid; r < k; r += kThreads) {
+        if (r < kk) {
+            vals[q * k + r] = (uint16_t)((uint32_t)(sel[r] >> 32) ^ flip);
+            idx[q * k + r] = (int32_t)(sel[r] & 0xFFFFFFFFu);
+        } else {
+            vals[q * k + r] = (uint16_t)(flip ? 0u : 0xFFFFu);
+            idx[q * k + r] = -1;
+        }
+    }
+}
+
+int validate_topk(int64_t Q, int64_t N, int32_t k)
+{
+    using namespace bolt;
+    BOLT_TRY(check_N(Q, "Q"));
+    BOLT_TRY(check_N(N, "N"));
+    if (k < 1)
+        return fail(BOLT_ERR_INVALID, "k must be >= 1 (got %d)", k);
+    if (k > BOLT_TOPK_MAX_K)
+        return fail(BOLT_ERR_UNSUPPORTED, "k must be <= %d (got %d)", BOLT_TOPK_MAX_K, k);
+    return BOLT_OK;
+}
+
+}  // namespace
+
+namespace bolt {
+int topk_u16(const uint16_t *d, int64_t Q, int64_t N, int64_t ldd, int k, int largest,
+             uint16_t *vals, int32_t *idx, hipStream_t s)
+{
+    const int vec = aligned(d, 16) && (ldd % 8 == 0);
+    hipLaunchKernelGGL(topk_rows_kernel, dim3((unsigned)Q), dim3(kThreads), 0, s, d, N, ldd, k,
+                       largest ? 0xFFFFu : 0u, vals, idx, vec);
+    return check_launch("bolt_topk");
+}
+}  // namespace bolt
+
+extern "C" size_t bolt_topk_ws_bytes(int64_t Q, int64_t N, int32_t k)
+{
+    (void)Q;
+    (void)N;
+    (void)k;
+    return 0;
+}
+
+extern "C" int bolt_topk(const uint16_t *dists, int64_t Q, int64_t N, int64_t ldd, int32_t k,
+                         int32_t largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
+                         void *stream)
+{
+    using namespace bolt;
+    (void)ws;
+    (void)ws_bytes;
+    BOLT_TRY(validate_topk(Q, N, k));
+    if (ldd < N)
+        return fail(BOLT_ERR_INVALID, "ldd (%lld) < N (%lld)", (long long)ldd, (long long)N);
+    if (Q == 0)
+        return BOLT_OK;
+    if (!vals || !idx || (N > 0 && !dists))
+        return fail(BOLT_ERR_INVALID, "bolt_topk: null pointer");
+    return topk_u16(dists, Q, N, ldd, k, largest != 0, vals, idx, as_stream(stream));
+}
+
+static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+extern "C" size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k)
+{
+    (void)M;
+    (void)k;
+    if (N <= 0 || Q <= 0)
+        return 0;
+    return round_up((size_t)Q * (size_t)N * sizeof(uint16_t), 256);
+}
+
+extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                              int64_t Q, int32_t metric, int32_t k, uint16_t *vals, int32_t *idx,
+                              void *ws, size_t ws_bytes, void *stream)
+{
+    using namespace bolt;
+    BOLT_TRY(check_M(M));
+    BOLT_TRY(validate_topk(Q, N, k));
+    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT)
+        return fail(BOLT_ERR_INVALID, "metric must be 0 or 1 (got %d)", metric);
+    if (Q == 0)
+        return BOLT_OK;
+    if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
+        return fail(BOLT_ERR_INVALID, "bolt_scan_topk: null pointer");
+    const size_t need = bolt_scan_topk_ws_bytes(N, M, Q, k);
+    if (ws_bytes < need || (need && !ws))
+        return fail(BOLT_ERR_NOMEM, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+    if (need && !aligned(ws, 16))
+        return fail(BOLT_ERR_INVALID, "workspace must be 16-byte aligned");
+    hipStream_t s = as_stream(stream);
+    uint16_t *d = reinterpret_cast<uint16_t *>(ws);
+    if (N > 0)
+        BOLT_TRY(scan_u16(codes, N, M, luts_u8, Q, d, N, s));
+    return topk_u16(d, Q, N, N, k, metric == BOLT_METRIC_DOT, vals, idx, s);
+}

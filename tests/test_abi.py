@@ -1,0 +1,67 @@
+"""The C-ABI library loads on the host and exports every symbol include/bolt.h
+declares; argument validation runs on the host without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bolt_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1706_10283_amd.bolt as b
+    return b
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared("bolt.h")
+    assert "bolt_encode" in names and "bolt_scan_topk" in names
+    for n in names:
+        assert hasattr(lib.lib(), n), n
+
+
+def test_validation_without_gpu(lib):
+    L = lib.lib()
+    # J % M != 0, odd M, M > 256: shape errors before any device work
+    assert L.bolt_encode(None, 10, 30, 30, None, 4, None, None) == lib.BOLT_ERR_SHAPE
+    assert L.bolt_encode(None, 10, 30, 30, None, 3, None, None) == lib.BOLT_ERR_SHAPE
+    assert L.bolt_scan_l2(None, 10, 258, None, 1, None, 10, None) == lib.BOLT_ERR_SHAPE
+    # empty work is a no-op
+    assert L.bolt_encode(None, 0, 32, 32, None, 8, None, None) == lib.BOLT_OK
+    assert L.bolt_scan_l2(None, 0, 8, None, 5, None, 0, None) == lib.BOLT_OK
+    # null pointers with work, bad k, bad ld
+    assert L.bolt_encode(None, 10, 32, 32, None, 8, None, None) == lib.BOLT_ERR_INVALID
+    assert L.bolt_topk(None, 1, 10, 10, 0, 0, None, None, None, 0, None) == lib.BOLT_ERR_INVALID
+    assert L.bolt_topk(None, 1, 10, 10, 4096, 0, None, None, None, 0, None) == lib.BOLT_ERR_UNSUPPORTED
+    assert L.bolt_scan_l2(None, 10, 8, None, 1, None, 5, None) == lib.BOLT_ERR_INVALID
+    assert "ldo" in lib.last_error()
+    assert lib.bolt_scan_topk_ws_bytes(1000, 32, 10, 100) >= 1000 * 10 * 2
+
+
+def test_train_host_matches_oracle_definition(lib):
+    """Host trainer of the library vs the oracle's (same definition, written
+    independently).  Training is parity-unpinned; this only guards against the
+    two drifting apart."""
+    J, M = 32, 8
+    X = synth.normal(201, (3000, J))
+    init = synth.permutation_prefix(202, 3000, 16)
+    Qt = X[synth.permutation_prefix(203, 3000, 300)]
+    for metric in ("l2", "dot"):
+        C, a, offs, ai = lib.bolt_train_host(X, M, 6, init, Qt, metric)
+        Co, ao, offso, aio = oracle.train(X, M, 6, init, Qt, metric)
+        np.testing.assert_allclose(C, Co, rtol=1e-5, atol=1e-6)
+        assert ai == aio
+        assert a == pytest.approx(ao, rel=1e-5)
+        np.testing.assert_allclose(offs, offso, rtol=1e-4, atol=1e-3)
