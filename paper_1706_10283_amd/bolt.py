@@ -65,6 +65,7 @@ _SIGS = {
     "bolt_learn_quantizer_host": ([_P, _I64, _I32, _I64, _P, _I64, _P, _I32, _I32, _P, _I32,
                                    _P, _P, _P], ctypes.c_int),
     "bolt_debug_force_scan_kernel": ([_I32], ctypes.c_int),
+    "bolt_debug_force_unfused_topk": ([_I32], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -279,6 +280,11 @@ def bolt_learn_quantizer_host(Qt, codes, centroids, metric, alphas=ALPHAS):
                                           _np_ptr(alphas), len(alphas), _np_ptr(a), _np_ptr(offs),
                                           _np_ptr(ai)))
     return float(a[0]), offs, int(ai[0])
+
+
+def debug_force_unfused_topk(on: bool):
+    """Test hook: route bolt_scan_topk through scan + bolt_topk."""
+    _check(_lib.bolt_debug_force_unfused_topk(1 if on else 0))
 
 
 def debug_force_scan_kernel(kind: int):

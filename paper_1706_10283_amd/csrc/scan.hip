@@ -31,6 +31,8 @@
 namespace {
 
 using bolt::OutMode;
+using bolt::load_row;
+using bolt::code_at;
 
 template <OutMode OUT>
 __device__ __forceinline__ void emit(uint32_t s, int64_t q, int64_t n, uint16_t *__restrict__ out,
@@ -46,36 +48,6 @@ __device__ __forceinline__ void emit(uint32_t s, int64_t q, int64_t n, uint16_t 
         else
             outf[n * ldo + q] = v;
     }
-}
-
-// Load the M/2 code bytes of one row into dwords (MM/8 of them).
-template <int MM>
-__device__ __forceinline__ void load_row(const uint8_t *__restrict__ codes, int64_t n, uint32_t *cw)
-{
-    const uint8_t *p = codes + n * (MM / 2);
-    if constexpr (MM / 2 >= 16) {
-#pragma unroll
-        for (int v = 0; v < MM / 32; ++v) {
-            uint4 t = reinterpret_cast<const uint4 *>(p)[v];
-            cw[4 * v + 0] = t.x;
-            cw[4 * v + 1] = t.y;
-            cw[4 * v + 2] = t.z;
-            cw[4 * v + 3] = t.w;
-        }
-    } else if constexpr (MM / 2 == 8) {
-        uint2 t = *reinterpret_cast<const uint2 *>(p);
-        cw[0] = t.x;
-        cw[1] = t.y;
-    } else {
-        static_assert(MM / 2 == 4, "rows of 4, 8 or a multiple of 16 bytes");
-        cw[0] = *reinterpret_cast<const uint32_t *>(p);
-    }
-}
-
-template <int MM>
-__device__ __forceinline__ uint32_t code_at(const uint32_t *cw, int m)
-{
-    return (cw[m >> 3] >> (4 * (m & 7))) & 15u;
 }
 
 // ---------------------------------------------------------------- many queries

@@ -17,8 +17,49 @@ extern int g_force_scan_kernel;
 int scan_u16(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, uint16_t *out,
              int64_t ldo, hipStream_t s);
 
+// Fused scan + top-k (fused.hip): workspace size (0 if the shape has no fused
+// kernel) and the launch (BOLT_ERR_UNSUPPORTED if it has none).
+size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k);
+int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
+                    bool largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
+                    hipStream_t s);
+
+// Test hook: 1 forces the unfused scan-then-select path of bolt_scan_topk.
+extern int g_force_unfused_topk;
+
 // Top-k of the rows of a uint16 matrix (arguments already validated).
 int topk_u16(const uint16_t *d, int64_t Q, int64_t N, int64_t ldd, int k, int largest,
              uint16_t *vals, int32_t *idx, hipStream_t s);
+
+// Load the M/2 code bytes of row n into dwords (MM/8 of them).
+template <int MM>
+__device__ __forceinline__ void load_row(const uint8_t *__restrict__ codes, int64_t n, uint32_t *cw)
+{
+    const uint8_t *p = codes + n * (MM / 2);
+    if constexpr (MM / 2 >= 16) {
+#pragma unroll
+        for (int v = 0; v < MM / 32; ++v) {
+            uint4 t = reinterpret_cast<const uint4 *>(p)[v];
+            cw[4 * v + 0] = t.x;
+            cw[4 * v + 1] = t.y;
+            cw[4 * v + 2] = t.z;
+            cw[4 * v + 3] = t.w;
+        }
+    } else if constexpr (MM / 2 == 8) {
+        uint2 t = *reinterpret_cast<const uint2 *>(p);
+        cw[0] = t.x;
+        cw[1] = t.y;
+    } else {
+        static_assert(MM / 2 == 4, "rows of 4, 8 or a multiple of 16 bytes");
+        cw[0] = *reinterpret_cast<const uint32_t *>(p);
+    }
+}
+
+// Code of subspace m from the row's dwords (low nibble = even subspace).
+template <int MM>
+__device__ __forceinline__ uint32_t code_at(const uint32_t *cw, int m)
+{
+    return (cw[m >> 3] >> (4 * (m & 7))) & 15u;
+}
 
 }  // namespace bolt

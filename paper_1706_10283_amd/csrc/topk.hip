@@ -260,13 +260,22 @@ extern "C" int bolt_topk(const uint16_t *dists, int64_t Q, int64_t N, int64_t ld
 
 static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-extern "C" size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k)
+namespace bolt {
+int g_force_unfused_topk = 0;
+}
+
+static size_t unfused_ws_bytes(int64_t N, int64_t Q)
 {
-    (void)M;
-    (void)k;
     if (N <= 0 || Q <= 0)
         return 0;
     return round_up((size_t)Q * (size_t)N * sizeof(uint16_t), 256);
+}
+
+extern "C" size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k)
+{
+    const size_t f = bolt::fused_ws_bytes(N, M, Q, k);
+    const size_t u = unfused_ws_bytes(N, Q);
+    return f > u ? f : u;
 }
 
 extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
@@ -285,11 +294,24 @@ extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const 
     const size_t need = bolt_scan_topk_ws_bytes(N, M, Q, k);
     if (ws_bytes < need || (need && !ws))
         return fail(BOLT_ERR_NOMEM, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
-    if (need && !aligned(ws, 16))
-        return fail(BOLT_ERR_INVALID, "workspace must be 16-byte aligned");
+    if (need && !aligned(ws, 256))
+        return fail(BOLT_ERR_INVALID, "workspace must be 256-byte aligned");
     hipStream_t s = as_stream(stream);
+    const bool largest = metric == BOLT_METRIC_DOT;
+    if (N > 0 && !g_force_unfused_topk) {
+        const int st = scan_topk_fused(codes, N, M, luts_u8, Q, k, largest, vals, idx, ws, ws_bytes, s);
+        if (st != BOLT_ERR_UNSUPPORTED)
+            return st;
+    }
     uint16_t *d = reinterpret_cast<uint16_t *>(ws);
     if (N > 0)
         BOLT_TRY(scan_u16(codes, N, M, luts_u8, Q, d, N, s));
-    return topk_u16(d, Q, N, N, k, metric == BOLT_METRIC_DOT, vals, idx, s);
+    return topk_u16(d, Q, N, N, k, largest, vals, idx, s);
+}
+
+// Test hook: 1 forces bolt_scan_topk onto the scan-then-select path.
+extern "C" int bolt_debug_force_unfused_topk(int32_t on)
+{
+    bolt::g_force_unfused_topk = on ? 1 : 0;
+    return BOLT_OK;
 }

@@ -293,3 +293,58 @@ def test_errors_are_reported(bolt):
     with pytest.raises(bolt.BoltError) as e:
         bolt.bolt_topk(d, 4096)
     assert e.value.status == bolt.BOLT_ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ fused scan + top-k
+
+FUSED_CASES = [
+    # (M, Q, N, k, lut kind)
+    (32, 1, 1, 1, "rand"), (32, 1, 300, 100, "rand"), (32, 3, 16384, 100, "rand"),
+    (32, 7, 16385, 100, "coarse"), (16, 5, 70000, 256, "rand"), (8, 2, 40000, 10, "coarse"),
+    (64, 4, 50001, 100, "rand"), (32, 1, 70000, 100, "const"), (32, 8, 33000, 100, "rand"),
+    (32, 17, 50000, 100, "coarse"), (32, 40, 20000, 10, "rand"), (16, 16, 70000, 256, "rand"),
+    (8, 33, 17000, 64, "coarse"), (64, 9, 40000, 100, "rand"), (64, 12, 30000, 100, "const"),
+    (32, 64, 16384 * 3 + 5, 100, "rand"), (32, 20, 5, 100, "rand"), (16, 100, 4000, 1, "coarse"),
+]
+
+
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("M,Q,N,k,kind", FUSED_CASES)
+def test_scan_topk_fused_parity(bolt, metric, M, Q, N, k, kind):
+    """The fused path (scan + in-LDS candidate selection + merge) gives exactly
+    the oracle's top-k, including heavy and total ties (coarse / constant
+    tables) and ragged row blocks."""
+    seed = 17 * M + 31 * Q + N + k
+    _say("fused scan_topk", metric, kind, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    elif kind == "const":
+        luts = np.full_like(luts, 3)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    v, i = bolt.bolt_scan_topk(cd, ld, metric, k)
+    bolt.debug_force_unfused_topk(True)
+    try:
+        vu, iu = bolt.bolt_scan_topk(cd, ld, metric, k)
+    finally:
+        bolt.debug_force_unfused_topk(False)
+    torch.cuda.synchronize()
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
+    assert np.array_equal(vu.cpu().numpy(), vr)
+    assert np.array_equal(iu.cpu().numpy(), ir)
+
+
+def test_scan_topk_fused_repeatable(bolt):
+    """Cross-workgroup bounds depend on timing; the answer must not."""
+    M, Q, N, k = 32, 24, 200_000, 100
+    codes = synth.random_codes(77, N, M)
+    luts = (synth.random_luts(78, Q, M) // 8).astype(np.uint8)
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    outs = [bolt.bolt_scan_topk(cd, ld, "l2", k) for _ in range(5)]
+    torch.cuda.synchronize()
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, False)
+    for v, i in outs:
+        assert np.array_equal(v.cpu().numpy(), vr) and np.array_equal(i.cpu().numpy(), ir)
