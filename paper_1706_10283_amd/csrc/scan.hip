@@ -16,10 +16,8 @@
 //   quarter of an instruction per lookup and the kernel runs at the LDS read
 //   bandwidth (2 bytes per lookup).  A uint16 lane cannot carry into its
 //   neighbour because 255 * M < 65536.
-// * scan_small<MM> (1..7 queries, the HBM-bound case).  Tables stay 16 bytes
-//   each; one ds_read_u8 per lookup, 4 consecutive rows per lane in flight.
-//   All 64 lanes of a wave read the same 16-byte table, i.e. 4 banks, so the
-//   reads are conflict-free.
+// * few.hip (1..7 queries, the HBM-bound case): pair tables, one 16-bit LDS
+//   read per code byte.
 // * scan_generic (any even M): the plain per-row loop, used for widths
 //   without a tuned kernel.
 //
@@ -131,53 +129,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
     }
 }
 
-// ---------------------------------------------------------------- few queries
-
-template <int MM, OutMode OUT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void scan_small_kernel(
-    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int nq,
-    int64_t rows_per_block, uint16_t *__restrict__ out, float *__restrict__ outf, int64_t ldo,
-    float bias, float scale)
-{
-    constexpr int R = (128 / MM) < 1 ? 1 : ((128 / MM) > 4 ? 4 : (128 / MM));   // rows per lane in flight
-    __shared__ uint4 tab[bolt::kSmallQ * MM];   // [q][m][16] bytes
-    const uint4 *src = reinterpret_cast<const uint4 *>(luts);
-    for (int e = threadIdx.x; e < nq * MM; e += 256)
-        tab[e] = src[e];
-    __syncthreads();
-    const uint8_t *tb = reinterpret_cast<const uint8_t *>(tab);
-
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = (r0 + rows_per_block) < N ? (r0 + rows_per_block) : N;
-    for (int64_t nb = r0 + threadIdx.x; nb < r1; nb += 256 * R) {
-        uint32_t cw[R][MM / 8];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t n = nb + 256 * r;
-            if (n < r1)
-                load_row<MM>(codes, n, cw[r]);
-            else
-#pragma unroll
-                for (int v = 0; v < MM / 8; ++v)
-                    cw[r][v] = 0;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t n = nb + 256 * r;
-            for (int q = 0; q < nq; ++q) {
-                const uint8_t *tq = tb + q * MM * 16;
-                uint32_t s = 0;
-#pragma unroll
-                for (int m = 0; m < MM; m += 2)
-                    s += (uint32_t)tq[m * 16 + code_at<MM>(cw[r], m)] +
-                         (uint32_t)tq[(m + 1) * 16 + code_at<MM>(cw[r], m + 1)];
-                if (n < r1)
-                    emit<OUT>(s, q, n, out, outf, ldo, bias, scale);
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------- any even M
 
 template <OutMode OUT>
@@ -231,16 +182,6 @@ void launch_grouped(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_
                        rpb, out, outf, ldo, bias, scale);
 }
 
-template <int MM, OutMode OUT>
-void launch_small(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, uint16_t *out,
-                  float *outf, int64_t ldo, float bias, float scale, hipStream_t s)
-{
-    const int64_t rpb = rows_per_block_for(N, 1, 2048) < 1024 ? 1024 : rows_per_block_for(N, 1, 2048);
-    dim3 grid((unsigned)((N + rpb - 1) / rpb));
-    hipLaunchKernelGGL((scan_small_kernel<MM, OUT>), grid, dim3(256), 0, s, codes, N, luts, (int)Q,
-                       rpb, out, outf, ldo, bias, scale);
-}
-
 template <OutMode OUT>
 int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q,
                   uint16_t *out, float *outf, int64_t ldo, float bias, float scale, hipStream_t s,
@@ -265,10 +206,11 @@ int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, i
     // force_kernel: -1 automatic, 0 generic, 1 small, 2 grouped (tests)
     int kind = force_kernel;
     const bool tuned_M = (M == 8 || M == 16 || M == 32 || M == 64 || M == 128 || M == 256);
+    const bool few_M = (M == 8 || M == 16 || M == 32 || M == 64);
     if (kind < 0)
-        kind = (!tuned_M || !vec_ok) ? 0 : (Q < bolt::kSmallQ ? 1 : 2);
-    if ((kind == 1 || kind == 2) && (!tuned_M || !vec_ok))
-        return bolt::fail(BOLT_ERR_UNSUPPORTED, "tuned scan kernels need M in {8..256, power of 2} and 16-byte aligned codes/tables");
+        kind = (!tuned_M || !vec_ok) ? 0 : (Q < bolt::kSmallQ ? (few_M ? 1 : 2) : 2);
+    if ((kind == 1 && (!few_M || !vec_ok)) || (kind == 2 && (!tuned_M || !vec_ok)))
+        return bolt::fail(BOLT_ERR_UNSUPPORTED, "tuned scan kernels need a power-of-two M (8..64 for few queries, 8..256 otherwise) and 16-byte aligned codes/tables");
     if (kind == 1 && Q >= bolt::kSmallQ)
         return bolt::fail(BOLT_ERR_UNSUPPORTED, "small-Q scan handles at most %d queries", bolt::kSmallQ - 1);
     if (kind == 0) {
@@ -281,14 +223,7 @@ int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, i
         hipLaunchKernelGGL(scan_generic_kernel<OUT>, grid, dim3(256), qb * M * 16, s, codes, N, M,
                            luts, Q, qb, rpb, out, outf, ldo, bias, scale);
     } else if (kind == 1) {
-        switch (M) {
-        case 8: launch_small<8, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
-        case 16: launch_small<16, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
-        case 32: launch_small<32, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
-        case 64: launch_small<64, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
-        case 128: launch_small<128, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
-        case 256: launch_small<256, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
-        }
+        return bolt::few_scan<OUT>(codes, N, M, luts, Q, out, outf, ldo, bias, scale, s);
     } else {
         switch (M) {
         case 8: launch_grouped<8, 16, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;

@@ -45,9 +45,77 @@ struct PruneResult {
 // to the lowest rows so that exactly k keys remain.  The caller stores the
 // returned count and lowers its bound to T.  Wave-uniform result.
 template <int CAP>
+__device__ PruneResult prune_local_lds(uint32_t *keys, uint32_t n, uint32_t k, bool exact)
+{
+    // Keys stay in LDS and are re-read at every descent step: for kernels
+    // whose scan loop is register-bound, holding CAP/64 keys per lane in
+    // registers would cost occupancy.
+    constexpr int PER = (CAP + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    if (n <= k)
+        return {0x10000u, n};
+    auto d_at = [&](int j) -> uint32_t {
+        const uint32_t slot = (uint32_t)(lane + 64 * j);
+        return slot < n ? (keys[slot] >> 16) : 0x10000u;   // 0x10000: never below a 16-bit trial
+    };
+    // T = largest t with #(d < t) < k, i.e. the k-th smallest d
+    uint32_t T = 0;
+    for (int b = 15; b >= 0; --b) {
+        const uint32_t t = T | (1u << b);
+        uint32_t c = 0;
+#pragma unroll 4
+        for (int j = 0; j < PER; ++j)
+            c += ballot_count(d_at(j) < t);
+        if (c < k)
+            T = t;
+    }
+    uint32_t keep_row_max = 0xFFFFu;   // among ties at T, rows <= this are kept
+    if (exact) {
+        uint32_t lt = 0;
+#pragma unroll 4
+        for (int j = 0; j < PER; ++j)
+            lt += ballot_count(d_at(j) < T);
+        const uint32_t need = k - lt;   // >= 1
+        uint32_t R = 0;                  // the need-th smallest row among ties at T
+        for (int b = 15; b >= 0; --b) {
+            const uint32_t t = R | (1u << b);
+            uint32_t c = 0;
+#pragma unroll 4
+            for (int j = 0; j < PER; ++j) {
+                const uint32_t slot = (uint32_t)(lane + 64 * j);
+                const uint32_t key = slot < n ? keys[slot] : 0xFFFFFFFFu;
+                c += ballot_count(slot < n && (key >> 16) == T && (key & 0xFFFFu) < t);
+            }
+            if (c < need)
+                R = t;
+        }
+        keep_row_max = R;
+    }
+    // compaction: slots are read before being overwritten because the
+    // destination index never exceeds the source index
+    uint32_t base = 0;
+#pragma unroll 1
+    for (int j = 0; j < PER; ++j) {
+        const uint32_t slot = (uint32_t)(lane + 64 * j);
+        const uint32_t key = slot < n ? keys[slot] : 0xFFFFFFFFu;
+        const uint32_t d = slot < n ? (key >> 16) : 0x10000u;
+        const bool keep = d < T || (d == T && (key & 0xFFFFu) <= keep_row_max);
+        const uint32_t r = ballot_rank(keep);
+        const uint32_t total = ballot_count(keep);
+        __builtin_amdgcn_wave_barrier();
+        if (keep)
+            keys[base + r] = key;
+        base += total;
+    }
+    return {T, base};
+}
+
+// The same prune with the keys held in registers (CAP/64 per lane): faster,
+// for kernels that can afford the registers.
+template <int CAP>
 __device__ PruneResult prune_local(uint32_t *keys, uint32_t n, uint32_t k, bool exact)
 {
-    constexpr int PER = CAP / 64;
+    constexpr int PER = (CAP + 63) / 64;
     const int lane = threadIdx.x & 63;
     if (n <= k)
         return {0x10000u, n};
@@ -57,9 +125,8 @@ __device__ PruneResult prune_local(uint32_t *keys, uint32_t n, uint32_t k, bool 
     for (int j = 0; j < PER; ++j) {
         const uint32_t slot = (uint32_t)(lane + 64 * j);
         key[j] = slot < n ? keys[slot] : 0xFFFFFFFFu;
-        d[j] = slot < n ? (key[j] >> 16) : 0x10000u;   // 0x10000: never below a 16-bit trial
+        d[j] = slot < n ? (key[j] >> 16) : 0x10000u;
     }
-    // T = largest t with #(d < t) < k, i.e. the k-th smallest d
     uint32_t T = 0;
     for (int b = 15; b >= 0; --b) {
         const uint32_t t = T | (1u << b);
@@ -70,14 +137,14 @@ __device__ PruneResult prune_local(uint32_t *keys, uint32_t n, uint32_t k, bool 
         if (c < k)
             T = t;
     }
-    uint32_t keep_row_max = 0xFFFFu;   // among ties at T, rows <= this are kept
+    uint32_t keep_row_max = 0xFFFFu;
     if (exact) {
         uint32_t lt = 0;
 #pragma unroll
         for (int j = 0; j < PER; ++j)
             lt += ballot_count(d[j] < T);
-        const uint32_t need = k - lt;   // >= 1
-        uint32_t R = 0;                  // the need-th smallest row among ties at T
+        const uint32_t need = k - lt;
+        uint32_t R = 0;
         for (int b = 15; b >= 0; --b) {
             const uint32_t t = R | (1u << b);
             uint32_t c = 0;
@@ -107,7 +174,7 @@ __device__ PruneResult prune_local(uint32_t *keys, uint32_t n, uint32_t k, bool 
 template <int CAP>
 __device__ uint64_t prune_u64(uint64_t *keys, uint32_t n, uint32_t k)
 {
-    constexpr int PER = CAP / 64;
+    constexpr int PER = (CAP + 63) / 64;
     const int lane = threadIdx.x & 63;
     if (n <= k)
         return ~0ull;

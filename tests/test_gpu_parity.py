@@ -138,8 +138,10 @@ SCAN_M = [2, 4, 6, 8, 16, 32, 64, 128, 256]
 @pytest.mark.parametrize("Q", [1, 3, 7, 8, 9, 33, 70])
 def test_scan_parity(bolt, kind, M, Q):
     tuned = M in (8, 16, 32, 64, 128, 256)
-    if kind in (1, 2) and not tuned:
-        pytest.skip("tuned kernels take power-of-two M >= 8")
+    if kind == 2 and not tuned:
+        pytest.skip("the grouped kernel takes power-of-two M in 8..256")
+    if kind == 1 and M not in (8, 16, 32, 64):
+        pytest.skip("the few-query kernel takes M in {8, 16, 32, 64}")
     if kind == 1 and Q >= 8:
         pytest.skip("few-query kernel takes Q < 8")
     N = 3000 + 37
@@ -305,6 +307,8 @@ FUSED_CASES = [
     (32, 17, 50000, 100, "coarse"), (32, 40, 20000, 10, "rand"), (16, 16, 70000, 256, "rand"),
     (8, 33, 17000, 64, "coarse"), (64, 9, 40000, 100, "rand"), (64, 12, 30000, 100, "const"),
     (32, 64, 16384 * 3 + 5, 100, "rand"), (32, 20, 5, 100, "rand"), (16, 100, 4000, 1, "coarse"),
+    # many candidate lists per query: two-level merge (few-query and grouped kernels)
+    (32, 2, 2_000_000, 100, "rand"), (16, 9, 1_200_000, 256, "coarse"), (64, 7, 300_000, 50, "rand"),
 ]
 
 
