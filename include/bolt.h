@@ -176,6 +176,62 @@ int bolt_amm(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
              int32_t transpose, void *stream);
 
 /*
+ * Batched scan + top-k over many encoded databases of uneven size in one
+ * persistent launch: the scan + top-k of bolt_scan_topk (Sec. 3.1 scan,
+ * Sec. 1.2 the k closest vectors) for every (database, query) of the batch,
+ * with bit-identical results.
+ *
+ * bolt_batch_db describes one database and its queries (all DEVICE pointers):
+ *   codes [N][M/2], luts [Q][M][16] (16-byte aligned), vals [Q][k] and idx
+ *   [Q][k] receive the sorted top k as in bolt_scan_topk (k smallest sums for
+ *   BOLT_METRIC_L2, k largest for BOLT_METRIC_DOT).  M in {8, 16, 32, 64},
+ *   1 <= k <= 256.  Q = 0 databases are ignored; N = 0 gives padding.
+ * bolt_batch_tuning (may be NULL for defaults): rows_per_tile (multiple of
+ *   1024 in [1024, 65536], default 16384), few_max_q (databases with at most
+ *   this many queries use the pair-table path, 0..7, default 4), blocks_per_cu
+ *   (persistent workgroups per CU, 1..8, default 3).
+ * bolt_batch_plan_create builds the tile list on the host, uploads it into
+ *   the caller-owned DEVICE workspace ws (bolt_batch_ws_bytes bytes, 256-byte
+ *   aligned; it also holds the candidate lists) and synchronises the stream.
+ *   The plan (a host object) and ws must outlive every run.
+ * bolt_batch_run enqueues one batched pass on the stream: it reads the
+ *   current contents of every luts buffer, so new queries can be written in
+ *   place between runs.  Runs sharing a plan must not overlap.
+ * bolt_batch_graph_create captures one run in a HIP graph (instantiated,
+ *   returned as void*); bolt_batch_graph_launch replays it on a stream.
+ */
+typedef struct bolt_batch_db {
+    const uint8_t *codes;
+    int64_t N;
+    int32_t M;
+    int32_t metric;
+    const uint8_t *luts;
+    int32_t Q;
+    int32_t k;
+    uint16_t *vals;
+    int32_t *idx;
+} bolt_batch_db;
+
+typedef struct bolt_batch_tuning {
+    int32_t rows_per_tile;
+    int32_t few_max_q;
+    int32_t blocks_per_cu;
+} bolt_batch_tuning;
+
+typedef struct bolt_batch_plan bolt_batch_plan;
+
+size_t bolt_batch_ws_bytes(const bolt_batch_db *dbs, int32_t n_db, const bolt_batch_tuning *tuning);
+int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db, const bolt_batch_tuning *tuning,
+                           void *ws, size_t ws_bytes, void *stream, bolt_batch_plan **plan);
+int bolt_batch_run(const bolt_batch_plan *plan, void *stream);
+int bolt_batch_plan_info(const bolt_batch_plan *plan, int64_t *n_tiles, int64_t *n_queries,
+                         int32_t *grid);
+int bolt_batch_plan_destroy(bolt_batch_plan *plan);
+int bolt_batch_graph_create(const bolt_batch_plan *plan, void **graph_exec);
+int bolt_batch_graph_launch(void *graph_exec, void *stream);
+int bolt_batch_graph_destroy(void *graph_exec);
+
+/*
  * Offline phase (Sec. 1.2), on the HOST: codebooks by k-means with K = 16
  * per subspace (Sec. 3.1, 3.2), then the quantiser of Sec. 3.2 for one
  * metric.  All pointers are HOST pointers.  Random choices are inputs:
@@ -213,6 +269,15 @@ int bolt_learn_quantizer_host(const float *Qt, int64_t nq, int32_t J, int64_t ld
                               const uint8_t *codes, int64_t n, const float *centroids,
                               int32_t M, int32_t metric, const double *alphas,
                               int32_t nalpha, float *a, float *offsets, int32_t *alpha_idx);
+
+/*
+ * Test hooks (not part of the hot path): pin the scan kernel (-1 automatic,
+ * 0 plain loop, 1 pair tables for few queries, 2 grouped) and route
+ * bolt_scan_topk through the unfused scan-then-select path (on != 0).
+ * Process-wide settings, not thread-safe.
+ */
+int bolt_debug_force_scan_kernel(int32_t kind);
+int bolt_debug_force_unfused_topk(int32_t on);
 
 #ifdef __cplusplus
 }

@@ -290,3 +290,109 @@ def debug_force_unfused_topk(on: bool):
 def debug_force_scan_kernel(kind: int):
     """Test hook: -1 automatic, 0 generic, 1 few-query, 2 grouped."""
     _check(_lib.bolt_debug_force_scan_kernel(kind))
+
+
+# ------------------------------------------------------------------ batched databases
+
+class BatchDb(ctypes.Structure):
+    _fields_ = [("codes", _P), ("N", _I64), ("M", _I32), ("metric", _I32), ("luts", _P),
+                ("Q", _I32), ("k", _I32), ("vals", _P), ("idx", _P)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("rows_per_tile", _I32), ("few_max_q", _I32), ("blocks_per_cu", _I32)]
+
+
+for _name, _args, _res in [
+    ("bolt_batch_ws_bytes", [ctypes.POINTER(BatchDb), _I32, ctypes.POINTER(BatchTuning)], _SZ),
+    ("bolt_batch_plan_create", [ctypes.POINTER(BatchDb), _I32, ctypes.POINTER(BatchTuning), _P, _SZ, _P,
+                                ctypes.POINTER(_P)], ctypes.c_int),
+    ("bolt_batch_run", [_P, _P], ctypes.c_int),
+    ("bolt_batch_plan_info", [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
+     ctypes.c_int),
+    ("bolt_batch_plan_destroy", [_P], ctypes.c_int),
+    ("bolt_batch_graph_create", [_P, ctypes.POINTER(_P)], ctypes.c_int),
+    ("bolt_batch_graph_launch", [_P, _P], ctypes.c_int),
+    ("bolt_batch_graph_destroy", [_P], ctypes.c_int),
+]:
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+class BatchPlan:
+    """A planned batched scan + top-k over many databases (bolt_batch_*).
+
+    dbs: list of dicts with keys codes (uint8 [N, M/2]), luts (uint8 [Q, M, 16]),
+    metric ("l2"/"dot"), k; outputs vals/idx are allocated here unless given.
+    The plan keeps references to every tensor it points at.
+    """
+
+    def __init__(self, dbs, tuning=None, stream=None):
+        self.dbs = []
+        arr = (BatchDb * max(len(dbs), 1))()
+        dev = None
+        for i, d in enumerate(dbs):
+            codes, luts = d["codes"], d["luts"]
+            _dev(codes, torch.uint8, "codes")
+            _dev(luts, torch.uint8, "luts")
+            dev = codes.device
+            Q, M = luts.shape[0], luts.shape[1]
+            k = int(d.get("k", 100))
+            vals = d.get("vals")
+            idx = d.get("idx")
+            if vals is None:
+                vals = torch.empty((Q, k), dtype=torch.uint16, device=codes.device)
+            if idx is None:
+                idx = torch.empty((Q, k), dtype=torch.int32, device=codes.device)
+            self.dbs.append({"codes": codes, "luts": luts, "vals": vals, "idx": idx, "k": k, "M": M,
+                             "metric": metric_id(d.get("metric", "l2"))})
+            arr[i] = BatchDb(_ptr(codes), codes.shape[0], M, metric_id(d.get("metric", "l2")),
+                             _ptr(luts), Q, k, _ptr(vals), _ptr(idx))
+        self._arr = arr
+        self.tuning = BatchTuning(*(tuning or (0, 0, 0)))
+        n = len(dbs)
+        nbytes = int(_lib.bolt_batch_ws_bytes(arr, n, ctypes.byref(self.tuning)))
+        if nbytes == 0:
+            raise BoltError(BOLT_ERR_INVALID, last_error())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev or "cuda")
+        self._plan = _P()
+        _check(_lib.bolt_batch_plan_create(arr, n, ctypes.byref(self.tuning), _ptr(self.ws), nbytes,
+                                           _stream(stream), ctypes.byref(self._plan)))
+        self._graph = None
+
+    def info(self):
+        t, q, g = _I64(), _I64(), _I32()
+        _check(_lib.bolt_batch_plan_info(self._plan, ctypes.byref(t), ctypes.byref(q), ctypes.byref(g)))
+        return {"tiles": t.value, "queries": q.value, "grid": g.value}
+
+    def run(self, stream=None):
+        _check(_lib.bolt_batch_run(self._plan, _stream(stream)))
+
+    def capture(self):
+        """Capture one run in a HIP graph (replayed by launch_graph)."""
+        if self._graph is None:
+            g = _P()
+            _check(_lib.bolt_batch_graph_create(self._plan, ctypes.byref(g)))
+            self._graph = g
+        return self._graph
+
+    def launch_graph(self, stream=None):
+        _check(_lib.bolt_batch_graph_launch(self.capture(), _stream(stream)))
+
+    def results(self):
+        return [(d["vals"], d["idx"]) for d in self.dbs]
+
+    def close(self):
+        if getattr(self, "_graph", None) is not None:
+            _lib.bolt_batch_graph_destroy(self._graph)
+            self._graph = None
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            _lib.bolt_batch_plan_destroy(self._plan)
+            self._plan = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

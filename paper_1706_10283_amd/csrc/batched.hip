@@ -1,0 +1,433 @@
+// Many queries against many encoded databases of uneven size in one
+// persistent launch (the batched form of the scan + top-k of Sec. 3.1 and
+// Sec. 1.2).
+//
+// Plan (host): every database is cut into tiles (query block x row block):
+// query blocks of 16 (8 for M = 64) on the grouped path, or all of a
+// database's queries on the pair-table path when they are few; row blocks
+// of `rows_per_tile` rows.  Tiles are sorted by decreasing work so that the
+// dynamic schedule hands out the longest tiles first.  The descriptors, the
+// per-database candidate lists and per-query bounds live in one caller-owned
+// workspace.
+//
+// Run (device): a fill kernel resets the tile counter and the bounds; the
+// persistent kernel (a few workgroups per CU) pulls tiles from the counter
+// until it passes the tile count, so every wave exits; a merge kernel then
+// turns each query's candidate lists into its sorted top k.  The three
+// launches depend only on the plan, so they can be captured once in a HIP
+// graph and replayed with new query tables in place.  Results are
+// bit-identical to bolt_scan_topk on each database alone: the sums are exact
+// integers and the keys totally ordered.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "scan_common.hpp"
+#include "tiles.hpp"
+
+namespace {
+
+struct DevDb {
+    const uint8_t *codes;
+    const uint8_t *luts;
+    uint64_t *cand;
+    uint32_t *gthr;
+    uint16_t *vals;
+    int32_t *idx;
+    int64_t N;
+    int64_t n_rb;
+    int32_t M;
+    int32_t Q;
+    int32_t k;
+    int32_t largest;
+};
+
+struct DevTile {
+    int32_t db;
+    int32_t kind;   // 1 pair tables (few queries), 2 grouped
+    int32_t q0;
+    int32_t nq;
+    int64_t rb;
+};
+
+struct DevQuery {
+    int32_t db;
+    int32_t q;
+};
+
+// Largest LDS footprint of any tile: GroupedLds<32, 2> or a few-query tile
+// of at most this many bytes.
+constexpr size_t kBatchLds = 49664;
+
+__global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0)
+        *counter = 0;
+    if (i < n)
+        gthr[i] = 0xFFFFu;
+}
+
+template <int MM>
+__device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_tile, char *lds)
+{
+    bolt::TileJob job;
+    job.codes = db.codes;
+    job.luts = db.luts;
+    job.cand = db.cand;
+    job.gthr = db.gthr;
+    job.rb = t.rb;
+    job.r0 = t.rb * rows_per_tile;
+    job.r1 = (job.r0 + rows_per_tile) < db.N ? (job.r0 + rows_per_tile) : db.N;
+    job.n_rb = db.n_rb;
+    job.q0 = t.q0;
+    job.nq = t.nq;
+    job.k = (uint32_t)db.k;
+    job.largest = db.largest;
+    if (t.kind == 1) {
+        bolt::few_tile<MM>(job, lds);
+    } else {
+        constexpr int NG = MM <= 32 ? 2 : 1;
+        bolt::grouped_tile<MM, NG>(job, *reinterpret_cast<bolt::GroupedLds<MM, NG> *>(lds));
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict__ dbs,
+                                                         const DevTile *__restrict__ tiles,
+                                                         int32_t n_tiles, int64_t rows_per_tile,
+                                                         uint32_t *counter)
+{
+    static_assert(sizeof(bolt::GroupedLds<32, 2>) <= kBatchLds, "grouped tile LDS");
+    static_assert(sizeof(bolt::GroupedLds<64, 1>) <= kBatchLds, "grouped tile LDS");
+    static_assert(sizeof(bolt::GroupedLds<16, 2>) <= kBatchLds, "grouped tile LDS");
+    static_assert(sizeof(bolt::GroupedLds<8, 2>) <= kBatchLds, "grouped tile LDS");
+    __shared__ __attribute__((aligned(16))) char lds[kBatchLds];
+    __shared__ int32_t sh_tile;
+    for (;;) {
+        if (threadIdx.x == 0)
+            sh_tile = (int32_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int32_t ti = sh_tile;
+        __syncthreads();   // everyone has read sh_tile; the previous tile is done with LDS
+        if (ti >= n_tiles)
+            break;
+        const DevTile t = tiles[ti];
+        const DevDb db = dbs[t.db];
+        switch (db.M) {
+        case 8: run_tile<8>(db, t, rows_per_tile, lds); break;
+        case 16: run_tile<16>(db, t, rows_per_tile, lds); break;
+        case 32: run_tile<32>(db, t, rows_per_tile, lds); break;
+        default: run_tile<64>(db, t, rows_per_tile, lds); break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restrict__ dbs,
+                                                          const DevQuery *__restrict__ queries)
+{
+    const DevQuery qq = queries[blockIdx.x];
+    const DevDb db = dbs[qq.db];
+    const int64_t per_query = db.n_rb * db.k;
+    bolt::merge_keys(db.cand + (int64_t)qq.q * per_query, 0, per_query, (uint32_t)db.k, db.gthr[qq.q],
+                     nullptr, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
+                     db.idx + (int64_t)qq.q * db.k);
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+    size_t dbs_off, tiles_off, queries_off, gthr_off, counter_off, cand_off, total;
+    int64_t n_tiles, n_queries;
+};
+
+int resolve(const bolt_batch_tuning *tuning, int32_t &rows, int32_t &few_max, int32_t &per_cu)
+{
+    rows = tuning && tuning->rows_per_tile ? tuning->rows_per_tile : 16384;
+    few_max = tuning && tuning->few_max_q ? tuning->few_max_q : 4;
+    per_cu = tuning && tuning->blocks_per_cu ? tuning->blocks_per_cu : 3;
+    if (rows < 1024 || rows > bolt::kTileRowsMax || rows % 1024)
+        return bolt::fail(BOLT_ERR_INVALID, "rows_per_tile must be a multiple of 1024 in [1024, 65536]");
+    if (few_max < 0 || few_max > 7)
+        return bolt::fail(BOLT_ERR_INVALID, "few_max_q must be in [0, 7]");
+    if (per_cu < 1 || per_cu > 8)
+        return bolt::fail(BOLT_ERR_INVALID, "blocks_per_cu must be in [1, 8]");
+    return BOLT_OK;
+}
+
+// Pair-table tiles need their LDS to fit the persistent kernel's buffer.
+bool few_fits(int M, int nq) { return bolt::few_tile_lds_bytes(M, nq) <= kBatchLds; }
+
+int validate(const bolt_batch_db *dbs, int32_t n_db)
+{
+    if (n_db < 0 || (n_db > 0 && !dbs))
+        return bolt::fail(BOLT_ERR_INVALID, "bad database list");
+    for (int i = 0; i < n_db; ++i) {
+        const bolt_batch_db &d = dbs[i];
+        if (!(d.M == 8 || d.M == 16 || d.M == 32 || d.M == 64))
+            return bolt::fail(BOLT_ERR_UNSUPPORTED, "database %d: M must be 8, 16, 32 or 64", i);
+        if (d.N < 0 || d.N > INT32_MAX || d.Q < 0)
+            return bolt::fail(BOLT_ERR_SHAPE, "database %d: bad N or Q", i);
+        if (d.k < 1 || d.k > 256)
+            return bolt::fail(BOLT_ERR_UNSUPPORTED, "database %d: k must be in [1, 256]", i);
+        if (d.metric != BOLT_METRIC_L2 && d.metric != BOLT_METRIC_DOT)
+            return bolt::fail(BOLT_ERR_INVALID, "database %d: bad metric", i);
+        if (d.Q > 0 && (!d.luts || !d.vals || !d.idx || (d.N > 0 && !d.codes)))
+            return bolt::fail(BOLT_ERR_INVALID, "database %d: null pointer", i);
+        if (!bolt::aligned(d.codes, 16) || !bolt::aligned(d.luts, 16))
+            return bolt::fail(BOLT_ERR_INVALID, "database %d: codes and tables must be 16-byte aligned", i);
+    }
+    return BOLT_OK;
+}
+
+Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t few_max)
+{
+    Layout L{};
+    int64_t tiles = 0, queries = 0;
+    size_t cand = 0;
+    for (int i = 0; i < n_db; ++i) {
+        const bolt_batch_db &d = dbs[i];
+        if (d.Q == 0)
+            continue;
+        const int64_t n_rb = (d.N + rows - 1) / rows;   // 0 for an empty database: padding only
+        const bool few = d.Q <= few_max && few_fits(d.M, d.Q);
+        const int qb = d.M <= 32 ? 16 : 8;
+        const int64_t n_qb = few ? 1 : (d.Q + qb - 1) / qb;
+        tiles += n_rb * n_qb;
+        queries += d.Q;
+        cand += align256((size_t)d.Q * n_rb * d.k * sizeof(uint64_t));
+    }
+    L.n_tiles = tiles;
+    L.n_queries = queries;
+    size_t off = 0;
+    L.dbs_off = off;
+    off += align256(sizeof(DevDb) * (size_t)(n_db > 0 ? n_db : 1));
+    L.tiles_off = off;
+    off += align256(sizeof(DevTile) * (size_t)(tiles > 0 ? tiles : 1));
+    L.queries_off = off;
+    off += align256(sizeof(DevQuery) * (size_t)(queries > 0 ? queries : 1));
+    L.gthr_off = off;
+    off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
+    L.counter_off = off;
+    off += 256;
+    L.cand_off = off;
+    off += cand;
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct bolt_batch_plan {
+    char *ws = nullptr;
+    int64_t n_tiles = 0, n_queries = 0;
+    int32_t rows_per_tile = 0, grid = 0;
+    std::vector<char> host;   // staged descriptors (kept until the plan is destroyed)
+    DevDb *dbs = nullptr;
+    DevTile *tiles = nullptr;
+    DevQuery *queries = nullptr;
+    uint32_t *gthr = nullptr;
+    uint32_t *counter = nullptr;
+};
+
+extern "C" size_t bolt_batch_ws_bytes(const bolt_batch_db *dbs, int32_t n_db, const bolt_batch_tuning *tuning)
+{
+    int32_t rows, few_max, per_cu;
+    if (resolve(tuning, rows, few_max, per_cu) || validate(dbs, n_db))
+        return 0;
+    return layout_of(dbs, n_db, rows, few_max).total;
+}
+
+extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
+                                      const bolt_batch_tuning *tuning, void *ws, size_t ws_bytes,
+                                      void *stream, bolt_batch_plan **plan_out)
+{
+    using namespace bolt;
+    if (!plan_out)
+        return fail(BOLT_ERR_INVALID, "plan pointer is null");
+    *plan_out = nullptr;
+    int32_t rows, few_max, per_cu;
+    BOLT_TRY(resolve(tuning, rows, few_max, per_cu));
+    BOLT_TRY(validate(dbs, n_db));
+    const Layout L = layout_of(dbs, n_db, rows, few_max);
+    if (L.n_tiles > INT32_MAX)
+        return fail(BOLT_ERR_UNSUPPORTED, "too many tiles");
+    if (ws_bytes < L.total || !ws || !aligned(ws, 256))
+        return fail(BOLT_ERR_NOMEM, "batch workspace of %zu bytes (256-byte aligned) needed", L.total);
+
+    bolt_batch_plan *p = new bolt_batch_plan();
+    p->ws = reinterpret_cast<char *>(ws);
+    p->n_tiles = L.n_tiles;
+    p->n_queries = L.n_queries;
+    p->rows_per_tile = rows;
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    p->grid = per_cu * cus;
+    p->dbs = reinterpret_cast<DevDb *>(p->ws + L.dbs_off);
+    p->tiles = reinterpret_cast<DevTile *>(p->ws + L.tiles_off);
+    p->queries = reinterpret_cast<DevQuery *>(p->ws + L.queries_off);
+    p->gthr = reinterpret_cast<uint32_t *>(p->ws + L.gthr_off);
+    p->counter = reinterpret_cast<uint32_t *>(p->ws + L.counter_off);
+
+    std::vector<DevDb> hd(n_db);
+    std::vector<DevTile> ht;
+    std::vector<double> cost;
+    std::vector<DevQuery> hq;
+    ht.reserve(L.n_tiles);
+    cost.reserve(L.n_tiles);
+    hq.reserve(L.n_queries);
+    size_t cand_off = L.cand_off;
+    int64_t qbase = 0;
+    for (int i = 0; i < n_db; ++i) {
+        const bolt_batch_db &d = dbs[i];
+        DevDb &o = hd[i];
+        std::memset(&o, 0, sizeof(o));
+        o.codes = d.codes;
+        o.luts = d.luts;
+        o.vals = d.vals;
+        o.idx = d.idx;
+        o.N = d.N;
+        o.M = d.M;
+        o.Q = d.Q;
+        o.k = d.k;
+        o.largest = d.metric == BOLT_METRIC_DOT;
+        if (d.Q == 0)
+            continue;
+        o.n_rb = (d.N + rows - 1) / rows;
+        o.cand = reinterpret_cast<uint64_t *>(p->ws + cand_off);
+        cand_off += align256((size_t)d.Q * o.n_rb * d.k * sizeof(uint64_t));
+        o.gthr = p->gthr + qbase;
+        qbase += d.Q;
+        const bool few = d.Q <= few_max && few_fits(d.M, d.Q);
+        const int qb = few ? d.Q : (d.M <= 32 ? 16 : 8);
+        for (int64_t rb = 0; rb < o.n_rb; ++rb) {
+            const int64_t r = std::min<int64_t>(rows, d.N - rb * rows);
+            for (int q0 = 0; q0 < d.Q; q0 += qb) {
+                DevTile t;
+                t.db = i;
+                t.kind = few ? 1 : 2;
+                t.q0 = q0;
+                t.nq = std::min(qb, d.Q - q0);
+                t.rb = rb;
+                ht.push_back(t);
+                // grouped tiles pay for a full query block whatever nq is
+                cost.push_back((double)r * d.M * (few ? t.nq : qb));
+            }
+        }
+        for (int q = 0; q < d.Q; ++q)
+            hq.push_back({i, q});
+    }
+    // longest tiles first
+    std::vector<int64_t> order(ht.size());
+    for (size_t e = 0; e < order.size(); ++e)
+        order[e] = (int64_t)e;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    const size_t nb_db = sizeof(DevDb) * hd.size(), nb_t = sizeof(DevTile) * ht.size(),
+                 nb_q = sizeof(DevQuery) * hq.size();
+    p->host.resize(nb_db + nb_t + nb_q + 1);
+    std::memcpy(p->host.data(), hd.data(), nb_db);
+    DevTile *st = reinterpret_cast<DevTile *>(p->host.data() + nb_db);
+    for (size_t e = 0; e < order.size(); ++e)
+        st[e] = ht[order[e]];
+    std::memcpy(p->host.data() + nb_db + nb_t, hq.data(), nb_q);
+    hipStream_t s = as_stream(stream);
+    hipError_t e1 = hipMemcpyAsync(p->dbs, p->host.data(), nb_db, hipMemcpyHostToDevice, s);
+    hipError_t e2 = hipMemcpyAsync(p->tiles, p->host.data() + nb_db, nb_t, hipMemcpyHostToDevice, s);
+    hipError_t e3 = hipMemcpyAsync(p->queries, p->host.data() + nb_db + nb_t, nb_q, hipMemcpyHostToDevice, s);
+    hipError_t e4 = hipStreamSynchronize(s);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+        delete p;
+        return fail(BOLT_ERR_DEVICE, "uploading the batch plan failed");
+    }
+    *plan_out = p;
+    return BOLT_OK;
+}
+
+extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
+{
+    using namespace bolt;
+    if (!p)
+        return fail(BOLT_ERR_INVALID, "plan is null");
+    if (p->n_queries == 0)
+        return BOLT_OK;
+    hipStream_t s = as_stream(stream);
+    const int64_t nz = p->n_queries;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, p->counter,
+                       p->gthr, nz);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs, p->tiles,
+                       (int32_t)p->n_tiles, (int64_t)p->rows_per_tile, p->counter);
+    hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)p->n_queries), dim3(256), 0, s, p->dbs,
+                       p->queries);
+    return check_launch("bolt_batch_run");
+}
+
+extern "C" int bolt_batch_plan_info(const bolt_batch_plan *p, int64_t *n_tiles, int64_t *n_queries,
+                                    int32_t *grid)
+{
+    if (!p)
+        return bolt::fail(BOLT_ERR_INVALID, "plan is null");
+    if (n_tiles)
+        *n_tiles = p->n_tiles;
+    if (n_queries)
+        *n_queries = p->n_queries;
+    if (grid)
+        *grid = p->grid;
+    return BOLT_OK;
+}
+
+extern "C" int bolt_batch_plan_destroy(bolt_batch_plan *p)
+{
+    delete p;
+    return BOLT_OK;
+}
+
+// HIP graph of one run: captured on a private stream, replayable on any.
+extern "C" int bolt_batch_graph_create(const bolt_batch_plan *p, void **graph_exec)
+{
+    using namespace bolt;
+    if (!p || !graph_exec)
+        return fail(BOLT_ERR_INVALID, "null argument");
+    *graph_exec = nullptr;
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return fail(BOLT_ERR_DEVICE, "stream creation failed");
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    int st = BOLT_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = fail(BOLT_ERR_DEVICE, "hipStreamBeginCapture failed");
+    } else {
+        const int rs = bolt_batch_run(p, cs);
+        const hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (rs != BOLT_OK)
+            st = rs;
+        else if (ee != hipSuccess || !g)
+            st = fail(BOLT_ERR_DEVICE, "hipStreamEndCapture failed");
+        else if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
+            st = fail(BOLT_ERR_DEVICE, "hipGraphInstantiate failed");
+    }
+    if (g)
+        hipGraphDestroy(g);
+    hipStreamDestroy(cs);
+    if (st == BOLT_OK)
+        *graph_exec = ge;
+    return st;
+}
+
+extern "C" int bolt_batch_graph_launch(void *graph_exec, void *stream)
+{
+    using namespace bolt;
+    if (!graph_exec)
+        return fail(BOLT_ERR_INVALID, "graph is null");
+    if (hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(graph_exec), as_stream(stream)) != hipSuccess)
+        return fail(BOLT_ERR_DEVICE, "hipGraphLaunch failed");
+    return BOLT_OK;
+}
+
+extern "C" int bolt_batch_graph_destroy(void *graph_exec)
+{
+    if (graph_exec)
+        hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec));
+    return BOLT_OK;
+}

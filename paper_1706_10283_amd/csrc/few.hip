@@ -12,94 +12,20 @@
 // which keeps occupancy high for a single query.
 #include "common.hpp"
 #include "scan_common.hpp"
-#include "topk_device.hpp"
+#include "tiles.hpp"
 
 namespace {
 
 using bolt::load_row;
 using bolt::OutMode;
 
-constexpr int kR = 4;                       // rows per lane per pass
-constexpr int kPass = 256 * kR;             // rows per pass
-constexpr int kFewCap = 2 * kPass;          // candidate slots per query (fused)
-constexpr int kFewRowsMax = 65536;          // rows per workgroup at most (16-bit local rows)
+constexpr int kPass = bolt::kFewPass;        // rows per pass
+constexpr int kFewRowsMax = bolt::kTileRowsMax;
 
-template <int MM>
-__device__ __forceinline__ void build_pair_tables(const uint8_t *__restrict__ luts, int nq, uint16_t *pt)
-{
-    constexpr int NP = MM / 2;
-    for (int e = threadIdx.x; e < nq * NP * 256; e += 256) {
-        const int b = e & 255, p = (e >> 8) % NP, q = (e >> 8) / NP;
-        const uint8_t *l = luts + ((int64_t)q * MM + 2 * p) * 16;
-        pt[e] = (uint16_t)(l[b & 15] + l[16 + (b >> 4)]);
-    }
-}
-
-// Sums of query q for the kR rows held in cw (pair tables of q at tq).
-template <int MM>
-__device__ __forceinline__ void sums_for(const uint16_t *tq, const uint32_t (&cw)[kR][MM / 8],
-                                         uint32_t (&s)[kR])
-{
-    const char *tb = reinterpret_cast<const char *>(tq);
-    uint32_t part[kR];
-#pragma unroll
-    for (int r = 0; r < kR; ++r)
-        part[r] = 0;
-    // one code dword (four pairs) per step keeps 4*kR reads in flight and the
-    // register count low
-#pragma unroll 1
-    for (int t = 0; t < MM / 8; ++t) {
-        uint32_t w[kR];
-#pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            w[r] = cw[r][0];
-#pragma unroll
-            for (int v = 1; v < MM / 8; ++v)
-                w[r] = (t == v) ? cw[r][v] : w[r];
-        }
-        const char *tt = tb + t * 4 * 512;
-        uint32_t v[kR][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                const uint32_t byte = (w[r] >> (8 * j)) & 0xFFu;
-                v[r][j] = *reinterpret_cast<const uint16_t *>(tt + j * 512 + 2 * byte);
-            }
-#pragma unroll
-        for (int r = 0; r < kR; ++r)
-            part[r] += v[r][0] + v[r][1] + v[r][2] + v[r][3];
-    }
-#pragma unroll
-    for (int r = 0; r < kR; ++r)
-        s[r] = part[r];
-}
-
-template <int MM>
-__device__ __forceinline__ void copy_rows(const uint32_t (&a)[kR][MM / 8], uint32_t (&b)[kR][MM / 8])
-{
-#pragma unroll
-    for (int r = 0; r < kR; ++r)
-#pragma unroll
-        for (int v = 0; v < MM / 8; ++v)
-            b[r][v] = a[r][v];
-}
-
-template <int MM>
-__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ codes, int64_t base, int64_t r1,
-                                          uint32_t (&cw)[kR][MM / 8])
-{
-#pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        const int64_t n = base + threadIdx.x + 256 * r;
-        if (n < r1)
-            load_row<MM>(codes, n, cw[r]);
-        else
-#pragma unroll
-            for (int v = 0; v < MM / 8; ++v)
-                cw[r][v] = 0;
-    }
-}
+using bolt::build_pair_tables;
+using bolt::copy_rows4;
+using bolt::load_rows4;
+using bolt::pair_sums;
 
 // ------------------------------------------------------------------ plain
 
@@ -116,17 +42,17 @@ __global__ __launch_bounds__(256) void few_scan_kernel(const uint8_t *__restrict
     __syncthreads();
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = (r0 + rows_per_block) < N ? (r0 + rows_per_block) : N;
-    uint32_t cw[kR][MM / 8], nx[kR][MM / 8];
-    load_rows<MM>(codes, r0, r1, nx);
+    uint32_t cw[bolt::kFewR][MM / 8], nx[bolt::kFewR][MM / 8];
+    load_rows4<MM>(codes, r0, r1, nx);
     for (int64_t base = r0; base < r1; base += kPass) {
-        copy_rows<MM>(nx, cw);
+        copy_rows4<MM>(nx, cw);
         if (base + kPass < r1)   // next pass in flight while this one is computed
-            load_rows<MM>(codes, base + kPass, r1, nx);
+            load_rows4<MM>(codes, base + kPass, r1, nx);
         for (int q = 0; q < nq; ++q) {
-            uint32_t s[kR];
-            sums_for<MM>(pt + q * (MM / 2) * 256, cw, s);
+            uint32_t s[bolt::kFewR];
+            pair_sums<MM>(pt + q * (MM / 2) * 256, cw, s);
 #pragma unroll
-            for (int r = 0; r < kR; ++r) {
+            for (int r = 0; r < bolt::kFewR; ++r) {
                 const int64_t n = base + threadIdx.x + 256 * r;
                 if (n < r1) {
                     if (OUT == OutMode::U16) {
@@ -147,101 +73,31 @@ __global__ __launch_bounds__(256) void few_scan_kernel(const uint8_t *__restrict
 // ------------------------------------------------------------------ fused with top-k
 
 template <int MM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void few_scan_topk_kernel(const uint8_t *__restrict__ codes,
-                                                            int64_t N, const uint8_t *__restrict__ luts,
-                                                            int nq, uint32_t k, int largest,
-                                                            int64_t rows_per_block, int n_rb,
-                                                            uint64_t *__restrict__ cand,
-                                                            uint32_t *__restrict__ gthr)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void few_scan_topk_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int nq, uint32_t k,
+    int largest, int64_t rows_per_block, int n_rb, uint64_t *__restrict__ cand,
+    uint32_t *__restrict__ gthr)
 {
-    constexpr uint32_t SMAX = 255u * MM;
-    extern __shared__ __attribute__((aligned(16))) uint16_t pt[];   // tables, then buffers
-    uint32_t *buf = reinterpret_cast<uint32_t *>(pt + nq * (MM / 2) * 256);   // [nq][kFewCap]
-    uint32_t *cnt = buf + nq * kFewCap;                                       // [nq]
-    uint32_t *bnd = cnt + nq;                                                 // [nq]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rb = blockIdx.x;
-    build_pair_tables<MM>(luts, nq, pt);
-    if (tid < nq) {
-        cnt[tid] = 0;
-        bnd[tid] = __atomic_load_n(&gthr[tid], __ATOMIC_RELAXED) + 1u;
-    }
-    __syncthreads();
-    const int64_t r0 = (int64_t)rb * rows_per_block;
-    const int64_t r1 = (r0 + rows_per_block) < N ? (r0 + rows_per_block) : N;
-    int pass = 0;
-    uint32_t cw[kR][MM / 8], nx[kR][MM / 8];
-    load_rows<MM>(codes, r0, r1, nx);
-    for (int64_t base = r0; base < r1; base += kPass, ++pass) {
-        copy_rows<MM>(nx, cw);
-        if (base + kPass < r1)   // next pass in flight while this one is computed
-            load_rows<MM>(codes, base + kPass, r1, nx);
-        for (int q = 0; q < nq; ++q) {
-            uint32_t s[kR];
-            sums_for<MM>(pt + q * (MM / 2) * 256, cw, s);
-            const uint32_t bq = bnd[q];
-#pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                const int64_t n = base + tid + 256 * r;
-                const uint32_t d = largest ? SMAX - s[r] : s[r];
-                if (n < r1 && d < bq) {
-                    const uint32_t pos = atomicAdd(&cnt[q], 1u);
-                    buf[q * kFewCap + pos] = bolt::local_key(d, (uint32_t)(n - r0));
-                }
-            }
-        }
-        __syncthreads();
-        const bool refresh = (pass & 7) == 7;
-        for (int q = wave; q < nq; q += 4) {
-            const uint32_t c = cnt[q];
-            uint32_t nb = 0xFFFFFFFFu;
-            if (c > kFewCap - kPass) {
-                bolt::PruneResult pr = bolt::prune_local_lds<kFewCap>(buf + q * kFewCap, c, k, false);
-                if (pr.count > kFewCap - kPass)
-                    pr = bolt::prune_local_lds<kFewCap>(buf + q * kFewCap, pr.count, k, true);
-                if (lane == 0) {
-                    cnt[q] = pr.count;
-                    if (pr.T <= 0xFFFFu)
-                        atomicMin(&gthr[q], pr.T);
-                }
-                nb = pr.T;
-            }
-            if (lane == 0 && (nb != 0xFFFFFFFFu || refresh)) {
-                uint32_t b = bnd[q];
-                b = nb < b ? nb : b;
-                const uint32_t gb = __atomic_load_n(&gthr[q], __ATOMIC_RELAXED) + 1u;
-                bnd[q] = gb < b ? gb : b;
-            }
-        }
-        __syncthreads();
-    }
-    for (int q = wave; q < nq; q += 4) {
-        uint32_t n = cnt[q];
-        uint32_t *bq = buf + q * kFewCap;
-        if (n > k) {
-            const bolt::PruneResult pr = bolt::prune_local_lds<kFewCap>(bq, n, k, true);
-            n = pr.count;
-            if (lane == 0)
-                atomicMin(&gthr[q], pr.T);
-        }
-        uint64_t *dst = cand + ((int64_t)q * n_rb + rb) * (int64_t)k;
-        for (uint32_t j = lane; j < k; j += 64) {
-            uint64_t key = ~0ull;
-            if (j < n) {
-                const uint32_t lk = bq[j];
-                key = ((uint64_t)(lk >> 16) << 32) | (uint64_t)(r0 + (lk & 0xFFFFu));
-            }
-            dst[j] = key;
-        }
-    }
+    extern __shared__ __attribute__((aligned(16))) char few_lds[];
+    bolt::TileJob job;
+    job.codes = codes;
+    job.luts = luts;
+    job.cand = cand;
+    job.gthr = gthr;
+    job.rb = blockIdx.x;
+    job.r0 = job.rb * rows_per_block;
+    job.r1 = (job.r0 + rows_per_block) < N ? (job.r0 + rows_per_block) : N;
+    job.n_rb = n_rb;
+    job.q0 = 0;
+    job.nq = nq;
+    job.k = k;
+    job.largest = largest;
+    bolt::few_tile<MM>(job, few_lds);
 }
 
 size_t few_lds_bytes(int M, int nq, bool fused)
 {
-    size_t b = (size_t)nq * (M / 2) * 256 * sizeof(uint16_t);
-    if (fused)
-        b += (size_t)nq * (kFewCap + 2) * sizeof(uint32_t);
-    return b;
+    return fused ? bolt::few_tile_lds_bytes(M, nq) : (size_t)nq * (M / 2) * 256 * sizeof(uint16_t);
 }
 
 template <int MM, OutMode OUT>
