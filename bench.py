@@ -1,23 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the Bolt hot path on one MI355X.
 
-Workload (single-database scan): N = 1,000,000 database vectors of J = 128
-dimensions from the 256-component Gaussian mixture, M = 32 subspaces (16-byte
-codes), Q = 1,000 queries, squared-L2 and dot-product tables, top-100.
+Headline workload (single-database scan): N = 1,000,000 database vectors of
+J = 128 dimensions from the 256-component Gaussian mixture, M = 32 subspaces
+(16-byte codes), Q = 1,000 queries, squared-L2 and dot-product tables,
+top-100.  One step is one pass of the whole hot path over that batch with
+inputs resident in HBM: encode all N vectors, build the uint8 tables of the
+Q queries for both metrics, scan + top-100 for both metrics.  `value` is the
+number of (query, vector) distances produced per second over the whole step
+(both metrics).
 
-One step is one pass of the whole hot path over that batch, inputs resident
-in HBM: encode all N vectors, build the uint8 tables of the Q queries for both
-metrics, scan + top-100 for both metrics.  The reported value is the number
-of (query, vector) distances produced per second over the whole step, summed
-over both metrics.
+Sub-reports on the same line (each its own workload):
+  amm      approximate matrix product, A 200,000 x 256 N(0,1), M = 32,
+           B 256 x K for K in {64, 256, 1024}: throughput and accuracy
+           against the exact fp32 product (and the fp32 GEMM's time)
+  batched  256 uneven mixture databases (N log-uniform in [1e3, 2e6],
+           J in {64,128,256}, M in {16,32,64}, 1..512 queries each, top-100):
+           one autotuned persistent launch replayed from a HIP graph vs one
+           launch per (database, query), identical results
+  serving  8 resident databases of 2.5e8 x 128 at M = 32 (32 GB of codes),
+           Poisson requests (90% query batches of 1..64, 10% inserts of
+           1e4..1e6 vectors): p50/p99 latency at 0.3/0.6/0.9 of the measured
+           saturation rate, against the plain one-query-per-launch FIFO server
 
-Printed: one JSON line (rank 0).  Per-kernel durations come from HIP events
-recorded on the launch stream around each call inside the timed steps.
+Per-kernel durations come from HIP events that the library records on each
+kernel's launch stream inside the timed region (bolt_prof_*).
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -27,8 +40,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
-VALU_LANE_OPS = 256 * 64 * 2.4e9  # CUs x lanes x clock: 32-bit VALU lane-ops/s
+# MI355X: 256 CUs at 2.4 GHz, 64 lanes per CU and clock (32-bit VALU ops)
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_GBPS = 8000.0
 
 
 def log(*a):
@@ -46,87 +60,82 @@ def parse():
     p.add_argument("--Q", type=int, default=1000)
     p.add_argument("--k", type=int, default=100)
     p.add_argument("--n-train", type=int, default=100_000)
+    p.add_argument("--parts", default="headline,amm,batched,serving")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-rows", type=int, default=20_000)
+    p.add_argument("--batched-dbs", type=int, default=256)
+    p.add_argument("--serving-rows", type=int, default=250_000_000)
+    p.add_argument("--serving-requests", type=int, default=300)
+    p.add_argument("--fifo-requests", type=int, default=100)
     return p.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the scan shards by database rows; see DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
-    import torch
+def event_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+# ------------------------------------------------------------------ headline
+
+def headline(args, torch, B, W):
     import synth
     import synth.device as sdev
-    import paper_1706_10283_amd.bolt as B
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    dev = "cuda"
     N, J, M, Q, k = args.N, args.J, args.M, args.Q, args.k
-    cfg = 2
-    mix_seed = synth.seed_for(cfg, 0)
-
-    # ---------------- inputs (synthetic, generated in HBM) and offline training
+    mix = synth.seed_for(2, 0)
     t0 = time.time()
-    X = sdev.gmm_rows(mix_seed, synth.seed_for(cfg, 1), 0, N, J)
-    Qd = sdev.gmm_rows(mix_seed, synth.seed_for(cfg, 2), 0, Q, J)
-    Xtr = sdev.gmm_rows(mix_seed, synth.seed_for(cfg, 3), 0, args.n_train, J).cpu().numpy()
-    init = synth.permutation_prefix(synth.seed_for(cfg, 4), args.n_train, 16)
-    Qt = Xtr[synth.permutation_prefix(synth.seed_for(cfg, 5), args.n_train, 1000)]
-    C, a_l2, off_l2, _ = B.bolt_train_host(Xtr, M, 10, init, Qt, "l2")
-    tr_codes = B.bolt_encode(torch.from_numpy(Xtr).to(dev), torch.from_numpy(C).to(dev), M).cpu().numpy()
-    a_dot, off_dot, _ = B.bolt_learn_quantizer_host(Qt, tr_codes, C, "dot")
-    log("inputs + training: %.1fs" % (time.time() - t0))
+    X = sdev.gmm_rows(mix, synth.seed_for(2, 1), 0, N, J)
+    Qd = sdev.gmm_rows(mix, synth.seed_for(2, 2), 0, Q, J)
+    C, quant = W.train(mix, synth.seed_for(2, 3), synth.seed_for(2, 4), synth.seed_for(2, 5), J, M,
+                       args.n_train, iters=10)
+    log("headline inputs + training: %.1fs" % (time.time() - t0))
     Cd = torch.from_numpy(C).to(dev)
-    offd = {"l2": torch.from_numpy(off_l2).to(dev), "dot": torch.from_numpy(off_dot).to(dev)}
-    scale = {"l2": a_l2, "dot": a_dot}
-
+    offd = {m: torch.from_numpy(quant[m][1]).to(dev) for m in quant}
+    scale = {m: quant[m][0] for m in quant}
     codes = torch.empty((N, M // 2), dtype=torch.uint8, device=dev)
     luts = {m: torch.empty((Q, M, 16), dtype=torch.uint8, device=dev) for m in ("l2", "dot")}
     vals = {m: torch.empty((Q, k), dtype=torch.uint16, device=dev) for m in ("l2", "dot")}
     idx = {m: torch.empty((Q, k), dtype=torch.int32, device=dev) for m in ("l2", "dot")}
     ws = torch.empty(B.bolt_scan_topk_ws_bytes(N, M, Q, k), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    names = ["encode", "luts_l2", "luts_dot", "scan_topk_l2", "scan_topk_dot"]
-    ev = {n: [] for n in names}
 
-    def step(record):
-        def mark(name, fn):
-            if record:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                fn()
-                e1.record(stream)
-                ev[name].append((e0, e1))
-            else:
-                fn()
-        mark("encode", lambda: B.bolt_encode(X, Cd, M, codes=codes))
+    def step():
+        B.bolt_encode(X, Cd, M, codes=codes)
         for m in ("l2", "dot"):
-            mark("luts_" + m, lambda m=m: B.bolt_build_luts(Qd, Cd, M, m, scale[m], offd[m], luts_u8=luts[m]))
+            B.bolt_build_luts(Qd, Cd, M, m, scale[m], offd[m], luts_u8=luts[m])
         for m in ("l2", "dot"):
-            mark("scan_topk_" + m, lambda m=m: B.bolt_scan_topk(codes, luts[m], m, k, vals=vals[m],
-                                                                idx=idx[m], ws=ws))
+            B.bolt_scan_topk(codes, luts[m], m, k, vals=vals[m], idx=idx[m], ws=ws)
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
+    B.prof_read(reset=True)
+    B.prof_enable(True)
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
+        step()
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    B.prof_enable(False)
+    prof = B.prof_read(reset=True)
     ms_per_step = 1e3 * t_total / args.steps
-    kern_ms = {n: float(np.mean([a.elapsed_time(b) for a, b in ev[n]])) for n in names}
+    kern = {n: {"launches": c, "avg_ms": round(ms / c, 5)} for n, (c, ms) in prof.items()}
     dists = 2.0 * Q * N
     value = dists / (ms_per_step * 1e-3) / 1e9
 
-    enc_bytes = 4.0 * N * J + N * M / 2
-    scan_lookups = Q * N * M
-    scan_ms = 0.5 * (kern_ms["scan_topk_l2"] + kern_ms["scan_topk_dot"])
-    result = {
+    dom = "scan_topk_grouped"
+    dom_ms = prof[dom][1] / prof[dom][0]
+    lookups = float(Q) * N * M                      # one table lookup-and-add per (q, n, m)
+    achieved = lookups / (dom_ms * 1e-3)
+    enc_ms = prof["encode"][1] / prof["encode"][0]
+    res = {
         "metric": "G distances/sec scanned + encode GB/s; p50/p99 latency vs plain per-query scan",
         "value": round(value, 3),
         "unit": "G distances/s",
@@ -139,49 +148,245 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": "single-database scan: N=%d x J=%d Gaussian-mixture rows, M=%d "
-                               "(%d B codes), Q=%d queries, L2 + dot tables, top-%d"
+        "config": {"workload": "single-database scan: N=%d x J=%d Gaussian-mixture rows, M=%d (%d B "
+                               "codes), Q=%d queries, L2 + dot tables, encode + tables + scan + top-%d"
                                % (N, J, M, M // 2, Q, k),
                    "N": N, "J": J, "M": M, "Q": Q, "k": k},
-        "encode_GBps": round(4.0 * N * J / (kern_ms["encode"] * 1e-3) / 1e9, 1),
-        "kernel_ms": {n: round(v, 4) for n, v in kern_ms.items()},
-        "scan_topk_G_distances_per_s": round(Q * N / (scan_ms * 1e-3) / 1e9, 2),
-    }
-    lookups_per_s = scan_lookups / (scan_ms * 1e-3)
-    result["roofline"] = {
-        "bound": "alu",
-        "kernel": "scan_topk (u8 lookups)",
-        "achieved": round(lookups_per_s / 1e12, 3),
-        "peak": round(VALU_LANE_OPS / 1e12, 2),
-        "unit": "T lookups/s",
-        "frac": round(lookups_per_s / VALU_LANE_OPS, 4),
-        "traffic": None,
+        "encode_GBps": round(4.0 * N * J / (enc_ms * 1e-3) / 1e9, 1),
+        "scan_topk_G_distances_per_s": round(Q * N / (dom_ms * 1e-3) / 1e9, 2),
+        "kernels": kern,
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": round(achieved / 1e12, 3),
+            "peak": round(VALU_LANE_OPS / 1e12, 2),
+            "unit": "TOP/s",
+            "op": "table lookup-and-add (one per query, vector and subspace)",
+            "frac": round(achieved / VALU_LANE_OPS, 4),
+            "traffic": None,
+        },
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args, C, a_l2, off_l2, a_dot, off_dot,
-                                              Qd.cpu().numpy(), mix_seed)
-    print(json.dumps(result), flush=True)
+        res["cpu_baseline"] = cpu_baseline(args, C, quant, Qd.cpu().numpy(), mix)
+    del X, codes, ws
+    return res
 
 
-def cpu_baseline(args, C, a_l2, off_l2, a_dot, off_dot, Qv, mix_seed):
+def cpu_baseline(args, C, quant, Qv, mix):
     """The oracle as it stands, one host thread, on a bounded sample of the
-    same workload (the first rows of the database, all queries, both metrics)."""
+    headline workload: the first rows of the database, all queries, both
+    metrics, encode + tables + scan + top-k."""
     import oracle
     import synth
     n = args.cpu_sample_rows
-    M, k = args.M, args.k
-    X = synth.gmm_rows(mix_seed, synth.seed_for(2, 1), 0, n, args.J)
+    X = synth.gmm_rows(mix, synth.seed_for(2, 1), 0, n, args.J)
     t0 = time.perf_counter()
-    codes = oracle.encode(X, C, M)
-    for metric, a, off in (("l2", a_l2, off_l2), ("dot", a_dot, off_dot)):
-        _, _, l8 = oracle.luts(Qv, C, M, metric, a, off)
+    codes = oracle.encode(X, C, args.M)
+    for metric in ("l2", "dot"):
+        a, off = quant[metric]
+        _, _, l8 = oracle.luts(Qv, C, args.M, metric, a, off)
         S = oracle.scan(codes, l8)
-        oracle.topk(S, k, metric == "dot")
+        oracle.topk(S, args.k, metric == "dot")
     dt = time.perf_counter() - t0
     return {"value": round(2.0 * Qv.shape[0] * n / dt / 1e9, 5), "unit": "G distances/s", "cores": 1,
             "kind": "oracle",
-            "sample": "first %d of %d rows, all %d queries, L2 + dot, encode + tables + scan + top-%d; "
-                      "%.1f s" % (n, args.N, Qv.shape[0], k, dt)}
+            "sample": "first %d of %d rows, all %d queries, L2 + dot, encode + tables + scan + top-%d "
+                      "(%.1f s)" % (n, args.N, Qv.shape[0], args.k, dt)}
+
+
+# ------------------------------------------------------------------ approximate matrix product
+
+def run_amm(args, torch, B, W):
+    import synth
+    dev = "cuda"
+    N, J, M = 200_000, 256, 32
+    t0 = time.time()
+    A = synth.normal(synth.seed_for(3, 1), (N, J))
+    Btrain = synth.normal(synth.seed_for(3, 5), (1000, J))
+    init = synth.permutation_prefix(synth.seed_for(3, 4), N, 16)
+    C, a, offs, _ = B.bolt_train_host(A, M, 10, init, Btrain, "dot")
+    log("amm training: %.1fs" % (time.time() - t0))
+    Ad = torch.from_numpy(A).to(dev)
+    Cd = torch.from_numpy(C).to(dev)
+    offd = torch.from_numpy(offs).to(dev)
+    bias = float(np.float32(offs.astype(np.float64).sum()))
+    scale = float(np.float32(1.0 / a))
+    codes = B.bolt_encode(Ad, Cd, M)
+    # reconstruction of A (for the per-entry bound) and its row error norms
+    cu = torch.stack([codes & 15, codes >> 4], dim=2).reshape(N, M).long()
+    xhat = torch.cat([Cd[m][cu[:, m]] for m in range(M)], dim=1)
+    err_norm = torch.linalg.norm(Ad - xhat, dim=1)
+    out = {"workload": "A %dx%d N(0,1), M=%d, B %dxK N(0,1), dot tables" % (N, J, M, J), "K": {}}
+    enc_ms = event_ms(torch, lambda: B.bolt_encode(Ad, Cd, M, codes=codes), 5)
+    out["encode_ms"] = round(enc_ms, 4)
+    for K in (64, 256, 1024):
+        Bm = synth.normal(synth.seed_for(3, 2) + K, (J, K))
+        Qv = torch.from_numpy(np.ascontiguousarray(Bm.T)).to(dev)
+        luts = B.bolt_build_luts(Qv, Cd, M, "dot", a, offd)
+        res = torch.empty((K, N), dtype=torch.float32, device=dev)
+        t_luts = event_ms(torch, lambda: B.bolt_build_luts(Qv, Cd, M, "dot", a, offd, luts_u8=luts), 5)
+        t_amm = event_ms(torch, lambda: B.bolt_amm(codes, luts, bias, scale, out=res), 5)
+        Bd = torch.from_numpy(Bm).to(dev)
+        exact = torch.empty((K, N), dtype=torch.float32, device=dev)
+        t_gemm = event_ms(torch, lambda: torch.matmul(Bd.t().contiguous(), Ad.t(), out=exact), 5)
+        diff = (exact - res).double()
+        ex = exact.double()
+        r = torch.corrcoef(torch.stack([ex.flatten(), res.double().flatten()]))[0, 1].item()
+        rel = (torch.linalg.norm(diff) / torch.linalg.norm(ex)).item()
+        bound = torch.linalg.norm(Qv, dim=1)[:, None].double() * err_norm[None].double() + M / a
+        within = (diff.abs() <= bound * (1 + 1e-6)).double().mean().item()
+        out["K"][str(K)] = {"tables_ms": round(t_luts, 4), "amm_ms": round(t_amm, 4),
+                            "fp32_gemm_ms": round(t_gemm, 4),
+                            "G_distances_per_s": round(K * N / (t_amm * 1e-3) / 1e9, 2),
+                            "pearson_r": round(r, 5), "rel_frobenius_err": round(rel, 5),
+                            "frac_within_bound": round(within, 6)}
+        log("amm K=%d: %.3f ms, r=%.4f" % (K, t_amm, r))
+    return out
+
+
+# ------------------------------------------------------------------ batched databases
+
+def run_batched(args, torch, B, W):
+    from paper_1706_10283_amd import autotune
+    t0 = time.time()
+    specs = W.batched_specs(args.batched_dbs)
+    dbs = W.build_batched(specs, log=log)
+    log("batched inputs: %d databases, %.1fs" % (len(dbs), time.time() - t0))
+    entries = [{"codes": d["codes"], "luts": d["luts"], "metric": d["metric"], "k": d["k"]} for d in dbs]
+    tuner = autotune.BatchTuner(os.path.join(ROOT, "paper_1706_10283_amd", "tuning_cache.json"))
+    tuning, trials = tuner.tune(entries, log=log)
+    plan = B.BatchPlan(entries, tuning=tuning)
+    plan.capture()
+    for _ in range(2):
+        plan.launch_graph()
+    torch.cuda.synchronize()
+    B.prof_read(reset=True)
+    B.prof_enable(True)
+    reps = 5
+    t_graph = event_ms(torch, plan.launch_graph, reps)
+    B.prof_enable(False)
+    torch.cuda.synchronize()
+    batched_res = [(v.clone(), i.clone()) for v, i in plan.results()]
+
+    # baseline: one launch (sequence) per (database, query)
+    def per_query():
+        out = []
+        for d in dbs:
+            Q = d["luts"].shape[0]
+            vs, is_ = [], []
+            for q in range(Q):
+                v, i = B.bolt_scan_topk(d["codes"], d["luts"][q:q + 1], d["metric"], d["k"])
+                vs.append(v)
+                is_.append(i)
+            out.append((torch.cat(vs), torch.cat(is_)))
+        return out
+    per_query()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    base = per_query()
+    torch.cuda.synchronize()
+    t_base = (time.perf_counter() - t1) * 1e3
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(batched_res, base))
+    dist = float(sum(s.Q * s.N for s in specs))
+    lookups = float(sum(s.Q * s.N * s.M for s in specs))
+    info = plan.info()
+    plan.close()
+    return {"workload": "%d uneven databases, %d queries, %.3g rows, %.3g distances" % (
+                len(specs), sum(s.Q for s in specs), sum(s.N for s in specs), dist),
+            "tuning": {"rows_per_tile": tuning[0], "few_max_q": tuning[1], "blocks_per_cu": tuning[2]},
+            "autotune_trials": trials, "tiles": info["tiles"],
+            "graph_ms": round(t_graph, 3), "per_query_launches_ms": round(t_base, 1),
+            "speedup": round(t_base / t_graph, 1),
+            "G_distances_per_s": round(dist / (t_graph * 1e-3) / 1e9, 1),
+            "lookup_TOPs": round(lookups / (t_graph * 1e-3) / 1e12, 3),
+            "frac_of_lookup_peak": round(lookups / (t_graph * 1e-3) / VALU_LANE_OPS, 4),
+            "identical_to_per_query": bool(same)}
+
+
+# ------------------------------------------------------------------ serving
+
+def run_serving(args, torch, B, W):
+    import synth
+    import synth.device as sdev
+    from paper_1706_10283_amd.serve import GpuExecutor, Server, make_requests, summarize
+    n_db, N, J, M, k = 8, args.serving_rows, 128, 32, 100
+    t0 = time.time()
+    dbs = []
+    for d in range(n_db):
+        mix = synth.seed_for(5, 0) + 100 * d
+        C, quant = W.train(mix, mix + 3, mix + 4, mix + 5, J, M, n_train=50_000, iters=10)
+        dbs.append(W.build_db(mix, mix + 1, N, J, M, C, quant, capacity=N + 4_000_000))
+        log("serving database %d/%d built (%.1fs)" % (d + 1, n_db, time.time() - t0))
+    torch.cuda.synchronize()
+    resident = sum(db.codes.numel() for db in dbs)
+    qpool = sdev.gmm_rows(synth.seed_for(5, 0), synth.seed_for(5, 2), 0, 8192, J).cpu().numpy()
+    ipool = sdev.gmm_rows(synth.seed_for(5, 0), synth.seed_for(5, 3), 0, 1_000_000, J).cpu().pin_memory()
+    budget = 8 << 30   # working memory on top of the resident codes
+    ex = GpuExecutor(dbs)
+
+    def serve(mode, rate, n_req, seed):
+        reqs = make_requests(n_req, n_db, J, rate, seed, qpool, ipool, k=k)
+        srv = Server(ex, dbs, budget, mode=mode)
+        wall = srv.run(reqs, realtime=rate > 0)
+        torch.cuda.synchronize()
+        return reqs, wall, srv
+
+    serve("continuous", 0.0, 30, 1)   # warm-up
+    reqs, wall, _ = serve("continuous", 0.0, args.serving_requests, 2)
+    sat = len(reqs) / wall
+    out = {"workload": "%d databases x %.3g rows, J=%d, M=%d (%.1f GB codes), budget resident + 8 GB"
+                       % (n_db, N, J, M, resident / 1e9),
+           "saturation_req_per_s": round(sat, 2), "continuous": {}, "fifo": {}}
+    out["continuous"]["saturation"] = summarize(reqs, wall)
+    check = None
+    for load in (0.3, 0.6, 0.9):
+        reqs, wall, srv = serve("continuous", load * sat, args.serving_requests, 10 + int(load * 10))
+        out["continuous"]["load_%.1f" % load] = summarize(reqs, wall)
+        log("continuous load %.1f: %s" % (load, out["continuous"]["load_%.1f" % load]))
+        if load == 0.6:
+            check = [r for r in reqs if r.kind == "query" and r.status == "done"][:20]
+    # mix == alone on a sample of served queries
+    same = True
+    for r in check or []:
+        db = dbs[r.db]
+        qd = torch.from_numpy(np.ascontiguousarray(r.Qv)).to("cuda")
+        v, i = B.bolt_scan_topk(db.codes[:r.watermark], db.luts(qd, r.metric), r.metric, r.k)
+        same &= bool(np.array_equal(v.cpu().numpy(), r.vals) and np.array_equal(i.cpu().numpy(), r.idx))
+    out["served_equals_alone"] = same
+    reqs, wall, _ = serve("fifo", 0.0, args.fifo_requests, 3)
+    fsat = len(reqs) / wall
+    out["fifo"]["saturation_req_per_s"] = round(fsat, 2)
+    out["fifo"]["saturation"] = summarize(reqs, wall)
+    reqs, wall, _ = serve("fifo", 0.3 * sat, args.fifo_requests, 13)
+    out["fifo"]["load_0.3_of_continuous"] = summarize(reqs, wall)
+    log("fifo at 0.3 of continuous saturation: %s" % out["fifo"]["load_0.3_of_continuous"])
+    del dbs, ex
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the scan would shard "
+              "by database rows; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1706_10283_amd.bolt as B
+    from paper_1706_10283_amd import workloads as W
+    torch.cuda.set_device(0)
+    parts = set(args.parts.split(","))
+    res = headline(args, torch, B, W)
+    log("headline: %.1f G distances/s, %.3f ms/step" % (res["value"], res["ms_per_step"]))
+    for name, fn in (("amm", run_amm), ("batched", run_batched), ("serving", run_serving)):
+        if name in parts:
+            t0 = time.time()
+            try:
+                res[name] = fn(args, torch, B, W)
+            except Exception as e:   # a failed sub-report is reported, not fatal to the headline
+                res[name] = {"error": repr(e)}
+            log("%s done in %.1fs" % (name, time.time() - t0))
+            torch.cuda.empty_cache()
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -271,6 +271,17 @@ int bolt_learn_quantizer_host(const float *Qt, int64_t nq, int32_t J, int64_t ld
                               int32_t nalpha, float *a, float *offsets, int32_t *alpha_idx);
 
 /*
+ * Kernel timing: with bolt_prof_enable(1), every library kernel launch is
+ * bracketed by HIP events recorded on its own stream (not inside graph
+ * capture).  bolt_prof_read waits for the recorded events and writes
+ * "name=launches:milliseconds;" for every kernel name into names (a HOST
+ * buffer of cap bytes, NUL-terminated, truncated if short); it returns the
+ * full length and, with reset != 0, clears the totals.
+ */
+int bolt_prof_enable(int32_t on);
+int bolt_prof_read(char *names, size_t cap, int32_t reset);
+
+/*
  * Test hooks (not part of the hot path): pin the scan kernel (-1 automatic,
  * 0 plain loop, 1 pair tables for few queries, 2 grouped) and route
  * bolt_scan_topk through the unfused scan-then-select path (on != 0).

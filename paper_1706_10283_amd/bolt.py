@@ -396,3 +396,30 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ kernel timing
+
+_lib.bolt_prof_enable.argtypes = [_I32]
+_lib.bolt_prof_enable.restype = ctypes.c_int
+_lib.bolt_prof_read.argtypes = [ctypes.c_char_p, _SZ, _I32]
+_lib.bolt_prof_read.restype = ctypes.c_int
+
+
+def prof_enable(on: bool = True):
+    """Record HIP events around every library kernel launch (on its stream)."""
+    _lib.bolt_prof_enable(1 if on else 0)
+
+
+def prof_read(reset: bool = True):
+    """{kernel name: (launches, total ms)} of the launches timed so far."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _lib.bolt_prof_read(buf, len(buf), 1 if reset else 0)
+    out = {}
+    for item in buf.value.decode().split(";"):
+        if not item:
+            continue
+        name, rest = item.split("=")
+        n, ms = rest.split(":")
+        out[name] = (int(n), float(ms))
+    return out

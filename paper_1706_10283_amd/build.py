@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libbolt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["errors.cpp", "encode.hip", "luts.hip", "scan.hip", "topk.hip", "fused.hip", "few.hip",
+SOURCES = ["errors.cpp", "prof.cpp", "encode.hip", "luts.hip", "scan.hip", "topk.hip", "fused.hip", "few.hip",
            "batched.hip", "train_host.cpp"]
 
 COMMON_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",

@@ -355,10 +355,16 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
     const int64_t nz = p->n_queries;
     hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, p->counter,
                        p->gthr, nz);
-    hipLaunchKernelGGL(batch_scan_kernel, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs, p->tiles,
-                       (int32_t)p->n_tiles, (int64_t)p->rows_per_tile, p->counter);
-    hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)p->n_queries), dim3(256), 0, s, p->dbs,
-                       p->queries);
+    {
+        bolt::ProfScope prof_("batch_scan", s);
+        hipLaunchKernelGGL(batch_scan_kernel, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs, p->tiles,
+                           (int32_t)p->n_tiles, (int64_t)p->rows_per_tile, p->counter);
+    }
+    {
+        bolt::ProfScope prof_("batch_merge", s);
+        hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)p->n_queries), dim3(256), 0, s, p->dbs,
+                           p->queries);
+    }
     return check_launch("bolt_batch_run");
 }
 

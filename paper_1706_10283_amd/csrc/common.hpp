@@ -48,6 +48,21 @@ inline int check_N(int64_t N, const char *name)
 
 constexpr int kCentroids = 16;  // K = 16 centroids per codebook (4-bit codes)
 
+// Times the launches enqueued during its lifetime on stream s under `name`
+// when timing is enabled (bolt_prof_enable); otherwise does nothing.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    const char *name_;
+    hipStream_t s_;
+    void *start_;
+};
+
 }  // namespace bolt
 
 #define BOLT_TRY(expr)          \

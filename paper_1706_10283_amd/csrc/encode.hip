@@ -184,8 +184,11 @@ void launch_lds(const float *X, int64_t N, int64_t ldx, const float *C, int M, u
                 int vec4, int byte_store, hipStream_t s)
 {
     dim3 grid((unsigned)((N + kRows - 1) / kRows));
-    hipLaunchKernelGGL(encode_lds_kernel<SUB>, grid, dim3(kThreads), 0, s, X, N, ldx, C, M, codes,
-                       vec4, byte_store);
+    {
+        bolt::ProfScope prof_("encode", s);
+        hipLaunchKernelGGL(encode_lds_kernel<SUB>, grid, dim3(kThreads), 0, s, X, N, ldx, C, M, codes,
+                           vec4, byte_store);
+    }
 }
 
 }  // namespace
@@ -215,8 +218,11 @@ extern "C" int bolt_encode(const float *X, int64_t N, int32_t J, int64_t ldx,
     case 32: launch_lds<32>(X, N, ldx, centroids, M, codes, vec4, byte_store, s); break;
     default: {
         const int64_t work = N * (M / 2);
-        hipLaunchKernelGGL(encode_generic_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
-                           s, X, N, ldx, centroids, M, sub, codes);
+        {
+            bolt::ProfScope prof_("encode", s);
+            hipLaunchKernelGGL(encode_generic_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
+                               s, X, N, ldx, centroids, M, sub, codes);
+        }
     }
     }
     return check_launch("bolt_encode");

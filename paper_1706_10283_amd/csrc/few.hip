@@ -106,8 +106,11 @@ void launch_few_scan(const uint8_t *codes, int64_t N, const uint8_t *luts, int n
 {
     const int64_t rpb = bolt::few_rows_per_block(N);
     const dim3 grid((unsigned)((N + rpb - 1) / rpb));
-    hipLaunchKernelGGL((few_scan_kernel<MM, OUT>), grid, dim3(256), few_lds_bytes(MM, nq, false), s,
-                       codes, N, luts, nq, rpb, out, outf, ldo, bias, scale);
+    {
+        bolt::ProfScope prof_("scan_few", s);
+        hipLaunchKernelGGL((few_scan_kernel<MM, OUT>), grid, dim3(256), few_lds_bytes(MM, nq, false), s,
+                           codes, N, luts, nq, rpb, out, outf, ldo, bias, scale);
+    }
 }
 
 }  // namespace
@@ -163,6 +166,7 @@ int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, i
     const int64_t rpb = few_rows_per_block(N);
     const int nq = (int)Q;
     const size_t lds = few_lds_bytes(M, nq, true);
+    bolt::ProfScope prof_("scan_topk_few", s);
     switch (M) {
     case 8:
         hipLaunchKernelGGL(few_scan_topk_kernel<8>, dim3(n_rb), dim3(256), lds, s, codes, N, luts, nq,

@@ -165,8 +165,11 @@ void launch_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, const uin
         return;
     }
     const unsigned grid = (unsigned)(p.n_qb * ((p.n_rb + 7) / 8 * 8));
-    hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes,
-                       N, luts, Q, (uint32_t)k, largest, p.n_rb, p.n_qb, cand, gthr);
+    {
+        bolt::ProfScope prof_("scan_topk_grouped", s);
+        hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes,
+                           N, luts, Q, (uint32_t)k, largest, p.n_rb, p.n_qb, cand, gthr);
+    }
 }
 
 }  // namespace
@@ -207,6 +210,7 @@ int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts,
     }
     const int64_t per_query = (int64_t)p.n_rb * k;
     const uint32_t smax = 255u * (uint32_t)M;
+    bolt::ProfScope prof_("topk_merge", s);
     if (p.n_chunks > 1) {
         hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s,
                            cand, per_query, p.chunk, (uint32_t)k, gthr, 0, (int)largest, smax,

@@ -67,8 +67,11 @@ extern "C" int bolt_build_luts(const float *Qv, int64_t Q, int32_t J, int64_t ld
     if (!Qv || !centroids || (luts_u8 && !offsets))
         return fail(BOLT_ERR_INVALID, "bolt_build_luts: null pointer");
     const int64_t work = Q * M * kCentroids;
-    hipLaunchKernelGGL(luts_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
-                       as_stream(stream), Qv, Q, ldq, centroids, M, J / M, metric, a, offsets,
-                       luts_f32, luts_u8);
+    {
+        bolt::ProfScope prof_("luts", as_stream(stream));
+        hipLaunchKernelGGL(luts_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
+                           as_stream(stream), Qv, Q, ldq, centroids, M, J / M, metric, a, offsets,
+                           luts_f32, luts_u8);
+    }
     return check_launch("bolt_build_luts");
 }

@@ -162,12 +162,14 @@ __global__ __launch_bounds__(256) void scan_generic_kernel(
 
 // ---------------------------------------------------------------- dispatch
 
+// Rows per workgroup: about target_blocks workgroups in all, but at least
+// 2048 rows so that staging the query tables stays a small part of the work.
 int64_t rows_per_block_for(int64_t N, int64_t n_qblocks, int64_t target_blocks)
 {
     int64_t want = (N * n_qblocks + target_blocks - 1) / target_blocks;
     want = (want + 255) / 256 * 256;
-    if (want < 256)
-        want = 256;
+    if (want < 2048)
+        want = 2048;
     return want;
 }
 
@@ -178,8 +180,11 @@ void launch_grouped(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_
     const int64_t qblocks = (Q + 8 * NG - 1) / (8 * NG);
     const int64_t rpb = rows_per_block_for(N, qblocks, 4096);
     dim3 grid((unsigned)((N + rpb - 1) / rpb), (unsigned)qblocks);
-    hipLaunchKernelGGL((scan_grouped_kernel<MM, NG, OUT>), grid, dim3(256), 0, s, codes, N, luts, Q,
-                       rpb, out, outf, ldo, bias, scale);
+    {
+        bolt::ProfScope prof_("scan_grouped", s);
+        hipLaunchKernelGGL((scan_grouped_kernel<MM, NG, OUT>), grid, dim3(256), 0, s, codes, N, luts, Q,
+                           rpb, out, outf, ldo, bias, scale);
+    }
 }
 
 template <OutMode OUT>
@@ -220,8 +225,11 @@ int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, i
         const int64_t qblocks = (Q + qb - 1) / qb;
         const int64_t rpb = rows_per_block_for(N, qblocks, 4096);
         dim3 grid((unsigned)((N + rpb - 1) / rpb), (unsigned)qblocks);
-        hipLaunchKernelGGL(scan_generic_kernel<OUT>, grid, dim3(256), qb * M * 16, s, codes, N, M,
-                           luts, Q, qb, rpb, out, outf, ldo, bias, scale);
+        {
+            bolt::ProfScope prof_("scan_generic", s);
+            hipLaunchKernelGGL(scan_generic_kernel<OUT>, grid, dim3(256), qb * M * 16, s, codes, N, M,
+                               luts, Q, qb, rpb, out, outf, ldo, bias, scale);
+        }
     } else if (kind == 1) {
         return bolt::few_scan<OUT>(codes, N, M, luts, Q, out, outf, ldo, bias, scale, s);
     } else {

@@ -227,8 +227,11 @@ int topk_u16(const uint16_t *d, int64_t Q, int64_t N, int64_t ldd, int k, int la
              uint16_t *vals, int32_t *idx, hipStream_t s)
 {
     const int vec = aligned(d, 16) && (ldd % 8 == 0);
-    hipLaunchKernelGGL(topk_rows_kernel, dim3((unsigned)Q), dim3(kThreads), 0, s, d, N, ldd, k,
-                       largest ? 0xFFFFu : 0u, vals, idx, vec);
+    {
+        bolt::ProfScope prof_("topk_rows", s);
+        hipLaunchKernelGGL(topk_rows_kernel, dim3((unsigned)Q), dim3(kThreads), 0, s, d, N, ldd, k,
+                           largest ? 0xFFFFu : 0u, vals, idx, vec);
+    }
     return check_launch("bolt_topk");
 }
 }  // namespace bolt
