@@ -44,6 +44,46 @@ sys.path.insert(0, ROOT)
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_GBPS = 8000.0
 
+# HBM traffic of the dominant kernel, from two rocprofv3 --pmc runs of this
+# script's headline (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the counter reads for a 1 GiB device-to-device copy in the
+# same runs (FETCH_SIZE 524312.6 KiB for 1048576 KiB read: factor 2.0;
+# WRITE_SIZE 1048576.0 KiB for 1048576 KiB written: factor 1.0).  Valid only
+# for the workload and kernel sources they were taken on: the sources are
+# hashed, and any change reports traffic as null until measured again.
+FETCH_FACTOR = 2.0
+WRITE_FACTOR = 1.0
+TRAFFIC = {
+    "scan_topk_grouped": {
+        "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
+        "fetch_kib": 12728.0,
+        "write_kib": 50239.8,
+        "sources_sha256": "dfac19093c2ae4b95edeaf2468c867887b4834edfec80e2f77c04725d060c4fd",
+    },
+}
+TRAFFIC_SOURCES = {
+    "scan_topk_grouped": ["fused.hip", "tiles.hpp", "topk_device.hpp", "scan_common.hpp"],
+}
+
+
+def sources_sha256(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1706_10283_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel, workload):
+    """Measured HBM bytes per launch, or None if not measured on these sources."""
+    t = TRAFFIC.get(kernel)
+    if not t or t["fetch_kib"] is None or t["workload"] != workload:
+        return None
+    if t["sources_sha256"] != sources_sha256(kernel):
+        return None
+    return 1024.0 * (FETCH_FACTOR * t["fetch_kib"] + WRITE_FACTOR * t["write_kib"])
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -62,11 +102,13 @@ def parse():
     p.add_argument("--n-train", type=int, default=100_000)
     p.add_argument("--parts", default="headline,amm,batched,serving")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-rows", type=int, default=20_000)
+    p.add_argument("--cpu-sample-rows", type=int, default=80_000)
     p.add_argument("--batched-dbs", type=int, default=256)
     p.add_argument("--serving-rows", type=int, default=250_000_000)
     p.add_argument("--serving-requests", type=int, default=300)
     p.add_argument("--fifo-requests", type=int, default=100)
+    p.add_argument("--calib-copy", action="store_true",
+                   help="also run a 1 GiB device-to-device copy (counter calibration for profiles)")
     return p.parse_args()
 
 
@@ -135,6 +177,7 @@ def headline(args, torch, B, W):
     lookups = float(Q) * N * M                      # one table lookup-and-add per (q, n, m)
     achieved = lookups / (dom_ms * 1e-3)
     enc_ms = prof["encode"][1] / prof["encode"][0]
+    traffic = traffic_bytes(dom, {"N": N, "J": J, "M": M, "Q": Q, "k": k})
     res = {
         "metric": "G distances/sec scanned + encode GB/s; p50/p99 latency vs plain per-query scan",
         "value": round(value, 3),
@@ -163,7 +206,9 @@ def headline(args, torch, B, W):
             "unit": "TOP/s",
             "op": "table lookup-and-add (one per query, vector and subspace)",
             "frac": round(achieved / VALU_LANE_OPS, 4),
-            "traffic": None,
+            "traffic": None if traffic is None else round(traffic),
+            "traffic_unit": "HBM bytes per launch (fetch + write)",
+            "algorithmic_bytes": N * M // 2 + Q * M * 16,
         },
     }
     if not args.no_cpu_baseline:
@@ -344,15 +389,17 @@ def run_serving(args, torch, B, W):
         out["continuous"]["load_%.1f" % load] = summarize(reqs, wall)
         log("continuous load %.1f: %s" % (load, out["continuous"]["load_%.1f" % load]))
         if load == 0.6:
+            # served == alone on a sample of served queries, checked before the
+            # next run's inserts rewrite the rows past the initial database
             check = [r for r in reqs if r.kind == "query" and r.status == "done"][:20]
-    # mix == alone on a sample of served queries
-    same = True
-    for r in check or []:
-        db = dbs[r.db]
-        qd = torch.from_numpy(np.ascontiguousarray(r.Qv)).to("cuda")
-        v, i = B.bolt_scan_topk(db.codes[:r.watermark], db.luts(qd, r.metric), r.metric, r.k)
-        same &= bool(np.array_equal(v.cpu().numpy(), r.vals) and np.array_equal(i.cpu().numpy(), r.idx))
-    out["served_equals_alone"] = same
+            same = bool(check)
+            for r in check:
+                db = dbs[r.db]
+                qd = torch.from_numpy(np.ascontiguousarray(r.Qv)).to("cuda")
+                v, i = B.bolt_scan_topk(db.codes[:r.watermark], db.luts(qd, r.metric), r.metric, r.k)
+                same &= bool(np.array_equal(v.cpu().numpy(), r.vals) and np.array_equal(i.cpu().numpy(), r.idx))
+            out["served_equals_alone"] = same
+            out["served_equals_alone_checked"] = len(check)
     reqs, wall, _ = serve("fifo", 0.0, args.fifo_requests, 3)
     fsat = len(reqs) / wall
     out["fifo"]["saturation_req_per_s"] = round(fsat, 2)
@@ -377,6 +424,12 @@ def main():
     parts = set(args.parts.split(","))
     res = headline(args, torch, B, W)
     log("headline: %.1f G distances/s, %.3f ms/step" % (res["value"], res["ms_per_step"]))
+    if args.calib_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     for name, fn in (("amm", run_amm), ("batched", run_batched), ("serving", run_serving)):
         if name in parts:
             t0 = time.time()

@@ -148,7 +148,12 @@ int bolt_topk(const uint16_t *dists, int64_t Q, int64_t N, int64_t ldd, int32_t 
  * result as bolt_scan_* then bolt_topk with largest = (metric == DOT).
  *
  *   metric     BOLT_METRIC_L2 (k smallest) or BOLT_METRIC_DOT (k largest)
- *   ws         device workspace of bolt_scan_topk_ws_bytes(N, M, Q, k) bytes
+ *   ws         device workspace of bolt_scan_topk_ws_bytes(N, M, Q, k) bytes,
+ *              256-byte aligned.  The size assumes codes and luts_u8 are
+ *              16-byte aligned (M in {8, 16, 32, 64} and k <= 256 then take the
+ *              fused path, whose workspace is about Q * N * k / 2048 bytes);
+ *              otherwise the call needs Q * N * 2 bytes for the sum matrix
+ *              and fails with BOLT_ERR_NOMEM, naming the size, if given less.
  */
 size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k);
 int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,

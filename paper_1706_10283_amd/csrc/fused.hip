@@ -176,6 +176,11 @@ void launch_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, const uin
 
 namespace bolt {
 
+bool fused_supported(int64_t N, int M, int64_t Q, int k, bool vec_ok)
+{
+    return plan_fused(N, M, Q, k, vec_ok).ok;
+}
+
 size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
 {
     FusedPlan p = plan_fused(N, M, Q, k, true);

@@ -17,8 +17,10 @@ extern int g_force_scan_kernel;
 int scan_u16(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, uint16_t *out,
              int64_t ldo, hipStream_t s);
 
-// Fused scan + top-k (fused.hip): workspace size (0 if the shape has no fused
-// kernel) and the launch (BOLT_ERR_UNSUPPORTED if it has none).
+// Fused scan + top-k (fused.hip): whether the shape has a fused kernel (vec_ok:
+// codes and tables 16-byte aligned), its workspace size (0 if it has none) and
+// the launch (BOLT_ERR_UNSUPPORTED if it has none).
+bool fused_supported(int64_t N, int M, int64_t Q, int k, bool vec_ok);
 size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k);
 int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
                     bool largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,

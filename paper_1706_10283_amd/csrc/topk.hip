@@ -274,11 +274,19 @@ static size_t unfused_ws_bytes(int64_t N, int64_t Q)
     return round_up((size_t)Q * (size_t)N * sizeof(uint16_t), 256);
 }
 
+// The fused path needs only its candidate buffers; the scan-then-select path
+// (shapes without a fused kernel, unaligned operands, or the test hook) needs
+// the whole [Q][N] sum matrix.
+static size_t scan_topk_need(int64_t N, int32_t M, int64_t Q, int32_t k, bool vec_ok)
+{
+    if (N > 0 && !bolt::g_force_unfused_topk && bolt::fused_supported(N, M, Q, k, vec_ok))
+        return bolt::fused_ws_bytes(N, M, Q, k);
+    return unfused_ws_bytes(N, Q);
+}
+
 extern "C" size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k)
 {
-    const size_t f = bolt::fused_ws_bytes(N, M, Q, k);
-    const size_t u = unfused_ws_bytes(N, Q);
-    return f > u ? f : u;
+    return scan_topk_need(N, M, Q, k, true);
 }
 
 extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
@@ -294,7 +302,8 @@ extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const 
         return BOLT_OK;
     if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
         return fail(BOLT_ERR_INVALID, "bolt_scan_topk: null pointer");
-    const size_t need = bolt_scan_topk_ws_bytes(N, M, Q, k);
+    const bool vec_ok = aligned(codes, 16) && aligned(luts_u8, 16);
+    const size_t need = scan_topk_need(N, M, Q, k, vec_ok);
     if (ws_bytes < need || (need && !ws))
         return fail(BOLT_ERR_NOMEM, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
     if (need && !aligned(ws, 256))

@@ -350,6 +350,7 @@ def summarize(reqs, wall: float):
     return {"requests": len(reqs), "done": sum(r.status == "done" for r in reqs),
             "refused": sum(r.status == "refused" for r in reqs),
             "failed": sum(r.status == "failed" for r in reqs),
+            "refused_reasons": sorted({r.error for r in reqs if r.status == "refused"}),
             "wall_s": round(wall, 4),
             "query_p50_ms": round(pct(q, 50), 3), "query_p99_ms": round(pct(q, 99), 3),
             "insert_p50_ms": round(pct(ins, 50), 3), "insert_p99_ms": round(pct(ins, 99), 3),

@@ -47,7 +47,10 @@ def test_validation_without_gpu(lib):
     assert L.bolt_topk(None, 1, 10, 10, 4096, 0, None, None, None, 0, None) == lib.BOLT_ERR_UNSUPPORTED
     assert L.bolt_scan_l2(None, 10, 8, None, 1, None, 5, None) == lib.BOLT_ERR_INVALID
     assert "ldo" in lib.last_error()
-    assert lib.bolt_scan_topk_ws_bytes(1000, 32, 10, 100) >= 1000 * 10 * 2
+    # M = 12 has no fused kernel: room for the [Q][N] sums
+    assert lib.bolt_scan_topk_ws_bytes(1000, 12, 10, 100) >= 1000 * 10 * 2
+    # M = 32 takes the fused path: candidate buffers only, far below the sums
+    assert 0 < lib.bolt_scan_topk_ws_bytes(10**8, 32, 64, 100) < 10**8 * 64 * 2 // 20
 
 
 def test_train_host_matches_oracle_definition(lib):
