@@ -11,6 +11,13 @@ number of (query, vector) distances produced per second over the whole step
 (both metrics).
 
 Sub-reports on the same line (each its own workload):
+  headline extras   the oracle's CPU time on a sample (cpu_baseline), one
+           query against the same cache-resident database, Recall@1/10/100
+           against exact fp64 search (Sec. 4.5)
+  msweep   the same step at M = 16 and M = 64 (8 and 32 B codes)
+  single_query  one query, top-100, against 2.5e8 rows at M = 16/32/64
+           (4/8/16 GB of codes), cache flushed between calls: latency and
+           the fraction of the HBM roofline
   amm      approximate matrix product, A 200,000 x 256 N(0,1), M = 32,
            B 256 x K for K in {64, 256, 1024}: throughput and accuracy
            against the exact fp32 product (and the fp32 GEMM's time)
@@ -100,7 +107,7 @@ def parse():
     p.add_argument("--Q", type=int, default=1000)
     p.add_argument("--k", type=int, default=100)
     p.add_argument("--n-train", type=int, default=100_000)
-    p.add_argument("--parts", default="headline,amm,batched,serving")
+    p.add_argument("--parts", default="headline,msweep,single_query,amm,batched,serving")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-rows", type=int, default=80_000)
     p.add_argument("--batched-dbs", type=int, default=256)
@@ -127,11 +134,17 @@ def event_ms(torch, fn, reps):
 
 # ------------------------------------------------------------------ headline
 
-def headline(args, torch, B, W):
+def headline(args, torch, B, W, M=None, steps=None, warmup=None, extras=True):
+    """One pass of the hot path per step (encode, both tables, scan + top-k for
+    both metrics); with extras, also the oracle's CPU time, the single-query
+    latency on the same (cache-resident) database and Recall@R."""
     import synth
     import synth.device as sdev
     dev = "cuda"
-    N, J, M, Q, k = args.N, args.J, args.M, args.Q, args.k
+    N, J, Q, k = args.N, args.J, args.Q, args.k
+    M = M or args.M
+    steps = steps or args.steps
+    warmup = args.warmup if warmup is None else warmup
     mix = synth.seed_for(2, 0)
     t0 = time.time()
     X = sdev.gmm_rows(mix, synth.seed_for(2, 1), 0, N, J)
@@ -155,19 +168,19 @@ def headline(args, torch, B, W):
         for m in ("l2", "dot"):
             B.bolt_scan_topk(codes, luts[m], m, k, vals=vals[m], idx=idx[m], ws=ws)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     B.prof_read(reset=True)
     B.prof_enable(True)
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     B.prof_enable(False)
     prof = B.prof_read(reset=True)
-    ms_per_step = 1e3 * t_total / args.steps
+    ms_per_step = 1e3 * t_total / steps
     kern = {n: {"launches": c, "avg_ms": round(ms / c, 5)} for n, (c, ms) in prof.items()}
     dists = 2.0 * Q * N
     value = dists / (ms_per_step * 1e-3) / 1e9
@@ -183,8 +196,8 @@ def headline(args, torch, B, W):
         "value": round(value, 3),
         "unit": "G distances/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
@@ -211,10 +224,106 @@ def headline(args, torch, B, W):
             "algorithmic_bytes": N * M // 2 + Q * M * 16,
         },
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args, C, quant, Qd.cpu().numpy(), mix)
+    if extras:
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = cpu_baseline(args, C, quant, Qd.cpu().numpy(), mix)
+        # one query against the same database (16 MB of codes: cache-resident)
+        one = {m: luts[m][:1].contiguous() for m in ("l2", "dot")}
+        res["single_query_cache_resident_ms"] = {
+            m: round(event_ms(torch, lambda: B.bolt_scan_topk(codes, one[m], m, k), 20), 4)
+            for m in ("l2", "dot")}
+        res["recall"] = recall(torch, X, Qd, idx)
     del X, codes, ws
     return res
+
+
+def recall(torch, X, Qd, idx):
+    """Recall@R (Sec. 4.5): the fraction of queries whose exact nearest
+    neighbour (fp64 squared L2; largest fp64 dot product for dot) is among
+    the first R results of the scan."""
+    X64 = X.double()
+    xx = (X64 * X64).sum(1)
+    true = {"l2": [], "dot": []}
+    for q0 in range(0, Qd.shape[0], 100):
+        dots = Qd[q0:q0 + 100].double() @ X64.t()
+        true["dot"].append(dots.argmax(1))
+        true["l2"].append((xx[None, :] - 2.0 * dots).argmin(1))
+    out = {}
+    for m in ("l2", "dot"):
+        t = torch.cat(true[m]).to(torch.int64)
+        got = idx[m].to(torch.int64)
+        out[m] = {"R%d" % R: round((got[:, :R] == t[:, None]).any(1).double().mean().item(), 4)
+                  for R in (1, 10, 100)}
+    del X64
+    return out
+
+
+def run_msweep(args, torch, B, W):
+    """The single-database step at the other code sizes (M = 16 and 64)."""
+    out = {}
+    for M in (16, 64):
+        r = headline(args, torch, B, W, M=M, steps=10, warmup=2, extras=False)
+        out["M%d" % M] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
+                          "encode_GBps": r["encode_GBps"],
+                          "scan_topk_G_distances_per_s": r["scan_topk_G_distances_per_s"],
+                          "kernels": r["kernels"], "lookup_frac": r["roofline"]["frac"]}
+        log("M=%d: %.1f G distances/s" % (M, r["value"]))
+    return out
+
+
+def run_single_query(args, torch, B, W):
+    """One query, top-100, against a 2.5e8-row database (4 / 8 / 16 GB of
+    codes at M = 16 / 32 / 64, far beyond the 256 MB last-level cache), with
+    a 1 GB write between calls so no call starts with codes in cache.  The
+    HBM roofline counts the code bytes once per call."""
+    import synth
+    import synth.device as sdev
+    N, J, k, reps = args.serving_rows, 128, args.k, 10
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    out = {"workload": "N=%.3g x J=%d mixture rows, 1 query, top-%d, cache flushed between calls" % (N, J, k)}
+    for M in (16, 32, 64):
+        mix = synth.seed_for(5, 0) + 7 * M
+        C, quant = W.train(mix, mix + 3, mix + 4, mix + 5, J, M, n_train=20_000, iters=10)
+        db = W.build_db(mix, mix + 1, N, J, M, C, quant)
+        qv = sdev.gmm_rows(mix, mix + 2, 0, 1, J)
+        row = {}
+        for metric in ("l2", "dot"):
+            luts = db.luts(qv, metric)
+            codes = db.codes[:N]
+            B.bolt_scan_topk(codes, luts, metric, k)
+            ms = []
+            B.prof_read(reset=True)
+            B.prof_enable(True)
+            for _ in range(reps):
+                flush.fill_(1.0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                B.bolt_scan_topk(codes, luts, metric, k)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            B.prof_enable(False)
+            prof = B.prof_read(reset=True)
+            med = float(np.median(ms))
+            scan_name = "scan_topk_few" if "scan_topk_few" in prof else "scan_topk_grouped"
+            scan_ms = prof[scan_name][1] / prof[scan_name][0]
+            nbytes = N * M // 2
+            row[metric] = {"ms_per_query": round(med, 4),
+                           "G_distances_per_s": round(N / (med * 1e-3) / 1e9, 1),
+                           "GBps": round(nbytes / (med * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(nbytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                           "scan_kernel": scan_name,
+                           "scan_kernel_ms": round(scan_ms, 4),
+                           "scan_kernel_hbm_frac": round(nbytes / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                           "kernels": {n: round(t / c, 4) for n, (c, t) in prof.items()}}
+            log("single query M=%d %s: %.3f ms, %.0f GB/s (kernel %.0f GB/s)"
+                % (M, metric, med, nbytes / (med * 1e-3) / 1e9, nbytes / (scan_ms * 1e-3) / 1e9))
+        out["M%d" % M] = row
+        del db, codes
+        torch.cuda.empty_cache()
+    del flush
+    return out
 
 
 def cpu_baseline(args, C, quant, Qv, mix):
@@ -430,7 +539,8 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    for name, fn in (("amm", run_amm), ("batched", run_batched), ("serving", run_serving)):
+    for name, fn in (("msweep", run_msweep), ("single_query", run_single_query), ("amm", run_amm),
+                     ("batched", run_batched), ("serving", run_serving)):
         if name in parts:
             t0 = time.time()
             try:
