@@ -86,7 +86,7 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     job.k = (uint32_t)db.k;
     job.largest = db.largest;
     if (t.kind == 1) {
-        bolt::few_tile<MM>(job, lds);
+        bolt::few_tile<MM, false>(job, lds);
     } else {
         constexpr int NG = MM <= 32 ? 2 : 1;
         bolt::grouped_tile<MM, NG>(job, *reinterpret_cast<bolt::GroupedLds<MM, NG> *>(lds));

@@ -10,6 +10,8 @@
 // lane in flight, and the lookups of the R rows are interleaved so that the
 // reads of different rows overlap.  LDS is sized by the actual query count,
 // which keeps occupancy high for a single query.
+#include <atomic>
+
 #include "common.hpp"
 #include "scan_common.hpp"
 #include "tiles.hpp"
@@ -19,17 +21,18 @@ namespace {
 using bolt::load_row;
 using bolt::OutMode;
 
-constexpr int kPass = bolt::kFewPass;        // rows per pass
-constexpr int kFewRowsMax = bolt::kTileRowsMax;
-
 using bolt::build_pair_tables;
-using bolt::copy_rows4;
-using bolt::load_rows4;
+using bolt::local_key;
+using bolt::PruneResult;
+using bolt::read_bound;
+using bolt::copy_rows;
+using bolt::load_rows;
+using bolt::load_rows_clamped;
 using bolt::pair_sums;
 
 // ------------------------------------------------------------------ plain
 
-template <int MM, OutMode OUT>
+template <int MM, OutMode OUT, bool ONE>
 __global__ __launch_bounds__(256) void few_scan_kernel(const uint8_t *__restrict__ codes, int64_t N,
                                                        const uint8_t *__restrict__ luts, int nq,
                                                        int64_t rows_per_block,
@@ -37,22 +40,30 @@ __global__ __launch_bounds__(256) void few_scan_kernel(const uint8_t *__restrict
                                                        float *__restrict__ outf, int64_t ldo,
                                                        float bias, float scale)
 {
-    extern __shared__ __attribute__((aligned(16))) uint16_t pt[];   // [nq][MM/2][256]
+    // one query: static tables at a fixed LDS address (table offsets fold
+    // into the reads); several: dynamic [nq][MM/2][256]
+    extern __shared__ __attribute__((aligned(16))) uint16_t pt_dyn[];
+    __shared__ __attribute__((aligned(16))) uint16_t pt_one[ONE ? (MM / 2) * 256 : 1];
+    uint16_t *pt = ONE ? pt_one : pt_dyn;
+    if (ONE)
+        nq = 1;
     build_pair_tables<MM>(luts, nq, pt);
     __syncthreads();
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = (r0 + rows_per_block) < N ? (r0 + rows_per_block) : N;
-    uint32_t cw[bolt::kFewR][MM / 8], nx[bolt::kFewR][MM / 8];
-    load_rows4<MM>(codes, r0, r1, nx);
-    for (int64_t base = r0; base < r1; base += kPass) {
-        copy_rows4<MM>(nx, cw);
-        if (base + kPass < r1)   // next pass in flight while this one is computed
-            load_rows4<MM>(codes, base + kPass, r1, nx);
+    constexpr int R = bolt::few_r(MM);
+    constexpr int PASS = bolt::few_pass(MM);
+    uint32_t cw[R][MM / 8], nx[R][MM / 8];
+    load_rows<MM, R>(codes, r0, r1, nx);
+    for (int64_t base = r0; base < r1; base += PASS) {
+        copy_rows<MM, R>(nx, cw);
+        if (base + PASS < r1)   // next pass in flight while this one is computed
+            load_rows<MM, R>(codes, base + PASS, r1, nx);
         for (int q = 0; q < nq; ++q) {
-            uint32_t s[bolt::kFewR];
-            pair_sums<MM>(pt + q * (MM / 2) * 256, cw, s);
+            uint32_t s[R];
+            pair_sums<MM, R, ONE>(reinterpret_cast<const char *>(pt + q * (MM / 2) * 256), cw, s);
 #pragma unroll
-            for (int r = 0; r < bolt::kFewR; ++r) {
+            for (int r = 0; r < R; ++r) {
                 const int64_t n = base + threadIdx.x + 256 * r;
                 if (n < r1) {
                     if (OUT == OutMode::U16) {
@@ -92,7 +103,82 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     job.nq = nq;
     job.k = k;
     job.largest = largest;
-    bolt::few_tile<MM>(job, few_lds);
+    bolt::few_tile<MM, false>(job, few_lds);
+}
+
+// One query (the HBM-bound case): one workgroup per tile of tile_rows rows;
+// the many small tiles let the dispatcher balance the load.  The tables are
+// static LDS at a fixed address, so their offsets fold into the reads; rows
+// are loaded with a uniform base and 32-bit lane offsets, unconditionally,
+// so the next pass stays in flight while this one is computed.  Each tile
+// writes its exact local top-k to cand[tile][k].
+template <int MM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void one_scan_topk_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k,
+    int largest, int64_t tile_rows, uint64_t *__restrict__ cand, uint32_t *__restrict__ gthr)
+{
+    constexpr int R = bolt::few_r(MM);
+    constexpr int PASS = bolt::few_pass(MM);
+    constexpr int CAP = bolt::few_cap(MM);
+    constexpr uint32_t SMAX = 255u * MM;
+    __shared__ __attribute__((aligned(16))) uint16_t pt[(MM / 2) * 256];
+    __shared__ __attribute__((aligned(16))) uint32_t buf[CAP];
+    __shared__ uint32_t s_cnt, s_bnd;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t r0 = tile * tile_rows;
+    const int64_t r1 = (r0 + tile_rows) < N ? (r0 + tile_rows) : N;
+    uint32_t cw[R][MM / 8], nx[R][MM / 8];
+    load_rows_clamped<MM, R>(codes, r0, r1, nx);
+    build_pair_tables<MM>(luts, 1, pt, reinterpret_cast<uint8_t *>(buf));
+    if (tid == 0) {
+        s_cnt = 0;
+        s_bnd = read_bound(gthr) + 1u;
+    }
+    __syncthreads();
+    int pass = 0;
+    for (int64_t base = r0; base < r1; base += PASS, ++pass) {
+        copy_rows<MM, R>(nx, cw);
+        if (base + PASS < r1)
+            load_rows_clamped<MM, R>(codes, base + PASS, r1, nx);
+        uint32_t s[R];
+        pair_sums<MM, R, true>(reinterpret_cast<const char *>(pt), cw, s);
+        const uint32_t bq = s_bnd;
+        const uint32_t loc = (uint32_t)(base - r0) + (uint32_t)tid;
+        const uint32_t lim = (uint32_t)((r1 - base) < PASS ? (r1 - base) : PASS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t d = largest ? SMAX - s[r] : s[r];
+            if (d < bq && (uint32_t)tid + 256u * r < lim) {
+                const uint32_t pos = atomicAdd(&s_cnt, 1u);
+                buf[pos] = local_key(d, loc + 256u * r);
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const uint32_t c = s_cnt;
+            uint32_t nb = 0xFFFFFFFFu;
+            if (c > CAP - PASS) {
+                PruneResult pr = bolt::prune_local_lds<CAP>(buf, c, k, false);
+                if (pr.count > CAP - PASS)
+                    pr = bolt::prune_local_lds<CAP>(buf, pr.count, k, true);
+                if (lane == 0) {
+                    s_cnt = pr.count;
+                    bolt::publish(gthr, pr.T, s_bnd);
+                }
+                nb = pr.T;
+            }
+            if (lane == 0 && (nb != 0xFFFFFFFFu || (pass & 7) == 7)) {
+                uint32_t b = s_bnd;
+                b = nb < b ? nb : b;
+                const uint32_t gb = read_bound(gthr) + 1u;
+                s_bnd = gb < b ? gb : b;
+            }
+        }
+        __syncthreads();
+    }
+    if (wave == 0)
+        bolt::write_local_topk<CAP, true>(buf, s_cnt, k, r0, cand + tile * k, gthr, s_bnd);
 }
 
 size_t few_lds_bytes(int M, int nq, bool fused)
@@ -104,13 +190,34 @@ template <int MM, OutMode OUT>
 void launch_few_scan(const uint8_t *codes, int64_t N, const uint8_t *luts, int nq, uint16_t *out,
                      float *outf, int64_t ldo, float bias, float scale, hipStream_t s)
 {
-    const int64_t rpb = bolt::few_rows_per_block(N);
+    const int64_t rpb = bolt::few_rows_per_block(N, MM, nq);
     const dim3 grid((unsigned)((N + rpb - 1) / rpb));
-    {
-        bolt::ProfScope prof_("scan_few", s);
-        hipLaunchKernelGGL((few_scan_kernel<MM, OUT>), grid, dim3(256), few_lds_bytes(MM, nq, false), s,
-                           codes, N, luts, nq, rpb, out, outf, ldo, bias, scale);
-    }
+    const size_t lds = few_lds_bytes(MM, nq, false);
+    bolt::ProfScope prof_("scan_few", s);
+    if (nq == 1)
+        hipLaunchKernelGGL((few_scan_kernel<MM, OUT, true>), grid, dim3(256), 0, s, codes, N, luts, nq, rpb,
+                           out, outf, ldo, bias, scale);
+    else
+        hipLaunchKernelGGL((few_scan_kernel<MM, OUT, false>), grid, dim3(256), lds, s, codes, N, luts, nq, rpb,
+                           out, outf, ldo, bias, scale);
+}
+
+template <int MM>
+void launch_few_scan_topk(const uint8_t *codes, int64_t N, const uint8_t *luts, int nq, int k, bool largest,
+                          int64_t rpb, int n_rb, uint64_t *cand, uint32_t *gthr, hipStream_t s)
+{
+    if (nq == 1)
+        hipLaunchKernelGGL(one_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), 0, s, codes, N, luts, (uint32_t)k,
+                           (int)largest, rpb, cand, gthr);
+    else
+        hipLaunchKernelGGL(few_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), few_lds_bytes(MM, nq, true), s,
+                           codes, N, luts, nq, (uint32_t)k, (int)largest, rpb, n_rb, cand, gthr);
+}
+
+template <int MM>
+hipError_t few_occupancy(int *per_cu, int nq, size_t lds)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, few_scan_topk_kernel<MM>, 256, lds);
 }
 
 }  // namespace
@@ -144,18 +251,66 @@ template int few_scan<OutMode::F32>(const uint8_t *, int64_t, int, const uint8_t
 template int few_scan<OutMode::F32T>(const uint8_t *, int64_t, int, const uint8_t *, int64_t,
                                      uint16_t *, float *, int64_t, float, float, hipStream_t);
 
-// Rows per workgroup: enough workgroups to fill the GPU (about 4 per CU),
-// at most 65536 rows (16-bit local row indices), a multiple of one pass.
 size_t few_fused_lds_bytes(int M, int nq) { return few_lds_bytes(M, nq, true); }
 
-int64_t few_rows_per_block(int64_t N)
+// Workgroups of the fused few-query kernel resident on the current device
+// (occupancy per CU times CUs), cached per (device, M, nq).
+static int few_slots(int M, int nq)
 {
-    int64_t r = (N + 1023) / 1024;
-    r = (r + kPass - 1) / kPass * kPass;
-    if (r < 4 * kPass)
-        r = 4 * kPass;
-    if (r > kFewRowsMax)
-        r = kFewRowsMax;
+    static std::atomic<int> cache[16][4][8];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16)
+        dev = 0;
+    const int mi = M == 8 ? 0 : M == 16 ? 1 : M == 32 ? 2 : 3;
+    const int qi = nq < 1 ? 1 : nq > 7 ? 7 : nq;
+    int v = cache[dev][mi][qi].load(std::memory_order_relaxed);
+    if (v > 0)
+        return v;
+    const size_t lds = few_lds_bytes(M, qi, true);
+    int per_cu = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (M) {
+    case 8: e = few_occupancy<8>(&per_cu, qi, lds); break;
+    case 16: e = few_occupancy<16>(&per_cu, qi, lds); break;
+    case 32: e = few_occupancy<32>(&per_cu, qi, lds); break;
+    case 64: e = few_occupancy<64>(&per_cu, qi, lds); break;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    (void)hipGetLastError();
+    if (e != hipSuccess || per_cu < 1)
+        return cus;   // not cached: no device to ask
+    v = per_cu * cus;
+    cache[dev][mi][qi].store(v, std::memory_order_relaxed);
+    return v;
+}
+
+// Rows per workgroup.  Several queries: equal blocks, as many as whole
+// rounds of resident workgroups need (so no round runs partly empty).  One
+// query: tiles of at most 32768 rows, so that the last round is short and a
+// small database still spreads over 2048 workgroups.  Always at most 65536
+// rows (16-bit local row indices), at least two passes, a multiple of one
+// pass.
+int64_t few_rows_per_block(int64_t N, int M, int nq)
+{
+    const int64_t pass = bolt::few_pass(M);
+    int64_t r;
+    if (nq == 1) {
+        r = (N + 2047) / 2048;
+        if (r > 32768)
+            r = 32768;
+    } else {
+        const int64_t slots = few_slots(M, nq);
+        const int64_t per_round = slots * (int64_t)bolt::kTileRowsMax;
+        const int64_t rounds = N > 0 ? (N + per_round - 1) / per_round : 1;
+        r = (N + slots * rounds - 1) / (slots * rounds);
+    }
+    r = (r + pass - 1) / pass * pass;
+    if (r < 2 * pass)
+        r = 2 * pass;
+    if (r > bolt::kTileRowsMax)
+        r = bolt::kTileRowsMax;
     return r;
 }
 
@@ -163,27 +318,14 @@ int64_t few_rows_per_block(int64_t N)
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
                   bool largest, int n_rb, uint64_t *cand, uint32_t *gthr, hipStream_t s)
 {
-    const int64_t rpb = few_rows_per_block(N);
     const int nq = (int)Q;
-    const size_t lds = few_lds_bytes(M, nq, true);
+    const int64_t rpb = few_rows_per_block(N, M, nq);
     bolt::ProfScope prof_("scan_topk_few", s);
     switch (M) {
-    case 8:
-        hipLaunchKernelGGL(few_scan_topk_kernel<8>, dim3(n_rb), dim3(256), lds, s, codes, N, luts, nq,
-                           (uint32_t)k, (int)largest, rpb, n_rb, cand, gthr);
-        break;
-    case 16:
-        hipLaunchKernelGGL(few_scan_topk_kernel<16>, dim3(n_rb), dim3(256), lds, s, codes, N, luts, nq,
-                           (uint32_t)k, (int)largest, rpb, n_rb, cand, gthr);
-        break;
-    case 32:
-        hipLaunchKernelGGL(few_scan_topk_kernel<32>, dim3(n_rb), dim3(256), lds, s, codes, N, luts, nq,
-                           (uint32_t)k, (int)largest, rpb, n_rb, cand, gthr);
-        break;
-    case 64:
-        hipLaunchKernelGGL(few_scan_topk_kernel<64>, dim3(n_rb), dim3(256), lds, s, codes, N, luts, nq,
-                           (uint32_t)k, (int)largest, rpb, n_rb, cand, gthr);
-        break;
+    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
+    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
+    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
+    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
     default: return fail(BOLT_ERR_UNSUPPORTED, "few-query scan takes M in {8, 16, 32, 64}");
     }
     return BOLT_OK;

@@ -71,31 +71,179 @@ __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
 
 // ------------------------------------------------------------------ merge
 
-// One workgroup per (query, chunk of a query's candidate keys).  Keys with
-// d above the query's final published bound cannot be in its top-k and are
-// skipped.  final_out = 0: the chunk's exact k smallest keys go to dst[q][chunk][k]
-// (unsorted, ~0 padded); final_out = 1 (one chunk): sorted values and rows.
+// The first histogram bin at which the running count of candidate keys
+// reaches k; its upper edge bounds the query's k-th smallest d (that many
+// distinct rows have d at or below it).  One wave; returns `bound` lowered to
+// that edge (unchanged if fewer than k keys were counted).
+__device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int shift, uint32_t bound)
+{
+    constexpr int PER = bolt::kHistBins / 64;
+    const int lane = threadIdx.x & 63;
+    const uint4 *h = reinterpret_cast<const uint4 *>(hq + lane * PER);
+    uint32_t b[PER];
+#pragma unroll
+    for (int v = 0; v < PER / 4; ++v) {
+        const uint4 t = h[v];
+        b[4 * v + 0] = t.x;
+        b[4 * v + 1] = t.y;
+        b[4 * v + 2] = t.z;
+        b[4 * v + 3] = t.w;
+    }
+    uint32_t own = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        own += b[i];
+    uint32_t inc = own;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o)
+            inc += t;
+    }
+    const uint64_t hit = __ballot(inc >= k);
+    if (hit == 0)
+        return bound;
+    const int first = (int)__builtin_ctzll(hit);
+    int bin = lane * PER + PER - 1;
+    uint32_t run = inc - own;
+    for (int i = 0; i < PER; ++i) {
+        run += b[i];
+        if (run >= k) {
+            bin = lane * PER + i;
+            break;
+        }
+    }
+    const uint32_t edge = (((uint32_t)__shfl(bin, first) + 1u) << shift) - 1u;
+    return edge < bound ? edge : bound;
+}
+
+// Merge, level 1: one workgroup per (query, chunk of the query's candidate
+// keys).  Keys with d above the query's final bound cannot be in its top-k
+// and are skipped.  With one chunk the workgroup writes the sorted values and
+// rows; with several, the chunk's exact k smallest survivors go to its slot
+// dst[q][chunk][k] and their number to dst_cnt[q][chunk].  No atomics: the
+// slots are fixed.
 __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restrict__ cand,
-                                                         int64_t per_query, int64_t chunk,
-                                                         uint32_t k, const uint32_t *__restrict__ gthr,
-                                                         int final_out, int largest, uint32_t smax,
-                                                         uint64_t *__restrict__ dst,
+                                                         int64_t per_query, int64_t chunk, uint32_t k,
+                                                         uint32_t *__restrict__ gthr,
+                                                         const uint32_t *__restrict__ hist, int shift,
+                                                         int largest, uint32_t smax, uint64_t *__restrict__ dst,
+                                                         uint32_t *__restrict__ dst_cnt,
                                                          uint16_t *__restrict__ vals,
                                                          int32_t *__restrict__ idx)
 {
+    __shared__ bolt::MergeLds L;
     const int64_t q = blockIdx.x;
     const int64_t c_lo = (int64_t)blockIdx.y * chunk;
     const int64_t c_hi = (c_lo + chunk) < per_query ? (c_lo + chunk) : per_query;
-    uint64_t *out = final_out ? nullptr : dst + (q * gridDim.y + blockIdx.y) * (int64_t)k;
-    bolt::merge_keys(cand + q * per_query, c_lo, c_hi, k, gthr[q], out, largest, smax,
-                     vals + q * k, idx + q * k);
+    if (threadIdx.x < 64) {
+        const uint32_t b = hist_bound(hist + q * bolt::kHistBins, k, shift, gthr[q]);
+        if (threadIdx.x == 0) {
+            L.misc = b;
+            // every workgroup of the query stores the same value (for level 2)
+            if (blockIdx.y == 0)
+                gthr[q] = b;
+        }
+    }
+    __syncthreads();
+    const uint32_t n = bolt::merge_collect(L, cand + q * per_query, c_lo, c_hi, k, L.misc);
+    if (gridDim.y == 1) {
+        bolt::merge_emit(L, n, k, largest, smax, vals + q * k, idx + q * k);
+        return;
+    }
+    const int64_t slot = q * gridDim.y + blockIdx.y;
+    for (uint32_t r = threadIdx.x; r < n; r += 256)
+        dst[slot * k + r] = L.mb[r];
+    if (threadIdx.x == 0)
+        dst_cnt[slot] = n;
 }
 
-__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v)
+// Merge, level 2: one workgroup per query gathers the level-1 survivors
+// (only the filled part of each slot) and writes the sorted result.
+__global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__restrict__ src,
+                                                          const uint32_t *__restrict__ src_cnt, int n_chunks,
+                                                          uint32_t k, const uint32_t *__restrict__ gthr,
+                                                          int largest, uint32_t smax,
+                                                          uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    __shared__ bolt::MergeLds L;
+    const int64_t q = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        L.mcnt = 0;
+        L.mbound = ((uint64_t)gthr[q] + 1u) << 32;
+    }
+    __syncthreads();
+    const uint64_t *sq = src + q * (int64_t)n_chunks * k;
+    const uint32_t *cq = src_cnt + q * (int64_t)n_chunks;
+    // each thread walks its chunks; a full buffer is pruned between rounds
+    for (int c0 = 0; c0 < n_chunks; c0 += 256) {
+        const int c = c0 + tid;
+        const uint32_t nc = c < n_chunks ? cq[c] : 0u;
+        uint32_t j = 0;
+        for (;;) {
+            const uint64_t bnd = L.mbound;
+            // at most 4 keys per thread per round keep the buffer within bounds
+            for (int e = 0; e < 4 && j < nc; ++e, ++j) {
+                const uint64_t key = sq[(int64_t)c * k + j];
+                if (key < bnd) {
+                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                    L.mb[pos] = key;
+                }
+            }
+            const int more = __syncthreads_or(j < nc);
+            if (tid < 64 && L.mcnt > bolt::kMergeCap - 256 * 4) {
+                const uint64_t kth = bolt::prune_u64<bolt::kMergeCap>(L.mb, L.mcnt, k);
+                if (tid == 0) {
+                    L.mcnt = k;
+                    L.mbound = kth + 1;
+                }
+            }
+            __syncthreads();
+            if (!more)
+                break;
+        }
+    }
+    uint32_t n = L.mcnt;
+    if (tid < 64 && n > k)
+        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
+    __syncthreads();
+    bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
+}
+
+// Bounds start open (65535: every d passes) and histograms empty.
+__global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, int64_t n_hist)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n)
-        p[i] = v;
+    if (i < Q)
+        gthr[i] = 0xFFFFu;
+    if (i < n_hist)
+        hist[i] = 0;
+}
+
+// Histogram of the d values of the candidate keys (padding ~0 skipped), one
+// workgroup per (query, chunk): counted in LDS, nonzero bins added to the
+// query's global histogram.
+__global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restrict__ cand, int64_t per_query,
+                                                        int64_t chunk, int shift, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[bolt::kHistBins];
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+        h[i] = 0;
+    __syncthreads();
+    const int64_t q = blockIdx.x;
+    const int64_t lo = (int64_t)blockIdx.y * chunk;
+    const int64_t hi = (lo + chunk) < per_query ? (lo + chunk) : per_query;
+    const uint64_t *c = cand + q * per_query;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const uint64_t key = c[i];
+        if (key != ~0ull)
+            atomicAdd(&h[(uint32_t)(key >> 32) >> shift], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+        if (h[i])
+            atomicAdd(&hist[q * bolt::kHistBins + i], h[i]);
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -116,7 +264,7 @@ struct FusedPlan {
     int kind = 0;        // 1 few-query, 2 grouped
     int n_rb = 0, n_qb = 0, qb_size = 0, n_chunks = 1;
     int64_t chunk = 0;
-    size_t cand_bytes = 0, gthr_bytes = 0, level2_bytes = 0;
+    size_t cand_bytes = 0, gthr_bytes = 0, hist_bytes = 0, level2_bytes = 0;
 };
 
 FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
@@ -126,7 +274,7 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
     if (!tuned_M || !vec_ok || k > 256 || N <= 0 || Q <= 0)
         return p;
     if (Q < bolt::kSmallQ && bolt::few_fused_lds_bytes(M, (int)Q) <= 160 * 1024) {
-        const int64_t rpb = bolt::few_rows_per_block(N);
+        const int64_t rpb = bolt::few_rows_per_block(N, M, (int)Q);
         p.n_rb = (int)((N + rpb - 1) / rpb);
         p.kind = 1;
         p.n_qb = 1;
@@ -142,6 +290,7 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
     }
     p.cand_bytes = align256((size_t)Q * p.n_rb * k * sizeof(uint64_t));
     p.gthr_bytes = align256((size_t)Q * sizeof(uint32_t));
+    p.hist_bytes = align256((size_t)Q * bolt::kHistBins * sizeof(uint32_t));
     const int64_t per_query = (int64_t)p.n_rb * k;
     // first-level chunks: enough workgroups to fill the GPU, 2048..16384 keys each
     int64_t chunk = per_query * Q / 512;
@@ -149,7 +298,9 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
     chunk = (chunk + 1023) / 1024 * 1024;
     p.chunk = chunk;
     p.n_chunks = per_query > 2 * chunk ? (int)((per_query + chunk - 1) / chunk) : 1;
-    p.level2_bytes = p.n_chunks > 1 ? align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)) : 0;
+    p.level2_bytes = p.n_chunks > 1 ? align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)) +
+                                          align256((size_t)Q * p.n_chunks * sizeof(uint32_t))
+                                    : 0;
     if (p.n_chunks > 65535)
         return p;
     p.ok = true;
@@ -186,7 +337,7 @@ size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
     FusedPlan p = plan_fused(N, M, Q, k, true);
     if (!p.ok)
         return 0;
-    return p.cand_bytes + p.gthr_bytes + p.level2_bytes;
+    return p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
 }
 
 // Fused scan + top-k; returns BOLT_ERR_UNSUPPORTED when the shape has no fused kernel.
@@ -198,35 +349,41 @@ int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts,
     FusedPlan p = plan_fused(N, M, Q, k, vec_ok);
     if (!p.ok)
         return BOLT_ERR_UNSUPPORTED;
-    const size_t need = p.cand_bytes + p.gthr_bytes + p.level2_bytes;
+    const size_t need = p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
     if (ws_bytes < need || !aligned(ws, 256))
         return fail(BOLT_ERR_NOMEM, "fused scan+top-k needs %zu workspace bytes", need);
-    uint64_t *level2 = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(ws) + p.cand_bytes +
-                                                    p.gthr_bytes);
-    uint64_t *cand = reinterpret_cast<uint64_t *>(ws);
-    uint32_t *gthr = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(ws) + p.cand_bytes);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, gthr, Q,
-                       0xFFFFu);
+    char *w = reinterpret_cast<char *>(ws);
+    uint64_t *cand = reinterpret_cast<uint64_t *>(w);
+    uint32_t *gthr = reinterpret_cast<uint32_t *>(w + p.cand_bytes);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w + p.cand_bytes + p.gthr_bytes);
+    uint64_t *level2 = reinterpret_cast<uint64_t *>(w + p.cand_bytes + p.gthr_bytes + p.hist_bytes);
+    uint32_t *level2_cnt = reinterpret_cast<uint32_t *>(
+        w + p.cand_bytes + p.gthr_bytes + p.hist_bytes + align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)));
+    const int64_t n_hist = Q * bolt::kHistBins;
+    hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
+                       hist, n_hist);
     switch (M) {
     case 8: launch_fused<8>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
     case 16: launch_fused<16>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
     case 32: launch_fused<32>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
     case 64: launch_fused<64>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
     }
+    {
+        bolt::ProfScope prof_("cand_hist", s);
+        const int64_t per_query = (int64_t)p.n_rb * k;
+        const int64_t hchunk = 4096;
+        hipLaunchKernelGGL(cand_hist_kernel, dim3((unsigned)Q, (unsigned)((per_query + hchunk - 1) / hchunk)),
+                           dim3(256), 0, s, cand, per_query, hchunk, bolt::hist_shift(M), hist);
+    }
     const int64_t per_query = (int64_t)p.n_rb * k;
     const uint32_t smax = 255u * (uint32_t)M;
     bolt::ProfScope prof_("topk_merge", s);
-    if (p.n_chunks > 1) {
-        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s,
-                           cand, per_query, p.chunk, (uint32_t)k, gthr, 0, (int)largest, smax,
-                           level2, vals, idx);
-        const int64_t per2 = (int64_t)p.n_chunks * k;
-        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, 1), dim3(256), 0, s, level2, per2, per2,
-                           (uint32_t)k, gthr, 1, (int)largest, smax, nullptr, vals, idx);
-    } else {
-        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, 1), dim3(256), 0, s, cand, per_query,
-                           per_query, (uint32_t)k, gthr, 1, (int)largest, smax, nullptr, vals, idx);
-    }
+    hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand,
+                       per_query, p.n_chunks > 1 ? p.chunk : per_query, (uint32_t)k, gthr, hist,
+                       bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx);
+    if (p.n_chunks > 1)
+        hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
+                           p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx);
     return check_launch("bolt_scan_topk (fused)");
 }
 

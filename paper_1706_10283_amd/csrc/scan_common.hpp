@@ -31,7 +31,7 @@ bool few_supported(int M, int64_t Q);
 template <OutMode OUT>
 int few_scan(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, uint16_t *out,
              float *outf, int64_t ldo, float bias, float scale, hipStream_t s);
-int64_t few_rows_per_block(int64_t N);
+int64_t few_rows_per_block(int64_t N, int M, int nq);
 size_t few_fused_lds_bytes(int M, int nq);
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
                   bool largest, int n_rb, uint64_t *cand, uint32_t *gthr, hipStream_t s);

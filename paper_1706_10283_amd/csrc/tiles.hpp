@@ -27,10 +27,21 @@ constexpr int kTileRowsMax = 65536;   // 16-bit local rows
 constexpr int kGroupedCap = 512;      // candidate slots per query
 constexpr int kRefresh = 8;           // passes between reads of the published bounds
 
-// Few-query tiles (pair tables; see few.hip).
-constexpr int kFewR = 4;              // rows per lane per pass
-constexpr int kFewPass = 256 * kFewR;
-constexpr int kFewCap = 2 * kFewPass; // candidate slots per query
+// Per-query histogram of the d values of all tiles' final local top-k keys
+// (distinct rows), kHistBins bins of 2^hist_shift(M) values each, built after
+// the scan.  The first bin at which the running count reaches k bounds the
+// k-th smallest d of the whole database from above, far more tightly than
+// the best single tile's bound, and lets the merge skip nearly every
+// candidate.
+constexpr int kHistBins = 1024;
+
+__host__ __device__ constexpr int hist_shift(int M)
+{
+    int s = 0;
+    while (((255 * M) >> s) >= kHistBins)
+        ++s;
+    return s;
+}
 
 struct TileJob {
     const uint8_t *codes;   // the database's codes [N][M/2]
@@ -57,16 +68,24 @@ __device__ __forceinline__ uint32_t sub_sat_u16x2(uint32_t a, uint32_t b)
 
 __device__ __forceinline__ uint32_t read_bound(const uint32_t *g) { return __atomic_load_n(g, __ATOMIC_RELAXED); }
 
-__device__ __forceinline__ void publish(uint32_t *g, uint32_t T)
+// Lowers the published bound to T, unless T does not beat the exclusive
+// bound the caller already holds (which includes the published one as last
+// read): same-address atomics from thousands of tiles would serialise.
+__device__ __forceinline__ void publish(uint32_t *g, uint32_t T, uint32_t known)
 {
-    if (T <= 0xFFFFu)
+    if (T <= 0xFFFFu && T + 1u < known)
         atomicMin(g, T);
 }
 
 // Final exact local top-k of one query (one wave), written as 48-bit keys.
+// known: the exclusive bound the tile holds (see publish).  Keys above the
+// published bound as read now cannot be in the top-k and are written as
+// padding (~0), which the readers skip; the tile that published the final
+// bound still writes its k keys at or below it, so the histogram built from
+// the written keys always reaches k.
 template <int CAP, bool LDS_PRUNE>
 __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t r0,
-                                 uint64_t *__restrict__ dst, uint32_t *gthr_q)
+                                 uint64_t *__restrict__ dst, uint32_t *gthr_q, uint32_t known)
 {
     const int lane = threadIdx.x & 63;
     if (n > k) {
@@ -74,13 +93,15 @@ __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t 
                                          : prune_local<CAP>(buf, n, k, true);
         n = pr.count;
         if (lane == 0)
-            publish(gthr_q, pr.T);
+            publish(gthr_q, pr.T, known);
     }
+    const uint32_t g = __builtin_amdgcn_readfirstlane(read_bound(gthr_q));
     for (uint32_t j = lane; j < k; j += 64) {
         uint64_t key = ~0ull;
         if (j < n) {
             const uint32_t lk = buf[j];
-            key = ((uint64_t)(lk >> 16) << 32) | (uint64_t)(r0 + (lk & 0xFFFFu));
+            if ((lk >> 16) <= g)
+                key = ((uint64_t)(lk >> 16) << 32) | (uint64_t)(r0 + (lk & 0xFFFFu));
         }
         dst[j] = key;
     }
@@ -207,7 +228,7 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
                     pr = prune_local<CAP>(L.buf + q * CAP, pr.count, k, true);
                 if (lane == 0) {
                     L.cnt[q] = pr.count;
-                    publish(&job.gthr[q0 + q], pr.T);
+                    publish(&job.gthr[q0 + q], pr.T, L.bnd[q]);
                 }
                 nb = pr.T;
             }
@@ -225,71 +246,152 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
     for (int q = wave; q < nq; q += 4)
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
-                                     &job.gthr[q0 + q]);
+                                     &job.gthr[q0 + q], L.bnd[q]);
 }
 
 // ------------------------------------------------------------------ few queries
 
+// Rows per lane per pass: enough code bytes in flight per lane (32 to 128)
+// to keep HBM busy, at most 32 registers of codes per buffer.
+__host__ __device__ constexpr int few_r(int M) { return M >= 32 ? 4 : 8; }
+__host__ __device__ constexpr int few_pass(int M) { return 256 * few_r(M); }
+// Candidate slots per query: a full pass plus room for k <= 256 and slack.
+__host__ __device__ constexpr int few_cap(int M) { return few_pass(M) + 1024; }
+
+// Pair tables of nq queries: entry b of pair p is lut[2p][b & 15] +
+// lut[2p+1][b >> 4].  stage (LDS, nq * MM * 16 bytes, 16-byte aligned, free
+// until the next barrier) takes the raw tables first with one 16-byte load
+// per table, so each entry is then built from LDS; without it (or with
+// unaligned tables) the entries read the tables from global memory byte by
+// byte.  Every thread of the workgroup must call it.
 template <int MM>
-__device__ __forceinline__ void build_pair_tables(const uint8_t *__restrict__ luts, int nq, uint16_t *pt)
+__device__ __forceinline__ void build_pair_tables(const uint8_t *__restrict__ luts, int nq, uint16_t *pt,
+                                                  uint8_t *stage = nullptr)
 {
     constexpr int NP = MM / 2;
+    const uint8_t *src = luts;
+    if (stage && (reinterpret_cast<uintptr_t>(luts) & 15) == 0) {
+        for (int t = threadIdx.x; t < nq * MM; t += 256)
+            reinterpret_cast<uint4 *>(stage)[t] = reinterpret_cast<const uint4 *>(luts)[t];
+        __syncthreads();
+        src = stage;
+    }
     for (int e = threadIdx.x; e < nq * NP * 256; e += 256) {
         const int b = e & 255, p = (e >> 8) % NP, q = (e >> 8) / NP;
-        const uint8_t *l = luts + ((int64_t)q * MM + 2 * p) * 16;
+        const uint8_t *l = src + ((int64_t)q * MM + 2 * p) * 16;
         pt[e] = (uint16_t)(l[b & 15] + l[16 + (b >> 4)]);
     }
 }
 
-// Sums of one query for the kFewR rows held in cw (pair tables of the query at tq).
-template <int MM>
-__device__ __forceinline__ void pair_sums(const uint16_t *tq, const uint32_t (&cw)[kFewR][MM / 8],
-                                          uint32_t (&s)[kFewR])
+// Byte J of w times 2 (the byte offset of a uint16 table entry) in one
+// VALU instruction: the SDWA source select extracts the byte.  Written as
+// volatile asm (an ALU instruction, not a load) so that it keeps its place
+// in the pipelined order below instead of being hoisted with all the others.
+template <int J>
+__device__ __forceinline__ uint32_t byte_x2(uint32_t w)
 {
-    const char *tb = reinterpret_cast<const char *>(tq);
-    uint32_t part[kFewR];
-#pragma unroll
-    for (int r = 0; r < kFewR; ++r)
-        part[r] = 0;
-    // one code dword (four pairs) per step keeps 4*kFewR reads in flight and
-    // the register count low
-#pragma unroll 1
-    for (int t = 0; t < MM / 8; ++t) {
-        uint32_t w[kFewR];
-#pragma unroll
-        for (int r = 0; r < kFewR; ++r) {
-            w[r] = cw[r][0];
-#pragma unroll
-            for (int v = 1; v < MM / 8; ++v)
-                w[r] = (t == v) ? cw[r][v] : w[r];
-        }
-        const char *tt = tb + t * 4 * 512;
-        uint32_t v[kFewR][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < kFewR; ++r) {
-                const uint32_t byte = (w[r] >> (8 * j)) & 0xFFu;
-                v[r][j] = *reinterpret_cast<const uint16_t *>(tt + j * 512 + 2 * byte);
-            }
-#pragma unroll
-        for (int r = 0; r < kFewR; ++r)
-            part[r] += v[r][0] + v[r][1] + v[r][2] + v[r][3];
-    }
-#pragma unroll
-    for (int r = 0; r < kFewR; ++r)
-        s[r] = part[r];
+    uint32_t r;
+    asm volatile("v_lshlrev_b32_sdwa %0, 1, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_%2"
+                 : "=v"(r)
+                 : "v"(w), "i"(J));
+    return r;
 }
 
-template <int MM>
-__device__ __forceinline__ void load_rows4(const uint8_t *__restrict__ codes, int64_t base, int64_t r1,
-                                           uint32_t (&cw)[kFewR][MM / 8])
+// a + b + c, kept in program order for the same reason.
+__device__ __forceinline__ uint32_t add3_ordered(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm volatile("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Table reads of code dword t of the R rows (4 bytes each, one pair table per byte).
+template <int MM, int R>
+__device__ __forceinline__ void pair_reads(const char *tq, const uint32_t (&cw)[R][MM / 8], int t,
+                                           uint32_t (&v)[R][4])
 {
 #pragma unroll
-    for (int r = 0; r < kFewR; ++r) {
-        const int64_t n = base + threadIdx.x + 256 * r;
-        if (n < r1)
-            load_row<MM>(codes, n, cw[r]);
+    for (int r = 0; r < R; ++r) {
+        const uint32_t w = cw[r][t];
+        v[r][0] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 0) * 512 + byte_x2<0>(w));
+        v[r][1] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 1) * 512 + byte_x2<1>(w));
+        v[r][2] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 2) * 512 + byte_x2<2>(w));
+        v[r][3] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 3) * 512 + byte_x2<3>(w));
+    }
+}
+
+// Sums of one query for the R rows held in cw; tq is the query's pair
+// tables (MM/2 tables of 256 uint16, 512 bytes each).  Every code byte is one
+// 16-bit LDS read at byte offset 512 * pair + 2 * byte.
+//
+// UNROLL (one query per tile, tables at a fixed LDS address): fully
+// unrolled, so each pair offset is an immediate of its read and a code byte
+// costs one VALU instruction plus half an add; the reads of dword t + 1 are
+// issued before the adds of dword t (two dwords of reads in flight).
+// Otherwise (several queries): the dword loop stays rolled and selects the
+// dword with a short chain, which keeps the registers low when the offsets
+// would otherwise be hoisted out of the loop over queries.
+template <int MM, int R, bool UNROLL>
+__device__ __forceinline__ void pair_sums(const char *tq, const uint32_t (&cw)[R][MM / 8], uint32_t (&s)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        s[r] = 0;
+    if constexpr (UNROLL) {
+        constexpr int T = MM / 8;
+        uint32_t v[2][R][4];
+        pair_reads<MM, R>(tq, cw, 0, v[0]);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            if (t + 1 < T)
+                pair_reads<MM, R>(tq, cw, t + 1, v[(t + 1) & 1]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                s[r] = add3_ordered(s[r], v[t & 1][r][0], v[t & 1][r][1]);
+                s[r] = add3_ordered(s[r], v[t & 1][r][2], v[t & 1][r][3]);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int t = 0; t < MM / 8; ++t) {
+            uint32_t w[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                w[r] = cw[r][0];
+#pragma unroll
+                for (int v = 1; v < MM / 8; ++v)
+                    w[r] = (t == v) ? cw[r][v] : w[r];
+            }
+            const char *tt = tq + t * 4 * 512;
+            uint32_t v[R][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t byte = (w[r] >> (8 * j)) & 0xFFu;
+                    v[r][j] = *reinterpret_cast<const uint16_t *>(tt + j * 512 + 2 * byte);
+                }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                s[r] += v[r][0] + v[r][1] + v[r][2] + v[r][3];
+        }
+    }
+}
+
+// Rows [base, min(r1, base + 256 R)) into cw (lane row tid + 256 r; zeros
+// past the end): a uniform base pointer and 32-bit lane offsets.
+template <int MM, int R>
+__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ codes, int64_t base, int64_t r1,
+                                          uint32_t (&cw)[R][MM / 8])
+{
+    const uint8_t *p = codes + base * (MM / 2);
+    const int64_t avail = r1 - base;
+    const uint32_t lim = avail >= 256 * R ? 256u * R : (avail > 0 ? (uint32_t)avail : 0u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = threadIdx.x + 256u * r;
+        if (i < lim)
+            load_row<MM>(p, (int64_t)i, cw[r]);
         else
 #pragma unroll
             for (int v = 0; v < MM / 8; ++v)
@@ -297,11 +399,29 @@ __device__ __forceinline__ void load_rows4(const uint8_t *__restrict__ codes, in
     }
 }
 
-template <int MM>
-__device__ __forceinline__ void copy_rows4(const uint32_t (&a)[kFewR][MM / 8], uint32_t (&b)[kFewR][MM / 8])
+// As load_rows, but every lane loads: a lane past the end re-reads the last
+// row of the range (row 0 of codes if the range is empty) and the caller
+// ignores it.  Unconditional loads keep the number of loads in flight known
+// to the compiler, so it waits only for the older batch, not for all.
+template <int MM, int R>
+__device__ __forceinline__ void load_rows_clamped(const uint8_t *__restrict__ codes, int64_t base, int64_t r1,
+                                                  uint32_t (&cw)[R][MM / 8])
+{
+    const int64_t avail = r1 - base;
+    const uint8_t *p = avail > 0 ? codes + base * (MM / 2) : codes;
+    const uint32_t last = avail >= 256 * R ? 256u * R - 1 : (avail > 0 ? (uint32_t)avail - 1 : 0u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = threadIdx.x + 256u * r;
+        load_row<MM>(p, (int64_t)(i < last ? i : last), cw[r]);
+    }
+}
+
+template <int MM, int R>
+__device__ __forceinline__ void copy_rows(const uint32_t (&a)[R][MM / 8], uint32_t (&b)[R][MM / 8])
 {
 #pragma unroll
-    for (int r = 0; r < kFewR; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int v = 0; v < MM / 8; ++v)
             b[r][v] = a[r][v];
@@ -310,23 +430,28 @@ __device__ __forceinline__ void copy_rows4(const uint32_t (&a)[kFewR][MM / 8], u
 // LDS of a few-query tile: pair tables, then candidate buffers and counters.
 __host__ __device__ constexpr size_t few_tile_lds_bytes(int M, int nq)
 {
-    return (size_t)nq * (M / 2) * 256 * sizeof(uint16_t) + (size_t)nq * (kFewCap + 2) * sizeof(uint32_t);
+    return (size_t)nq * (M / 2) * 256 * sizeof(uint16_t) + (size_t)nq * (few_cap(M) + 2) * sizeof(uint32_t);
 }
 
-template <int MM>
-__device__ void few_tile(const TileJob &job, char *lds)
+// ONE: the tile has exactly one query (compile-time), so the table base is
+// the start of LDS and every table offset folds into the reads.
+template <int MM, bool ONE>
+__device__ void few_tile_impl(const TileJob &job, char *lds)
 {
     constexpr uint32_t SMAX = 255u * MM;
-    const int nq = job.nq;
+    constexpr int R = few_r(MM);
+    constexpr int PASS = few_pass(MM);
+    constexpr int CAP = few_cap(MM);
+    const int nq = ONE ? 1 : job.nq;
     const uint32_t k = job.k;
     const int largest = job.largest;
     uint16_t *pt = reinterpret_cast<uint16_t *>(lds);                         // [nq][MM/2][256]
-    uint32_t *buf = reinterpret_cast<uint32_t *>(pt + nq * (MM / 2) * 256);  // [nq][kFewCap]
-    uint32_t *cnt = buf + nq * kFewCap;
+    uint32_t *buf = reinterpret_cast<uint32_t *>(pt + nq * (MM / 2) * 256);  // [nq][CAP]
+    uint32_t *cnt = buf + nq * CAP;
     uint32_t *bnd = cnt + nq;
     uint32_t *gthr = job.gthr + job.q0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    build_pair_tables<MM>(job.luts + job.q0 * MM * 16, nq, pt);
+    build_pair_tables<MM>(job.luts + job.q0 * MM * 16, nq, pt, reinterpret_cast<uint8_t *>(buf));
     if (tid < nq) {
         cnt[tid] = 0;
         bnd[tid] = read_bound(&gthr[tid]) + 1u;
@@ -334,23 +459,23 @@ __device__ void few_tile(const TileJob &job, char *lds)
     __syncthreads();
     const int64_t r0 = job.r0, r1 = job.r1;
     int pass = 0;
-    uint32_t cw[kFewR][MM / 8], nx[kFewR][MM / 8];
-    load_rows4<MM>(job.codes, r0, r1, nx);
-    for (int64_t base = r0; base < r1; base += kFewPass, ++pass) {
-        copy_rows4<MM>(nx, cw);
-        if (base + kFewPass < r1)   // next pass in flight while this one is computed
-            load_rows4<MM>(job.codes, base + kFewPass, r1, nx);
+    uint32_t cw[R][MM / 8], nx[R][MM / 8];
+    load_rows<MM, R>(job.codes, r0, r1, nx);
+    for (int64_t base = r0; base < r1; base += PASS, ++pass) {
+        copy_rows<MM, R>(nx, cw);
+        if (base + PASS < r1)   // next pass in flight while this one is computed
+            load_rows<MM, R>(job.codes, base + PASS, r1, nx);
         for (int q = 0; q < nq; ++q) {
-            uint32_t s[kFewR];
-            pair_sums<MM>(pt + q * (MM / 2) * 256, cw, s);
+            uint32_t s[R];
+            pair_sums<MM, R, ONE>(reinterpret_cast<const char *>(pt + q * (MM / 2) * 256), cw, s);
             const uint32_t bq = bnd[q];
 #pragma unroll
-            for (int r = 0; r < kFewR; ++r) {
+            for (int r = 0; r < R; ++r) {
                 const int64_t n = base + tid + 256 * r;
                 const uint32_t d = largest ? SMAX - s[r] : s[r];
                 if (n < r1 && d < bq) {
                     const uint32_t pos = atomicAdd(&cnt[q], 1u);
-                    buf[q * kFewCap + pos] = local_key(d, (uint32_t)(n - r0));
+                    buf[q * CAP + pos] = local_key(d, (uint32_t)(n - r0));
                 }
             }
         }
@@ -359,13 +484,13 @@ __device__ void few_tile(const TileJob &job, char *lds)
         for (int q = wave; q < nq; q += 4) {
             const uint32_t c = cnt[q];
             uint32_t nb = 0xFFFFFFFFu;
-            if (c > kFewCap - kFewPass) {
-                PruneResult pr = prune_local_lds<kFewCap>(buf + q * kFewCap, c, k, false);
-                if (pr.count > kFewCap - kFewPass)
-                    pr = prune_local_lds<kFewCap>(buf + q * kFewCap, pr.count, k, true);
+            if (c > CAP - PASS) {
+                PruneResult pr = prune_local_lds<CAP>(buf + q * CAP, c, k, false);
+                if (pr.count > CAP - PASS)
+                    pr = prune_local_lds<CAP>(buf + q * CAP, pr.count, k, true);
                 if (lane == 0) {
                     cnt[q] = pr.count;
-                    publish(&gthr[q], pr.T);
+                    publish(&gthr[q], pr.T, bnd[q]);
                 }
                 nb = pr.T;
             }
@@ -379,9 +504,16 @@ __device__ void few_tile(const TileJob &job, char *lds)
         __syncthreads();
     }
     for (int q = wave; q < nq; q += 4)
-        write_local_topk<kFewCap, true>(buf + q * kFewCap, cnt[q], k, r0,
-                                        job.cand + ((job.q0 + q) * job.n_rb + job.rb) * (int64_t)k,
-                                        &gthr[q]);
+        write_local_topk<CAP, true>(buf + q * CAP, cnt[q], k, r0,
+                                    job.cand + ((job.q0 + q) * job.n_rb + job.rb) * (int64_t)k,
+                                    &gthr[q], bnd[q]);
+}
+
+// A few-query tile; ONE requires job.nq == 1.
+template <int MM, bool ONE>
+__device__ void few_tile(const TileJob &job, char *lds)
+{
+    few_tile_impl<MM, ONE>(job, lds);
 }
 
 // ------------------------------------------------------------------ merge
@@ -389,62 +521,65 @@ __device__ void few_tile(const TileJob &job, char *lds)
 constexpr int kMergeCap = 2048;   // merge buffer (keys)
 constexpr int kMergeE = 4;        // keys per thread per merge pass
 
+struct MergeLds {
+    uint64_t mb[kMergeCap];
+    uint64_t mbound;
+    uint32_t mcnt;
+    uint32_t misc;
+};
+
 // Exact k smallest of the 48-bit keys src[lo, hi) with d <= bound (one
-// workgroup).  out != NULL: the k keys (unsorted, ~0 padded) are written to
-// out; otherwise they are sorted and written as values (sum, converted back
-// from d) and rows, padded with 65535 / 0 and -1.
-__device__ void merge_keys(const uint64_t *__restrict__ src, int64_t lo, int64_t hi, uint32_t k,
-                           uint32_t bound, uint64_t *__restrict__ out, int largest, uint32_t smax,
-                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+// workgroup): left unsorted in L.mb[0, n), n <= k returned.
+__device__ uint32_t merge_collect(MergeLds &L, const uint64_t *__restrict__ src, int64_t lo, int64_t hi,
+                                 uint32_t k, uint32_t bound)
 {
-    __shared__ uint64_t mb[kMergeCap];
-    __shared__ uint32_t mcnt;
-    __shared__ uint64_t mbound;
     const int tid = threadIdx.x;
     if (tid == 0) {
-        mcnt = 0;
-        mbound = ((uint64_t)bound + 1u) << 32;   // keys with d <= bound
+        L.mcnt = 0;
+        L.mbound = ((uint64_t)bound + 1u) << 32;   // keys with d <= bound
     }
     __syncthreads();
     for (int64_t c0 = lo; c0 < hi; c0 += 256 * kMergeE) {
-        const uint64_t bnd = mbound;
+        const uint64_t bnd = L.mbound;
 #pragma unroll
         for (int e = 0; e < kMergeE; ++e) {
             const int64_t i = c0 + tid + 256 * e;
             if (i < hi) {
                 const uint64_t key = src[i];
                 if (key < bnd) {
-                    const uint32_t pos = atomicAdd(&mcnt, 1u);
-                    mb[pos] = key;
+                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                    L.mb[pos] = key;
                 }
             }
         }
         __syncthreads();
-        if (tid < 64 && mcnt > kMergeCap - 256 * kMergeE) {
-            const uint64_t kth = prune_u64<kMergeCap>(mb, mcnt, k);
+        if (tid < 64 && L.mcnt > kMergeCap - 256 * kMergeE) {
+            const uint64_t kth = prune_u64<kMergeCap>(L.mb, L.mcnt, k);
             if (tid == 0) {
-                mcnt = k;
-                mbound = kth + 1;
+                L.mcnt = k;
+                L.mbound = kth + 1;
             }
         }
         __syncthreads();
     }
-    uint32_t n = mcnt;
+    uint32_t n = L.mcnt;
     if (tid < 64 && n > k)
-        prune_u64<kMergeCap>(mb, n, k);
+        prune_u64<kMergeCap>(L.mb, n, k);
     __syncthreads();
-    if (n > k)
-        n = k;
-    if (out) {
-        for (uint32_t r = tid; r < k; r += 256)
-            out[r] = r < n ? mb[r] : ~0ull;
-        return;
-    }
+    return n > k ? k : n;
+}
+
+// Sorts L.mb[0, n) and writes values (sums, converted back from d) and rows,
+// padded to k with 65535 / 0 and -1.
+__device__ void merge_emit(MergeLds &L, uint32_t n, uint32_t k, int largest, uint32_t smax,
+                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    const int tid = threadIdx.x;
     uint32_t P = 1;
     while (P < n)
         P <<= 1;
     for (uint32_t i = n + tid; i < P; i += 256)
-        mb[i] = ~0ull;
+        L.mb[i] = ~0ull;
     __syncthreads();
     for (uint32_t size = 2; size <= P; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
@@ -452,10 +587,10 @@ __device__ void merge_keys(const uint64_t *__restrict__ src, int64_t lo, int64_t
                 const uint32_t i = 2 * t - (t & (stride - 1));
                 const uint32_t j = i + stride;
                 const bool asc = (i & size) == 0;
-                const uint64_t a = mb[i], b = mb[j];
+                const uint64_t a = L.mb[i], b = L.mb[j];
                 if ((a > b) == asc) {
-                    mb[i] = b;
-                    mb[j] = a;
+                    L.mb[i] = b;
+                    L.mb[j] = a;
                 }
             }
             __syncthreads();
@@ -463,14 +598,31 @@ __device__ void merge_keys(const uint64_t *__restrict__ src, int64_t lo, int64_t
     }
     for (uint32_t r = tid; r < k; r += 256) {
         if (r < n) {
-            const uint32_t d = (uint32_t)(mb[r] >> 32);
+            const uint32_t d = (uint32_t)(L.mb[r] >> 32);
             vals[r] = (uint16_t)(largest ? smax - d : d);
-            idx[r] = (int32_t)(mb[r] & 0xFFFFFFFFu);
+            idx[r] = (int32_t)(L.mb[r] & 0xFFFFFFFFu);
         } else {
             vals[r] = (uint16_t)(largest ? 0u : 0xFFFFu);
             idx[r] = -1;
         }
     }
+}
+
+// Exact k smallest keys of src[lo, hi) with d <= bound.  out != NULL: the k
+// keys (unsorted, ~0 padded) are written to out; otherwise sorted values and
+// rows as merge_emit.
+__device__ void merge_keys(const uint64_t *__restrict__ src, int64_t lo, int64_t hi, uint32_t k,
+                           uint32_t bound, uint64_t *__restrict__ out, int largest, uint32_t smax,
+                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    __shared__ MergeLds L;
+    const uint32_t n = merge_collect(L, src, lo, hi, k, bound);
+    if (out) {
+        for (uint32_t r = threadIdx.x; r < k; r += 256)
+            out[r] = r < n ? L.mb[r] : ~0ull;
+        return;
+    }
+    merge_emit(L, n, k, largest, smax, vals, idx);
 }
 
 }  // namespace bolt
