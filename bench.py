@@ -185,7 +185,7 @@ def headline(args, torch, B, W, M=None, steps=None, warmup=None, extras=True):
     dists = 2.0 * Q * N
     value = dists / (ms_per_step * 1e-3) / 1e9
 
-    dom = "scan_topk_grouped"
+    dom = [n for n in ("scan_topk_grouped", "scan_topk_few") if n in prof][0]
     dom_ms = prof[dom][1] / prof[dom][0]
     lookups = float(Q) * N * M                      # one table lookup-and-add per (q, n, m)
     achieved = lookups / (dom_ms * 1e-3)

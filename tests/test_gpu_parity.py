@@ -307,6 +307,7 @@ FUSED_CASES = [
     (32, 17, 50000, 100, "coarse"), (32, 40, 20000, 10, "rand"), (16, 16, 70000, 256, "rand"),
     (8, 33, 17000, 64, "coarse"), (64, 9, 40000, 100, "rand"), (64, 12, 30000, 100, "const"),
     (32, 64, 16384 * 3 + 5, 100, "rand"), (32, 20, 5, 100, "rand"), (16, 100, 4000, 1, "coarse"),
+    (16, 24, 140_000, 100, "const"), (8, 8, 65_537, 100, "rand"), (32, 15, 131_073, 200, "coarse"),
     # many candidate lists per query: two-level merge (few-query and grouped kernels)
     (32, 2, 2_000_000, 100, "rand"), (16, 9, 1_200_000, 256, "coarse"), (64, 7, 300_000, 50, "rand"),
 ]
