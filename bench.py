@@ -63,9 +63,9 @@ WRITE_FACTOR = 1.0
 TRAFFIC = {
     "scan_topk_grouped": {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 12728.0,
-        "write_kib": 50239.8,
-        "sources_sha256": "dfac19093c2ae4b95edeaf2468c867887b4834edfec80e2f77c04725d060c4fd",
+        "fetch_kib": 13069.3,
+        "write_kib": 49929.8,
+        "sources_sha256": "34cacd3ffcd72a257b3be44e1394d7b62529550922c6edca78d0087fb96d08bb",
     },
 }
 TRAFFIC_SOURCES = {
