@@ -13,7 +13,8 @@ number of (query, vector) distances produced per second over the whole step
 Sub-reports on the same line (each its own workload):
   headline extras   the oracle's CPU time on a sample (cpu_baseline), one
            query against the same cache-resident database, Recall@1/10/100
-           against exact fp64 search (Sec. 4.5)
+           against exact fp64 search (Sec. 4.5), and the same with the float
+           tables (Bolt No Quantize, Sec. 4.2) on 200 of the queries
   msweep   the same step at M = 16 and M = 64 (8 and 32 B codes)
   single_query  one query, top-100, against 2.5e8 rows at M = 16/32/64
            (4/8/16 GB of codes), cache flushed between calls: latency and
@@ -232,15 +233,16 @@ def headline(args, torch, B, W, M=None, steps=None, warmup=None, extras=True):
         res["single_query_cache_resident_ms"] = {
             m: round(event_ms(torch, lambda: B.bolt_scan_topk(codes, one[m], m, k), 20), 4)
             for m in ("l2", "dot")}
-        res["recall"] = recall(torch, X, Qd, idx)
+        true = exact_nn(torch, X, Qd)
+        res["recall"] = {m: recall_at(torch, idx[m], true[m]) for m in ("l2", "dot")}
+        res["no_quantize"] = no_quantize(torch, B, codes, Qd, Cd, M, k, idx, true, n_q=200)
     del X, codes, ws
     return res
 
 
-def recall(torch, X, Qd, idx):
-    """Recall@R (Sec. 4.5): the fraction of queries whose exact nearest
-    neighbour (fp64 squared L2; largest fp64 dot product for dot) is among
-    the first R results of the scan."""
+def exact_nn(torch, X, Qd):
+    """Each query's exact nearest neighbour: fp64 squared L2, and the largest
+    fp64 dot product (maximum inner product search)."""
     X64 = X.double()
     xx = (X64 * X64).sum(1)
     true = {"l2": [], "dot": []}
@@ -248,13 +250,35 @@ def recall(torch, X, Qd, idx):
         dots = Qd[q0:q0 + 100].double() @ X64.t()
         true["dot"].append(dots.argmax(1))
         true["l2"].append((xx[None, :] - 2.0 * dots).argmin(1))
-    out = {}
-    for m in ("l2", "dot"):
-        t = torch.cat(true[m]).to(torch.int64)
-        got = idx[m].to(torch.int64)
-        out[m] = {"R%d" % R: round((got[:, :R] == t[:, None]).any(1).double().mean().item(), 4)
-                  for R in (1, 10, 100)}
     del X64
+    return {m: torch.cat(v).to(torch.int64) for m, v in true.items()}
+
+
+def recall_at(torch, idx, true):
+    """Recall@R (Sec. 4.5): the fraction of queries whose exact nearest
+    neighbour is among the first R results."""
+    got = idx.to(torch.int64)
+    return {"R%d" % R: round((got[:, :R] == true[:, None]).any(1).double().mean().item(), 4)
+            for R in (1, 10, 100)}
+
+
+def no_quantize(torch, B, codes, Qd, Cd, M, k, idx, true, n_q):
+    """Bolt No Quantize (Sec. 4.2): the same codes scanned with the float
+    tables, on the first n_q queries; Recall@R beside the uint8 tables'
+    on the same queries, and the float scan's throughput."""
+    N = codes.shape[0]
+    Qs = Qd[:n_q].contiguous()
+    zeros = torch.zeros(M, dtype=torch.float32, device=Qd.device)
+    out = {"queries": n_q, "recall": {}, "recall_uint8_tables": {}}
+    for metric in ("l2", "dot"):
+        _, lf = B.bolt_build_luts(Qs, Cd, M, metric, 1.0, zeros, want_f32=True)
+        S = B.bolt_scan_f32(codes, lf)
+        ms = event_ms(torch, lambda: B.bolt_scan_f32(codes, lf, out=S), 3)
+        _, i = B.bolt_topk_f32(S, k, largest=metric == "dot")
+        out["recall"][metric] = recall_at(torch, i, true[metric][:n_q])
+        out["recall_uint8_tables"][metric] = recall_at(torch, idx[metric][:n_q], true[metric][:n_q])
+        out["scan_f32_G_distances_per_s"] = round(n_q * N / (ms * 1e-3) / 1e9, 1)
+        del S
     return out
 
 

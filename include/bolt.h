@@ -181,6 +181,37 @@ int bolt_amm(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
              int32_t transpose, void *stream);
 
 /*
+ * Bolt No Quantize (Sec. 4.2: Bolt's encoding with the float tables instead
+ * of their uint8 quantisation, the control for what the quantiser costs in
+ * accuracy).  out[q][n] is the fp32 sum of the float table entries selected
+ * by the codes, in one fixed order: acc = 0, then acc = acc + luts_f32[q][m]
+ * [code(n, m)] for m = 0 .. M-1, each add rounded to nearest (no fused
+ * operations), so the result is the same bit for bit on any device.
+ *
+ *   codes      device uint8 [N][M/2], any even M in [2, 256]
+ *   luts_f32   device fp32 [Q][M][16] (the luts_f32 of bolt_build_luts)
+ *   out        device fp32 [Q][ldo], ldo >= N
+ * Errors: BOLT_ERR_SHAPE for a bad M, N or Q; BOLT_ERR_INVALID for null
+ * pointers or ldo < N; BOLT_ERR_UNSUPPORTED above 524280 queries per call.
+ */
+int bolt_scan_f32(const uint8_t *codes, int64_t N, int32_t M, const float *luts_f32,
+                  int64_t Q, float *out, int64_t ldo, void *stream);
+
+/*
+ * Top-k of fp32 rows (the float-table scan's retrieval, Sec. 1.2): per row
+ * of dists the k smallest values (largest = 0) or the k largest (largest =
+ * 1), ordered by value and, among equal values, by ascending index.  Inputs
+ * must be finite.  If k > N the tail holds +inf (largest = 0) or -inf
+ * (largest = 1) with idx = -1.
+ *
+ *   dists      device fp32 [Q][ldd], ldd >= N
+ *   k          1 .. BOLT_TOPK_MAX_K
+ *   vals       device fp32 [Q][k];  idx  device int32 [Q][k]
+ */
+int bolt_topk_f32(const float *dists, int64_t Q, int64_t N, int64_t ldd, int32_t k,
+                  int32_t largest, float *vals, int32_t *idx, void *stream);
+
+/*
  * Batched scan + top-k over many encoded databases of uneven size in one
  * persistent launch: the scan + top-k of bolt_scan_topk (Sec. 3.1 scan,
  * Sec. 1.2 the k closest vectors) for every (database, query) of the batch,

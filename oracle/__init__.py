@@ -10,7 +10,7 @@ compiles it with gcc and marshals numpy arrays.
 
 Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``):
   encode, subspace_dists_f64, luts, scan, scan_pairs, topk,
-  rescale_f64, rescale_f32                      pinned
+  scan_f32, topk_f32, rescale_f64, rescale_f32  pinned
   kmeans, learn_quantizer                       parity unpinned (the paper
                                                 prints no trained values; only
                                                 invariants are checked)
@@ -126,6 +126,28 @@ def topk(d, k, largest=False):
     idx = np.zeros((Q, k), dtype=np.int32)
     _load().orc_topk(_p(d), I64(Q), I64(N), I64(N), I32(k), I32(1 if largest else 0),
                      _p(vals), _p(idx))
+    return vals, idx
+
+
+def scan_f32(codes, lutf):
+    """Bolt No Quantize: fp32 sums [Q, N] of float tables [Q, M, 16], ascending m."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    lutf = _f32(lutf)
+    N = codes.shape[0]
+    Q, M, _ = lutf.shape
+    out = np.zeros((Q, N), dtype=np.float32)
+    _load().orc_scan_f32(_p(codes), I64(N), I32(M), _p(lutf), I64(Q), _p(out))
+    return out
+
+
+def topk_f32(d, k, largest=False):
+    """(vals fp32 [Q, k], idx int32 [Q, k]): k smallest (largest) values, ties by index."""
+    d = _f32(d)
+    Q, N = d.shape
+    vals = np.zeros((Q, k), dtype=np.float32)
+    idx = np.zeros((Q, k), dtype=np.int32)
+    _load().orc_topk_f32(_p(d), I64(Q), I64(N), I64(N), I32(k), I32(1 if largest else 0),
+                         _p(vals), _p(idx))
     return vals, idx
 
 

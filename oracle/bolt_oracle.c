@@ -227,6 +227,74 @@ void orc_topk(const uint16_t *d, int64_t Q, int64_t N, int64_t ldd, int32_t k,
 }
 
 /*
+ * Bolt No Quantize (Sec. 4.2): the sum of the float table entries selected
+ * by the codes.  The paper fixes no order for it; this project's reading is
+ * ascending m with every add rounded to fp32:
+ *   acc = 0;  acc = acc + D[q][m][code(n, m)]  for m = 0 .. M-1.
+ */
+void orc_scan_f32(const uint8_t *codes, int64_t N, int32_t M, const float *lutf,
+                  int64_t Q, float *out)
+{
+    for (int64_t q = 0; q < Q; q++)
+        for (int64_t n = 0; n < N; n++) {
+            float acc = 0.0f;
+            for (int m = 0; m < M; m++)
+                acc = acc + lutf[(q * M + m) * K + code_of(codes, n, M, m)];
+            out[q * N + n] = acc;
+        }
+}
+
+/* One (value, index) candidate of a float top-k. */
+struct fcand {
+    float v;
+    int64_t i;
+};
+
+static int cmp_fcand_small(const void *a, const void *b)
+{
+    const struct fcand *x = (const struct fcand *)a, *y = (const struct fcand *)b;
+    if (x->v != y->v)
+        return x->v < y->v ? -1 : 1;
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+static int cmp_fcand_large(const void *a, const void *b)
+{
+    const struct fcand *x = (const struct fcand *)a, *y = (const struct fcand *)b;
+    if (x->v != y->v)
+        return x->v > y->v ? -1 : 1;
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+/*
+ * Top-k of float rows (Sec. 1.2, the k closest): the k smallest values
+ * (largest = 0) or the k largest, equal values by ascending index; rows with
+ * fewer than k values are padded with +inf / -inf and index -1.
+ */
+void orc_topk_f32(const float *d, int64_t Q, int64_t N, int64_t ldd, int32_t k,
+                  int32_t largest, float *vals, int32_t *idx)
+{
+    struct fcand *c = (struct fcand *)malloc(sizeof(struct fcand) * (size_t)(N > 0 ? N : 1));
+    for (int64_t q = 0; q < Q; q++) {
+        for (int64_t n = 0; n < N; n++) {
+            c[n].v = d[q * ldd + n];
+            c[n].i = n;
+        }
+        qsort(c, (size_t)N, sizeof(struct fcand), largest ? cmp_fcand_large : cmp_fcand_small);
+        for (int32_t r = 0; r < k; r++) {
+            if (r < N) {
+                vals[q * k + r] = c[r].v;
+                idx[q * k + r] = (int32_t)c[r].i;
+            } else {
+                vals[q * k + r] = largest ? -INFINITY : INFINITY;
+                idx[q * k + r] = -1;
+            }
+        }
+    }
+    free(c);
+}
+
+/*
  * Reconstruction of a quantised sum (Sec. 3.2: y_hat = (beta + b) / a,
  * summed over the M tables whose offsets add up to one bias):
  *   S_hat = (S + sum_m b'_m) / a          in fp64.

@@ -60,6 +60,8 @@ _SIGS = {
     "bolt_scan_topk_ws_bytes": ([_I64, _I32, _I64, _I32], _SZ),
     "bolt_scan_topk": ([_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "bolt_amm": ([_P, _I64, _I32, _P, _I64, _F32, _F32, _P, _I64, _I32, _P], ctypes.c_int),
+    "bolt_scan_f32": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
+    "bolt_topk_f32": ([_P, _I64, _I64, _I64, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "bolt_train_host": ([_P, _I64, _I32, _I64, _I32, _I32, _P, _P, _I64, _I64, _I32, _P, _I32,
                          _P, _P, _P, _P], ctypes.c_int),
     "bolt_learn_quantizer_host": ([_P, _I64, _I32, _I64, _P, _I64, _P, _I32, _I32, _P, _I32,
@@ -199,6 +201,33 @@ def bolt_topk(dists, k, largest=False, vals=None, idx=None, stream=None):
     ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dists.device)
     _check(_lib.bolt_topk(_ptr(dists), Q, N, ldd, k, 1 if largest else 0, _ptr(vals), _ptr(idx),
                           _ptr(ws), nws, _stream(stream)))
+    return vals, idx
+
+
+def bolt_scan_f32(codes, luts_f32, out=None, stream=None):
+    """Bolt No Quantize: fp32 sums [Q, N] of the float tables over the codes."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(luts_f32, torch.float32, "luts_f32")
+    N = codes.shape[0]
+    Q, M = luts_f32.shape[0], luts_f32.shape[1]
+    if out is None:
+        out = torch.empty((Q, N), dtype=torch.float32, device=codes.device)
+    _dev(out, torch.float32, "out")
+    ldo = out.stride(0) if out.shape[0] > 0 else N
+    _check(_lib.bolt_scan_f32(_ptr(codes), N, M, _ptr(luts_f32), Q, _ptr(out), ldo, _stream(stream)))
+    return out
+
+
+def bolt_topk_f32(dists, k, largest=False, vals=None, idx=None, stream=None):
+    """(vals fp32 [Q, k], idx int32 [Q, k]) of each row of fp32 dists [Q, N]."""
+    _dev(dists, torch.float32, "dists")
+    Q, N, ldd = _rows(dists, "dists")
+    if vals is None:
+        vals = torch.empty((Q, k), dtype=torch.float32, device=dists.device)
+    if idx is None:
+        idx = torch.empty((Q, k), dtype=torch.int32, device=dists.device)
+    _check(_lib.bolt_topk_f32(_ptr(dists), Q, N, ldd, k, 1 if largest else 0, _ptr(vals), _ptr(idx),
+                              _stream(stream)))
     return vals, idx
 
 

@@ -381,3 +381,67 @@ def test_quantizer_learning_matches_expanded_quantiles():
     beta = np.clip(np.floor(np.float64(a) * Y - offs[:, None].astype(np.float64)), 0, 255)
     yh = (beta + offs[:, None]) / np.float64(a)
     assert losses[best] == pytest.approx(((yh - Y) ** 2).mean(), rel=1e-9)
+
+
+# ------------------------------------------------------------------ Bolt No Quantize (Sec. 4.2)
+
+def test_scan_f32_integer_tables_equal_integer_scan():
+    """Integer-valued float tables: every partial sum is an exact fp32 integer,
+    so the float scan must equal the (pinned) integer scan exactly."""
+    N, M, Q = 3000, 32, 5
+    codes = synth.random_codes(71, N, M)
+    lut8 = synth.random_luts(72, Q, M)
+    got = oracle.scan_f32(codes, lut8.astype(np.float32))
+    assert np.array_equal(got, oracle.scan(codes, lut8).astype(np.float32))
+
+
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+def test_scan_f32_reconstruction_closed_form(metric):
+    """Float tables over h(x): the sum is the squared distance to (or the dot
+    product with) the reconstruction x_hat, up to fp32 rounding of the M
+    table entries and M adds (Sec. 3.1; Sec. 3.3 Definition)."""
+    J, M = 64, 16
+    X = synth.normal(73, (200, J))
+    Qv = synth.normal(74, (6, J))
+    C = synth.normal(75, (M, 16, J // M))
+    codes = oracle.encode(X, C, M)
+    xh = _reconstruct(_unpack(codes, M), C)
+    _, l32, _ = oracle.luts(Qv, C, M, metric)
+    got = oracle.scan_f32(codes, l32).astype(np.float64)
+    q64 = Qv.astype(np.float64)
+    if metric == "l2":
+        ref = ((q64[:, None, :] - xh[None]) ** 2).sum(-1)
+        np.testing.assert_allclose(got, ref, rtol=4 * M * 2.0 ** -24)
+    else:
+        ref = q64 @ xh.T
+        scale = np.abs(q64)[:, None, :] * np.abs(xh)[None]
+        assert (np.abs(got - ref) <= 4 * M * 2.0 ** -24 * scale.sum(-1)).all()
+
+
+def test_scan_f32_adds_in_ascending_m_order():
+    """The sum is left to right in ascending m with fp32 rounding after each
+    add: for entries 1, 1e8, -1e8 that gives (1 + 1e8) - 1e8 = 0 in fp32,
+    where the exact sum (or fp64, or another order) gives 1."""
+    M = 4
+    lut = np.zeros((1, M, 16), dtype=np.float32)
+    lut[0, 0, 0], lut[0, 1, 0], lut[0, 2, 0], lut[0, 3, 0] = 1.0, 1e8, -1e8, 0.0
+    codes = np.zeros((1, M // 2), dtype=np.uint8)
+    assert oracle.scan_f32(codes, lut)[0, 0] == np.float32(0.0)
+    lut[0, 0, 0], lut[0, 1, 0], lut[0, 2, 0] = 1e8, -1e8, 1.0
+    assert oracle.scan_f32(codes, lut)[0, 0] == np.float32(1.0)
+
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_topk_f32_lexsort(largest):
+    """Float top-k against numpy.lexsort on (value, index), with forced ties."""
+    d = (np.round(synth.normal(76, (7, 900)) * 4) / 4).astype(np.float32)
+    k = 50
+    vals, idx = oracle.topk_f32(d, k, largest)
+    for q in range(d.shape[0]):
+        keys = -d[q].astype(np.float64) if largest else d[q].astype(np.float64)
+        order = np.lexsort((np.arange(d.shape[1]), keys))[:k]
+        assert np.array_equal(idx[q], order)
+        assert np.array_equal(vals[q], d[q][order])
+    v, i = oracle.topk_f32(d[:, :3], 5, largest)
+    assert (i[:, 3:] == -1).all()
+    assert (v[:, 3:] == (-np.inf if largest else np.inf)).all()
