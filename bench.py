@@ -233,11 +233,38 @@ def headline(args, torch, B, W, M=None, steps=None, warmup=None, extras=True):
         res["single_query_cache_resident_ms"] = {
             m: round(event_ms(torch, lambda: B.bolt_scan_topk(codes, one[m], m, k), 20), 4)
             for m in ("l2", "dot")}
+        res["training"] = training_times(args, torch, B, mix)
         true = exact_nn(torch, X, Qd)
         res["recall"] = {m: recall_at(torch, idx[m], true[m]) for m in ("l2", "dot")}
         res["no_quantize"] = no_quantize(torch, B, codes, Qd, Cd, M, k, idx, true, n_q=200)
     del X, codes, ws
     return res
+
+
+def training_times(args, torch, B, mix):
+    """k-means codebooks for the headline's training set (n_train mixture
+    rows, 10 Lloyd iterations): on the GPU (bolt_kmeans) and with the host
+    trainer's k-means (threads on the host cores)."""
+    import synth
+    import synth.device as sdev
+    n, J, M = args.n_train, args.J, args.M
+    Xtr = sdev.gmm_rows(mix, synth.seed_for(2, 3), 0, n, J)
+    init = synth.permutation_prefix(synth.seed_for(2, 4), n, 16)
+    B.bolt_kmeans(Xtr, M, 1, init)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Cg, _ = B.bolt_kmeans(Xtr, M, 10, init)
+    gpu_s = time.perf_counter() - t0
+    Xh = Xtr.cpu().numpy()
+    Qt = Xh[:64]
+    t0 = time.perf_counter()
+    Ch, _, _, _ = B.bolt_train_host(Xh, M, 10, init, Qt, "l2")
+    host_s = time.perf_counter() - t0
+    return {"workload": "k-means, %d x %d mixture rows, M=%d, 10 iterations" % (n, J, M),
+            "kmeans_gpu_ms": round(gpu_s * 1e3, 2),
+            "host_trainer_ms": round(host_s * 1e3, 1),
+            "host_trainer_note": "k-means plus the quantiser for 64 queries, host threads",
+            "identical_codebooks": bool(np.array_equal(Cg.cpu().numpy(), Ch))}
 
 
 def exact_nn(torch, X, Qd):

@@ -291,6 +291,33 @@ int bolt_batch_graph_destroy(void *graph_exec);
  * statistics; the alpha with the smallest mean squared reconstruction error
  * wins, ties to the smaller alpha.
  */
+/*
+ * Codebook learning on the GPU: the k-means of bolt_train_host (K = 16 per
+ * subspace, Sec. 3.1, 3.2) with its data and centroids in device memory.
+ * Lloyd iterations: every (row, subspace) goes to the centroid at the
+ * smallest fp64 squared distance (ascending dimension order, ties to the
+ * lowest index), each centroid becomes the fp64 mean of its rows rounded to
+ * fp32, and an empty cluster keeps its centroid.  The fp64 means are summed
+ * in parallel order: bit-identical to ascending-row sums whenever those are
+ * exact (integer-valued data), else within the last bit of the fp32 result.
+ *
+ *   X          device fp32 [n][ldx] training vectors, n >= 16
+ *   iters      Lloyd iterations, 0 .. 10000
+ *   init_rows  HOST int64 [16]: centroid i of every subspace starts at row
+ *              init_rows[i] (the random choice is an input)
+ *   centroids  device fp32 [M][16][J/M] (output)
+ *   objective  HOST fp64 [iters + 1] (output, may be NULL): total squared
+ *              error of the assignment before each update and after the last
+ *   ws         device workspace of bolt_kmeans_ws_bytes(J, M, iters) bytes,
+ *              256-byte aligned
+ * The call synchronises the stream before it returns.  J * 16 fp64 sums are
+ * kept in LDS: BOLT_ERR_UNSUPPORTED for J above about 1100.
+ */
+size_t bolt_kmeans_ws_bytes(int32_t J, int32_t M, int32_t iters);
+int bolt_kmeans(const float *X, int64_t n, int32_t J, int64_t ldx, int32_t M, int32_t iters,
+                const int64_t *init_rows, float *centroids, double *objective, void *ws,
+                size_t ws_bytes, void *stream);
+
 int bolt_train_host(const float *X, int64_t n, int32_t J, int64_t ldx, int32_t M,
                     int32_t iters, const int64_t *init_rows, const float *Qt, int64_t nq,
                     int64_t ldq, int32_t metric, const double *alphas, int32_t nalpha,

@@ -61,6 +61,8 @@ _SIGS = {
     "bolt_scan_topk": ([_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "bolt_amm": ([_P, _I64, _I32, _P, _I64, _F32, _F32, _P, _I64, _I32, _P], ctypes.c_int),
     "bolt_scan_f32": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
+    "bolt_kmeans_ws_bytes": ([_I32, _I32, _I32], _SZ),
+    "bolt_kmeans": ([_P, _I64, _I32, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "bolt_topk_f32": ([_P, _I64, _I64, _I64, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "bolt_train_host": ([_P, _I64, _I32, _I64, _I32, _I32, _P, _P, _I64, _I64, _I32, _P, _I32,
                          _P, _P, _P, _P], ctypes.c_int),
@@ -229,6 +231,24 @@ def bolt_topk_f32(dists, k, largest=False, vals=None, idx=None, stream=None):
     _check(_lib.bolt_topk_f32(_ptr(dists), Q, N, ldd, k, 1 if largest else 0, _ptr(vals), _ptr(idx),
                               _stream(stream)))
     return vals, idx
+
+
+def bolt_kmeans(X, M, iters, init_rows, centroids=None, stream=None):
+    """Codebooks on the GPU: (centroids device fp32 [M, 16, J/M], objective numpy fp64 [iters + 1])."""
+    _dev(X, torch.float32, "X")
+    n, J, ldx = _rows(X, "X")
+    init = np.ascontiguousarray(init_rows, dtype=np.int64)
+    if init.shape != (16,):
+        raise ValueError("init_rows must hold 16 row indices")
+    if centroids is None:
+        centroids = torch.empty((M, 16, J // M if M else 0), dtype=torch.float32, device=X.device)
+    _dev(centroids, torch.float32, "centroids")
+    nws = int(_lib.bolt_kmeans_ws_bytes(J, M, iters))
+    ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=X.device)
+    obj = np.zeros(max(iters + 1, 1), dtype=np.float64)
+    _check(_lib.bolt_kmeans(_ptr(X), n, J, ldx, M, iters, init.ctypes.data, _ptr(centroids),
+                            obj.ctypes.data, _ptr(ws), nws, _stream(stream)))
+    return centroids, obj
 
 
 def bolt_scan_topk_ws_bytes(N, M, Q, k):

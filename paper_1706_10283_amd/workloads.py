@@ -46,13 +46,17 @@ class EncodedDB:
 
 def train(mix_seed: int, train_seed: int, init_seed: int, lut_seed: int, J: int, M: int,
           n_train: int, iters: int = 10, n_lut_train: int = 1000, device="cuda"):
-    """Host training on a GPU-generated mixture sample: (centroids, {metric: (a, offsets)})."""
+    """Training on a GPU-generated mixture sample: k-means on the GPU, the
+    quantisers on the host.  Returns (centroids, {metric: (a, offsets)})."""
     Xtr = sdev.gmm_rows(mix_seed, train_seed, 0, n_train, J, device=device)
     init = synth.permutation_prefix(init_seed, n_train, 16)
-    Xh = Xtr.cpu().numpy()
-    Qt = Xh[synth.permutation_prefix(lut_seed, n_train, n_lut_train)]
-    C, a_l2, off_l2, _ = B.bolt_train_host(Xh, M, iters, init, Qt, "l2")
-    tr_codes = B.bolt_encode(Xtr, torch.from_numpy(C).to(device), M).cpu().numpy()
+    Qt = Xtr[torch.from_numpy(synth.permutation_prefix(lut_seed, n_train, n_lut_train)).to(device)].cpu().numpy()
+    # codebooks on the GPU (bit-identical to the host k-means on this
+    # integer-valued data), quantisers on the host
+    Cd, _ = B.bolt_kmeans(Xtr, M, iters, init)
+    C = Cd.cpu().numpy()
+    tr_codes = B.bolt_encode(Xtr, Cd, M).cpu().numpy()
+    a_l2, off_l2, _ = B.bolt_learn_quantizer_host(Qt, tr_codes, C, "l2")
     a_dot, off_dot, _ = B.bolt_learn_quantizer_host(Qt, tr_codes, C, "dot")
     return C, {"l2": (a_l2, off_l2), "dot": (a_dot, off_dot)}
 

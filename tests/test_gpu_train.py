@@ -1,0 +1,78 @@
+"""Codebook learning on the GPU (bolt_kmeans) against the oracle's k-means,
+through the C ABI.  The assignment uses the oracle's fp64 operations in its
+order, so on integer-valued data (the Gaussian-mixture workloads: every fp64
+sum is exact) the centroids must be identical bit for bit; on N(0, 1) data
+the parallel fp64 sums may round differently, within the last bit of the
+fp32 mean.  The oracle's k-means itself is parity unpinned (the paper
+prints no trained codebooks): these tests bind the GPU to it, and the
+invariants (non-increasing objective) to the mathematics."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def bolt():
+    import paper_1706_10283_amd.bolt as b
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return b
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("J,M,iters", [(128, 32, 10), (128, 16, 6), (64, 64, 4), (32, 8, 10)])
+def test_kmeans_mixture_bit_exact(bolt, J, M, iters):
+    n = 20_000
+    _say("kmeans mixture", "n", n, "J", J, "M", M, "iters", iters)
+    X = synth.gmm_rows(synth.seed_for(4, 0), synth.seed_for(4, 3) + J, 0, n, J)
+    init = synth.permutation_prefix(synth.seed_for(4, 4) + M, n, 16)
+    C_ref, obj_ref = oracle.kmeans(X, M, iters, init)
+    C, obj = bolt.bolt_kmeans(torch.from_numpy(X).to(DEV), M, iters, init)
+    assert np.array_equal(C.cpu().numpy().view(np.uint32), C_ref.view(np.uint32))
+    np.testing.assert_allclose(obj, obj_ref, rtol=1e-12)
+    assert (np.diff(obj) <= 1e-9 * obj[0]).all()
+
+
+def test_kmeans_empty_clusters_keep_centroid(bolt):
+    """Seeds on duplicated rows: the later copy loses every tie, so its cluster
+    starts empty and keeps its centroid; both sides must agree bit for bit."""
+    n, J, M = 5000, 32, 8
+    X = synth.gmm_rows(synth.seed_for(4, 0), 99, 0, n, J)
+    init = synth.permutation_prefix(123, n, 16)
+    init[9] = init[3]
+    init[15] = init[0]
+    C_ref, obj_ref = oracle.kmeans(X, M, 5, init)
+    C, obj = bolt.bolt_kmeans(torch.from_numpy(X).to(DEV), M, 5, init)
+    assert np.array_equal(C.cpu().numpy().view(np.uint32), C_ref.view(np.uint32))
+    np.testing.assert_allclose(obj, obj_ref, rtol=1e-12)
+
+
+def test_kmeans_normal_data_within_last_bit(bolt):
+    n, J, M, iters = 6000, 32, 8, 3
+    _say("kmeans normal", "n", n, "J", J, "M", M, "iters", iters)
+    X = synth.normal(311, (n, J))
+    init = synth.permutation_prefix(312, n, 16)
+    C_ref, obj_ref = oracle.kmeans(X, M, iters, init)
+    C, obj = bolt.bolt_kmeans(torch.from_numpy(X).to(DEV), M, iters, init)
+    np.testing.assert_array_max_ulp(C.cpu().numpy(), C_ref, maxulp=2)
+    np.testing.assert_allclose(obj, obj_ref, rtol=1e-9)
+
+
+def test_kmeans_errors(bolt):
+    X = torch.zeros((10, 8), dtype=torch.float32, device=DEV)
+    with pytest.raises(bolt.BoltError):
+        bolt.bolt_kmeans(X, 4, 2, np.arange(16))          # fewer than 16 rows
+    X = torch.zeros((100, 8), dtype=torch.float32, device=DEV)
+    with pytest.raises(bolt.BoltError):
+        bolt.bolt_kmeans(X, 4, 2, np.arange(16) + 90)     # seed row out of range
+    with pytest.raises(bolt.BoltError):
+        bolt.bolt_kmeans(X, 3, 2, np.arange(16))          # odd M
