@@ -55,7 +55,11 @@ typedef enum bolt_status {
     BOLT_ERR_NOMEM = -5        /* workspace too small */
 } bolt_status;
 
-enum { BOLT_METRIC_L2 = 0, BOLT_METRIC_DOT = 1 };
+/* Table metrics (Sec. 1.1, eq. distFuncForm: a sum over dimensions of a
+ * per-dimension term): squared L2 (q - c)^2, dot product q * c, and L1
+ * |q - c| (the L_p distance with p = 1).  L2 and L1 retrieve the smallest
+ * sums, dot the largest.  Encoding uses squared L2 for all of them. */
+enum { BOLT_METRIC_L2 = 0, BOLT_METRIC_DOT = 1, BOLT_METRIC_L1 = 2 };
 
 enum { BOLT_TOPK_MAX_K = 2048 };
 
@@ -95,7 +99,7 @@ int bolt_encode(const float *X, int64_t N, int32_t J, int64_t ldx,
  * so that the learned lower quantile maps to 0 (Sec. 3.2).
  *
  *   Qv         device fp32 [Q][ldq]
- *   metric     BOLT_METRIC_L2 or BOLT_METRIC_DOT
+ *   metric     BOLT_METRIC_L2, BOLT_METRIC_DOT or BOLT_METRIC_L1
  *   a          shared scale (> 0), host scalar
  *   offsets    device fp32 [M]
  *   luts_f32   device fp32 [Q][M][16] or NULL (the unquantised D)
@@ -147,7 +151,8 @@ int bolt_topk(const uint16_t *dists, int64_t Q, int64_t N, int64_t ldd, int32_t 
  * Scan followed by top-k without materialising the [Q][N] sums: the same
  * result as bolt_scan_* then bolt_topk with largest = (metric == DOT).
  *
- *   metric     BOLT_METRIC_L2 (k smallest) or BOLT_METRIC_DOT (k largest)
+ *   metric     BOLT_METRIC_L2 or BOLT_METRIC_L1 (k smallest), BOLT_METRIC_DOT
+ *              (k largest)
  *   ws         device workspace of bolt_scan_topk_ws_bytes(N, M, Q, k) bytes,
  *              256-byte aligned.  The size assumes codes and luts_u8 are
  *              16-byte aligned (M in {8, 16, 32, 64} and k <= 256 then take the
@@ -159,6 +164,28 @@ size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k);
 int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
                    int64_t Q, int32_t metric, int32_t k, uint16_t *vals, int32_t *idx,
                    void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Scan + top-k over a subset of the rows, as an index produces it (Sec. 1.2:
+ * the k closest among the vectors a search visits): the union of n_ranges
+ * row ranges [ranges[2r], ranges[2r+1]).  The result is that of
+ * bolt_scan_topk over the rows in the ranges, with row indices into the
+ * whole code matrix.  All queries of the call scan the same ranges.
+ *
+ *   ranges     HOST int64 [n_ranges][2], ascending, disjoint, inside [0, N]
+ *   ws         device workspace of bolt_scan_topk_ranges_ws_bytes(ranges,
+ *              n_ranges, M, Q, k) bytes, 256-byte aligned (0 bytes when the
+ *              ranges hold no row: then every result is padding)
+ * Needs the fused kernels: M in {8, 16, 32, 64}, k <= 256, codes and tables
+ * 16-byte aligned, else BOLT_ERR_UNSUPPORTED.  The tile list is copied from
+ * host memory on the stream (the call may wait for that copy).
+ */
+size_t bolt_scan_topk_ranges_ws_bytes(const int64_t *ranges, int32_t n_ranges, int32_t M,
+                                      int64_t Q, int32_t k);
+int bolt_scan_topk_ranges(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                          int64_t Q, int32_t metric, int32_t k, const int64_t *ranges,
+                          int32_t n_ranges, uint16_t *vals, int32_t *idx, void *ws,
+                          size_t ws_bytes, void *stream);
 
 /*
  * Approximate matrix product (Sec. 4.4: rows of the first matrix are the

@@ -29,7 +29,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 ALPHAS = np.array([0.0, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1], dtype=np.float64)
-METRICS = {"l2": 0, "dot": 1}
+METRICS = {"l2": 0, "dot": 1, "l1": 2}
 
 
 def build(force: bool = False) -> str:

@@ -103,11 +103,14 @@ void orc_subspace_dists_f64(const float *X, int64_t N, int32_t J, int64_t ldx,
  *   D[m][i] = sum over j in p_m of delta(q_j, c_ij)
  *       delta = (q - c)^2 for squared Euclidean (metric 0)
  *       delta = q * c     for the dot product   (metric 1)
+ *       delta = |q - c|   for L1, the L_p distance with p = 1 (metric 2;
+ *                         eq. distFuncForm with f the identity)
  *
  *   lut64: the entries in fp64 (the "true" table).
  *   lut32: the entries in fp32, canonical order, acc = 0 then j ascending,
  *          L2: t = q_j - c_j; acc = fmaf(t, t, acc)
  *          dot: acc = fmaf(q_j, c_j, acc)
+ *          L1:  acc = acc + |q_j - c_j|
  *   lut8:  beta = max(0, min(255, floor(a*y - b'_m))), with a*y - b'_m
  *          evaluated as one fmaf(a, lut32, -offsets[m]).  offsets[m] is
  *          b'_m = a * F^-1(alpha) for table m, i.e. the offset in
@@ -132,6 +135,9 @@ void orc_luts(const float *Qv, int64_t Q, int32_t J, int64_t ldq,
                         s64 += t * t;
                         float t32 = qv[jj] - c[jj];
                         s32 = fmaf(t32, t32, s32);
+                    } else if (metric == 2) {
+                        s64 += fabs((double)qv[jj] - (double)c[jj]);
+                        s32 = s32 + fabsf(qv[jj] - c[jj]);
                     } else {
                         s64 += (double)qv[jj] * (double)c[jj];
                         s32 = fmaf(qv[jj], c[jj], s32);
@@ -476,7 +482,7 @@ int orc_learn_quantizer(const float *Qt, int64_t nq, int32_t J, int64_t ldq,
                 for (int jj = 0; jj < sub; jj++) {
                     double qv = (double)Qt[q * ldq + m * sub + jj];
                     double cv = (double)C[((int64_t)m * K + i) * sub + jj];
-                    s += (metric == 0) ? (qv - cv) * (qv - cv) : qv * cv;
+                    s += (metric == 0) ? (qv - cv) * (qv - cv) : (metric == 2 ? fabs(qv - cv) : qv * cv);
                 }
                 wsample *e = &y[m * per_table + q * K + i];
                 e->v = s;

@@ -24,6 +24,7 @@ BOLT_ERR_DEVICE = -4
 BOLT_ERR_NOMEM = -5
 METRIC_L2 = 0
 METRIC_DOT = 1
+METRIC_L1 = 2
 TOPK_MAX_K = 2048
 ALPHAS = (0.0, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1)
 
@@ -61,6 +62,9 @@ _SIGS = {
     "bolt_scan_topk": ([_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "bolt_amm": ([_P, _I64, _I32, _P, _I64, _F32, _F32, _P, _I64, _I32, _P], ctypes.c_int),
     "bolt_scan_f32": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
+    "bolt_scan_topk_ranges_ws_bytes": ([_P, _I32, _I32, _I64, _I32], _SZ),
+    "bolt_scan_topk_ranges": ([_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _I32, _P, _P, _P, _SZ, _P],
+                              ctypes.c_int),
     "bolt_kmeans_ws_bytes": ([_I32, _I32, _I32], _SZ),
     "bolt_kmeans": ([_P, _I64, _I32, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "bolt_topk_f32": ([_P, _I64, _I64, _I64, _I32, _I32, _P, _P, _P], ctypes.c_int),
@@ -126,9 +130,9 @@ def _rows(t, name):
 
 
 def metric_id(metric):
-    if metric in (METRIC_L2, METRIC_DOT):
+    if metric in (METRIC_L2, METRIC_DOT, METRIC_L1):
         return int(metric)
-    return {"l2": METRIC_L2, "dot": METRIC_DOT}[metric]
+    return {"l2": METRIC_L2, "dot": METRIC_DOT, "l1": METRIC_L1}[metric]
 
 
 # ------------------------------------------------------------------ hot path
@@ -274,6 +278,26 @@ def bolt_scan_topk(codes, luts_u8, metric, k, vals=None, idx=None, ws=None, stre
     wsb = ws.numel() * ws.element_size()
     _check(_lib.bolt_scan_topk(_ptr(codes), N, M, _ptr(luts_u8), Q, metric_id(metric), k,
                                _ptr(vals), _ptr(idx), _ptr(ws), wsb, _stream(stream)))
+    return vals, idx
+
+
+def bolt_scan_topk_ranges(codes, luts_u8, metric, k, ranges, vals=None, idx=None, stream=None):
+    """Scan + top-k over the rows of `ranges` (host int64 [R, 2]: ascending,
+    disjoint [start, end) pairs); row indices refer to the whole codes."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(luts_u8, torch.uint8, "luts_u8")
+    N = codes.shape[0]
+    Q, M = luts_u8.shape[0], luts_u8.shape[1]
+    rg = np.ascontiguousarray(np.asarray(ranges, dtype=np.int64).reshape(-1, 2))
+    R = rg.shape[0]
+    if vals is None:
+        vals = torch.empty((Q, k), dtype=torch.uint16, device=codes.device)
+    if idx is None:
+        idx = torch.empty((Q, k), dtype=torch.int32, device=codes.device)
+    nws = int(_lib.bolt_scan_topk_ranges_ws_bytes(rg.ctypes.data, R, M, Q, k))
+    ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=codes.device)
+    _check(_lib.bolt_scan_topk_ranges(_ptr(codes), N, M, _ptr(luts_u8), Q, metric_id(metric), k, rg.ctypes.data,
+                                      R, _ptr(vals), _ptr(idx), _ptr(ws), nws, _stream(stream)))
     return vals, idx
 
 

@@ -170,7 +170,7 @@ int validate(const bolt_batch_db *dbs, int32_t n_db)
             return bolt::fail(BOLT_ERR_SHAPE, "database %d: bad N or Q", i);
         if (d.k < 1 || d.k > 256)
             return bolt::fail(BOLT_ERR_UNSUPPORTED, "database %d: k must be in [1, 256]", i);
-        if (d.metric != BOLT_METRIC_L2 && d.metric != BOLT_METRIC_DOT)
+        if (d.metric != BOLT_METRIC_L2 && d.metric != BOLT_METRIC_DOT && d.metric != BOLT_METRIC_L1)
             return bolt::fail(BOLT_ERR_INVALID, "database %d: bad metric", i);
         if (d.Q > 0 && (!d.luts || !d.vals || !d.idx || (d.N > 0 && !d.codes)))
             return bolt::fail(BOLT_ERR_INVALID, "database %d: null pointer", i);

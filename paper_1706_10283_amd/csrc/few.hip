@@ -87,7 +87,7 @@ template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void few_scan_topk_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int nq, uint32_t k,
     int largest, int64_t rows_per_block, int n_rb, uint64_t *__restrict__ cand,
-    uint32_t *__restrict__ gthr)
+    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
 {
     extern __shared__ __attribute__((aligned(16))) char few_lds[];
     bolt::TileJob job;
@@ -96,8 +96,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     job.cand = cand;
     job.gthr = gthr;
     job.rb = blockIdx.x;
-    job.r0 = job.rb * rows_per_block;
-    job.r1 = (job.r0 + rows_per_block) < N ? (job.r0 + rows_per_block) : N;
+    if (tiles) {   // row ranges given by the caller, cut into tiles
+        job.r0 = tiles[2 * job.rb];
+        job.r1 = tiles[2 * job.rb + 1];
+    } else {
+        job.r0 = job.rb * rows_per_block;
+        job.r1 = (job.r0 + rows_per_block) < N ? (job.r0 + rows_per_block) : N;
+    }
     job.n_rb = n_rb;
     job.q0 = 0;
     job.nq = nq;
@@ -115,7 +120,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
 template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void one_scan_topk_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k,
-    int largest, int64_t tile_rows, uint64_t *__restrict__ cand, uint32_t *__restrict__ gthr)
+    int largest, int64_t tile_rows, uint64_t *__restrict__ cand, uint32_t *__restrict__ gthr,
+    const int64_t *__restrict__ tiles)
 {
     constexpr int R = bolt::few_r(MM);
     constexpr int PASS = bolt::few_pass(MM);
@@ -126,8 +132,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void o
     __shared__ uint32_t s_cnt, s_bnd;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tile = blockIdx.x;
-    const int64_t r0 = tile * tile_rows;
-    const int64_t r1 = (r0 + tile_rows) < N ? (r0 + tile_rows) : N;
+    const int64_t r0 = tiles ? tiles[2 * tile] : tile * tile_rows;
+    const int64_t r1 = tiles ? tiles[2 * tile + 1] : ((r0 + tile_rows) < N ? (r0 + tile_rows) : N);
     uint32_t cw[R][MM / 8], nx[R][MM / 8];
     load_rows_clamped<MM, R>(codes, r0, r1, nx);
     build_pair_tables<MM>(luts, 1, pt, reinterpret_cast<uint8_t *>(buf));
@@ -204,14 +210,15 @@ void launch_few_scan(const uint8_t *codes, int64_t N, const uint8_t *luts, int n
 
 template <int MM>
 void launch_few_scan_topk(const uint8_t *codes, int64_t N, const uint8_t *luts, int nq, int k, bool largest,
-                          int64_t rpb, int n_rb, uint64_t *cand, uint32_t *gthr, hipStream_t s)
+                          int64_t rpb, int n_rb, uint64_t *cand, uint32_t *gthr, const int64_t *tiles,
+                          hipStream_t s)
 {
     if (nq == 1)
         hipLaunchKernelGGL(one_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), 0, s, codes, N, luts, (uint32_t)k,
-                           (int)largest, rpb, cand, gthr);
+                           (int)largest, rpb, cand, gthr, tiles);
     else
         hipLaunchKernelGGL(few_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), few_lds_bytes(MM, nq, true), s,
-                           codes, N, luts, nq, (uint32_t)k, (int)largest, rpb, n_rb, cand, gthr);
+                           codes, N, luts, nq, (uint32_t)k, (int)largest, rpb, n_rb, cand, gthr, tiles);
 }
 
 template <int MM>
@@ -316,16 +323,16 @@ int64_t few_rows_per_block(int64_t N, int M, int nq)
 
 // Stage 1 of the fused few-query path: candidates [Q][n_rb][k] and bounds.
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                  bool largest, int n_rb, uint64_t *cand, uint32_t *gthr, hipStream_t s)
+                  bool largest, int n_rb, uint64_t *cand, uint32_t *gthr, const int64_t *tiles, hipStream_t s)
 {
     const int nq = (int)Q;
     const int64_t rpb = few_rows_per_block(N, M, nq);
     bolt::ProfScope prof_("scan_topk_few", s);
     switch (M) {
-    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
-    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
-    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
-    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, s); break;
+    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, tiles, s); break;
+    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, tiles, s); break;
+    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, tiles, s); break;
+    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, gthr, tiles, s); break;
     default: return fail(BOLT_ERR_UNSUPPORTED, "few-query scan takes M in {8, 16, 32, 64}");
     }
     return BOLT_OK;

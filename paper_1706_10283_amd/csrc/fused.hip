@@ -20,6 +20,8 @@
 // Workgroups of one row block are placed on one XCD (consecutive workgroup
 // ids are dispatched round-robin to the 8 XCDs), so each XCD's L2 holds only
 // its share of the codes while all query blocks reuse them.
+#include <vector>
+
 #include "common.hpp"
 #include "scan_common.hpp"
 #include "tiles.hpp"
@@ -45,7 +47,7 @@ template <int MM, int NG>
 __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand,
-    uint32_t *__restrict__ gthr)
+    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
 {
     __shared__ bolt::GroupedLds<MM, NG> L;
     int qb, rb;
@@ -58,8 +60,13 @@ __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
     job.luts = luts;
     job.cand = cand;
     job.gthr = gthr;
-    job.r0 = (int64_t)rb * kRowsPerBlock;
-    job.r1 = (job.r0 + kRowsPerBlock) < N ? (job.r0 + kRowsPerBlock) : N;
+    if (tiles) {   // row ranges given by the caller, cut into tiles
+        job.r0 = tiles[2 * rb];
+        job.r1 = tiles[2 * rb + 1];
+    } else {
+        job.r0 = (int64_t)rb * kRowsPerBlock;
+        job.r1 = (job.r0 + kRowsPerBlock) < N ? (job.r0 + kRowsPerBlock) : N;
+    }
     job.rb = rb;
     job.n_rb = n_rb;
     job.q0 = (int64_t)qb * QB;
@@ -211,6 +218,16 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
 }
 
+// Result padding when no row is scanned: 65535 / 0 and index -1.
+__global__ void pad_topk_kernel(uint16_t *vals, int32_t *idx, int64_t n, int largest)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        vals[i] = (uint16_t)(largest ? 0u : 0xFFFFu);
+        idx[i] = -1;
+    }
+}
+
 // Bounds start open (65535: every d passes) and histograms empty.
 __global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, int64_t n_hist)
 {
@@ -263,31 +280,37 @@ struct FusedPlan {
     bool ok = false;
     int kind = 0;        // 1 few-query, 2 grouped
     int n_rb = 0, n_qb = 0, qb_size = 0, n_chunks = 1;
+    int64_t rpb = 0;     // rows per tile
     int64_t chunk = 0;
     size_t cand_bytes = 0, gthr_bytes = 0, hist_bytes = 0, level2_bytes = 0;
 };
 
-FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
+// The kernel for the shape and its rows per tile (N: rows to scan).
+bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
 {
-    FusedPlan p;
     const bool tuned_M = (M == 8 || M == 16 || M == 32 || M == 64);
     if (!tuned_M || !vec_ok || k > 256 || N <= 0 || Q <= 0)
-        return p;
+        return false;
     if (Q < bolt::kSmallQ && bolt::few_fused_lds_bytes(M, (int)Q) <= 160 * 1024) {
-        const int64_t rpb = bolt::few_rows_per_block(N, M, (int)Q);
-        p.n_rb = (int)((N + rpb - 1) / rpb);
+        p.rpb = bolt::few_rows_per_block(N, M, (int)Q);
         p.kind = 1;
         p.n_qb = 1;
         p.qb_size = (int)Q;
     } else {
-        p.n_rb = (int)((N + kRowsPerBlock - 1) / kRowsPerBlock);
+        p.rpb = kRowsPerBlock;
         p.kind = 2;
         const int ng = M <= 32 ? 2 : 1;
         p.qb_size = 8 * ng;
         p.n_qb = (int)((Q + p.qb_size - 1) / p.qb_size);
-        if ((int64_t)p.n_qb * ((p.n_rb + 7) / 8) * 8 > INT32_MAX)
-            return p;
     }
+    return true;
+}
+
+// Workspace layout once the number of tiles p.n_rb is known.
+FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
+{
+    if (p.kind == 2 && (int64_t)p.n_qb * ((p.n_rb + 7) / 8) * 8 > INT32_MAX)
+        return p;
     p.cand_bytes = align256((size_t)Q * p.n_rb * k * sizeof(uint64_t));
     p.gthr_bytes = align256((size_t)Q * sizeof(uint32_t));
     p.hist_bytes = align256((size_t)Q * bolt::kHistBins * sizeof(uint32_t));
@@ -307,19 +330,28 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
     return p;
 }
 
+FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
+{
+    FusedPlan p;
+    if (!plan_kind(N, M, Q, k, vec_ok, p))
+        return p;
+    p.n_rb = (int)((N + p.rpb - 1) / p.rpb);
+    return plan_finish(p, Q, k);
+}
+
 template <int MM>
 void launch_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
-                  int k, int largest, uint64_t *cand, uint32_t *gthr, hipStream_t s)
+                  int k, int largest, uint64_t *cand, uint32_t *gthr, const int64_t *tiles, hipStream_t s)
 {
     if (p.kind == 1) {
-        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, p.n_rb, cand, gthr, s);
+        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, p.n_rb, cand, gthr, tiles, s);
         return;
     }
     const unsigned grid = (unsigned)(p.n_qb * ((p.n_rb + 7) / 8 * 8));
     {
         bolt::ProfScope prof_("scan_topk_grouped", s);
         hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes,
-                           N, luts, Q, (uint32_t)k, largest, p.n_rb, p.n_qb, cand, gthr);
+                           N, luts, Q, (uint32_t)k, largest, p.n_rb, p.n_qb, cand, gthr, tiles);
     }
 }
 
@@ -340,19 +372,12 @@ size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
     return p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
 }
 
-// Fused scan + top-k; returns BOLT_ERR_UNSUPPORTED when the shape has no fused kernel.
-int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                    bool largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
-                    hipStream_t s)
+// Launches of a planned fused scan + top-k (tiles: null, or the caller's
+// row ranges cut into p.n_rb tiles, already in device memory).
+static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M, const uint8_t *luts,
+                     int64_t Q, int k, bool largest, uint16_t *vals, int32_t *idx, char *w,
+                     const int64_t *tiles, hipStream_t s)
 {
-    const bool vec_ok = aligned(codes, 16) && aligned(luts, 16);
-    FusedPlan p = plan_fused(N, M, Q, k, vec_ok);
-    if (!p.ok)
-        return BOLT_ERR_UNSUPPORTED;
-    const size_t need = p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
-    if (ws_bytes < need || !aligned(ws, 256))
-        return fail(BOLT_ERR_NOMEM, "fused scan+top-k needs %zu workspace bytes", need);
-    char *w = reinterpret_cast<char *>(ws);
     uint64_t *cand = reinterpret_cast<uint64_t *>(w);
     uint32_t *gthr = reinterpret_cast<uint32_t *>(w + p.cand_bytes);
     uint32_t *hist = reinterpret_cast<uint32_t *>(w + p.cand_bytes + p.gthr_bytes);
@@ -363,19 +388,18 @@ int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts,
     hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
                        hist, n_hist);
     switch (M) {
-    case 8: launch_fused<8>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
-    case 16: launch_fused<16>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
-    case 32: launch_fused<32>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
-    case 64: launch_fused<64>(p, codes, N, luts, Q, k, largest, cand, gthr, s); break;
+    case 8: launch_fused<8>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
+    case 16: launch_fused<16>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
+    case 32: launch_fused<32>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
+    case 64: launch_fused<64>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
     }
+    const int64_t per_query = (int64_t)p.n_rb * k;
     {
         bolt::ProfScope prof_("cand_hist", s);
-        const int64_t per_query = (int64_t)p.n_rb * k;
         const int64_t hchunk = 4096;
         hipLaunchKernelGGL(cand_hist_kernel, dim3((unsigned)Q, (unsigned)((per_query + hchunk - 1) / hchunk)),
                            dim3(256), 0, s, cand, per_query, hchunk, bolt::hist_shift(M), hist);
     }
-    const int64_t per_query = (int64_t)p.n_rb * k;
     const uint32_t smax = 255u * (uint32_t)M;
     bolt::ProfScope prof_("topk_merge", s);
     hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand,
@@ -385,6 +409,88 @@ int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts,
         hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
                            p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx);
     return check_launch("bolt_scan_topk (fused)");
+}
+
+static size_t plan_bytes(const FusedPlan &p) { return p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes; }
+
+// Fused scan + top-k; returns BOLT_ERR_UNSUPPORTED when the shape has no fused kernel.
+int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
+                    bool largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
+                    hipStream_t s)
+{
+    const bool vec_ok = aligned(codes, 16) && aligned(luts, 16);
+    FusedPlan p = plan_fused(N, M, Q, k, vec_ok);
+    if (!p.ok)
+        return BOLT_ERR_UNSUPPORTED;
+    const size_t need = plan_bytes(p);
+    if (ws_bytes < need || !aligned(ws, 256))
+        return fail(BOLT_ERR_NOMEM, "fused scan+top-k needs %zu workspace bytes", need);
+    return run_fused(p, codes, N, M, luts, Q, k, largest, vals, idx, reinterpret_cast<char *>(ws), nullptr, s);
+}
+
+// Row ranges: the tiles of [start, end) ranges of at most p.rpb rows each.
+static void range_tiles(const int64_t *ranges, int n_ranges, int64_t rpb, std::vector<int64_t> &tiles)
+{
+    tiles.clear();
+    for (int r = 0; r < n_ranges; ++r)
+        for (int64_t a = ranges[2 * r]; a < ranges[2 * r + 1]; a += rpb) {
+            tiles.push_back(a);
+            tiles.push_back(a + rpb < ranges[2 * r + 1] ? a + rpb : ranges[2 * r + 1]);
+        }
+}
+
+// Plan of a ranges call (p.ok false: no fused kernel for the shape).
+static FusedPlan plan_ranges(const int64_t *ranges, int n_ranges, int M, int64_t Q, int k, bool vec_ok,
+                             std::vector<int64_t> &tiles, size_t *tiles_bytes)
+{
+    FusedPlan p;
+    int64_t rows = 0;
+    for (int r = 0; r < n_ranges; ++r)
+        rows += ranges[2 * r + 1] - ranges[2 * r];
+    if (!plan_kind(rows > 0 ? rows : 1, M, Q, k, vec_ok, p))
+        return p;
+    range_tiles(ranges, n_ranges, p.rpb, tiles);
+    p.n_rb = (int)(tiles.size() / 2);
+    if (p.n_rb == 0)
+        return p;
+    *tiles_bytes = align256(tiles.size() * sizeof(int64_t));
+    return plan_finish(p, Q, k);
+}
+
+size_t ranges_ws_bytes(const int64_t *ranges, int n_ranges, int M, int64_t Q, int k)
+{
+    std::vector<int64_t> tiles;
+    size_t tb = 0;
+    FusedPlan p = plan_ranges(ranges, n_ranges, M, Q, k, true, tiles, &tb);
+    return p.ok ? plan_bytes(p) + tb : 0;
+}
+
+int scan_topk_ranges(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
+                     bool largest, const int64_t *ranges, int n_ranges, uint16_t *vals, int32_t *idx, void *ws,
+                     size_t ws_bytes, hipStream_t s)
+{
+    const bool vec_ok = aligned(codes, 16) && aligned(luts, 16);
+    std::vector<int64_t> tiles;
+    size_t tb = 0;
+    FusedPlan p = plan_ranges(ranges, n_ranges, M, Q, k, vec_ok, tiles, &tb);
+    if (p.n_rb == 0 && p.kind != 0) {
+        // no rows at all: the padding of an empty database
+        hipLaunchKernelGGL(pad_topk_kernel, dim3((unsigned)((Q * k + 255) / 256)), dim3(256), 0, s, vals, idx,
+                           Q * k, (int)largest);
+        return check_launch("bolt_scan_topk_ranges");
+    }
+    if (!p.ok)
+        return fail(BOLT_ERR_UNSUPPORTED, "row-range scans need M in {8, 16, 32, 64}, k <= 256 and 16-byte "
+                                          "aligned codes and tables");
+    const size_t need = plan_bytes(p) + tb;
+    if (ws_bytes < need || !ws || !aligned(ws, 256))
+        return fail(BOLT_ERR_NOMEM, "row-range scan needs %zu workspace bytes", need);
+    char *w = reinterpret_cast<char *>(ws);
+    int64_t *dtiles = reinterpret_cast<int64_t *>(w + plan_bytes(p));
+    if (hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return check_launch("bolt_scan_topk_ranges (tile list)");
+    return run_fused(p, codes, N, M, luts, Q, k, largest, vals, idx, w, dtiles, s);
 }
 
 }  // namespace bolt

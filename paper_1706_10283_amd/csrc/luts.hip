@@ -31,6 +31,9 @@ __global__ __launch_bounds__(256) void luts_kernel(
             float t = qv[j] - c[j];
             acc = __builtin_fmaf(t, t, acc);
         }
+    } else if (metric == BOLT_METRIC_L1) {
+        for (int j = 0; j < sub; ++j)
+            acc = acc + __builtin_fabsf(qv[j] - c[j]);
     } else {
         for (int j = 0; j < sub; ++j)
             acc = __builtin_fmaf(qv[j], c[j], acc);
@@ -56,8 +59,8 @@ extern "C" int bolt_build_luts(const float *Qv, int64_t Q, int32_t J, int64_t ld
     using namespace bolt;
     BOLT_TRY(check_JM(J, M));
     BOLT_TRY(check_N(Q, "Q"));
-    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT)
-        return fail(BOLT_ERR_INVALID, "metric must be 0 (L2) or 1 (dot), got %d", metric);
+    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT && metric != BOLT_METRIC_L1)
+        return fail(BOLT_ERR_INVALID, "metric must be 0 (L2), 1 (dot) or 2 (L1), got %d", metric);
     if (ldq < J)
         return fail(BOLT_ERR_INVALID, "ldq (%lld) < J (%d)", (long long)ldq, J);
     if (luts_u8 && !(a > 0.0f))

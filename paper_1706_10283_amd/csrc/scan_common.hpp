@@ -22,6 +22,11 @@ int scan_u16(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_
 // the launch (BOLT_ERR_UNSUPPORTED if it has none).
 bool fused_supported(int64_t N, int M, int64_t Q, int k, bool vec_ok);
 size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k);
+// The same over caller-given row ranges (host int64 [n_ranges][2]).
+size_t ranges_ws_bytes(const int64_t *ranges, int n_ranges, int M, int64_t Q, int k);
+int scan_topk_ranges(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
+                     bool largest, const int64_t *ranges, int n_ranges, uint16_t *vals, int32_t *idx, void *ws,
+                     size_t ws_bytes, hipStream_t s);
 int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
                     bool largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
                     hipStream_t s);
@@ -34,7 +39,7 @@ int few_scan(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_
 int64_t few_rows_per_block(int64_t N, int M, int nq);
 size_t few_fused_lds_bytes(int M, int nq);
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                  bool largest, int n_rb, uint64_t *cand, uint32_t *gthr, hipStream_t s);
+                  bool largest, int n_rb, uint64_t *cand, uint32_t *gthr, const int64_t *tiles, hipStream_t s);
 
 // Test hook: 1 forces the unfused scan-then-select path of bolt_scan_topk.
 extern int g_force_unfused_topk;

@@ -296,8 +296,8 @@ extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const 
     using namespace bolt;
     BOLT_TRY(check_M(M));
     BOLT_TRY(validate_topk(Q, N, k));
-    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT)
-        return fail(BOLT_ERR_INVALID, "metric must be 0 or 1 (got %d)", metric);
+    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT && metric != BOLT_METRIC_L1)
+        return fail(BOLT_ERR_INVALID, "metric must be 0, 1 or 2 (got %d)", metric);
     if (Q == 0)
         return BOLT_OK;
     if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
@@ -319,6 +319,51 @@ extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const 
     if (N > 0)
         BOLT_TRY(scan_u16(codes, N, M, luts_u8, Q, d, N, s));
     return topk_u16(d, Q, N, N, k, largest, vals, idx, s);
+}
+
+static int validate_ranges(const int64_t *ranges, int32_t n_ranges, int64_t N)
+{
+    using namespace bolt;
+    if (n_ranges < 0)
+        return fail(BOLT_ERR_INVALID, "n_ranges must be >= 0 (got %d)", n_ranges);
+    if (n_ranges > 0 && !ranges)
+        return fail(BOLT_ERR_INVALID, "ranges is null");
+    int64_t prev_end = 0;
+    for (int32_t r = 0; r < n_ranges; ++r) {
+        const int64_t a = ranges[2 * r], b = ranges[2 * r + 1];
+        if (a < prev_end || b < a || b > N)
+            return fail(BOLT_ERR_INVALID,
+                        "range %d = [%lld, %lld): ranges must be ascending, disjoint and inside [0, %lld]", r,
+                        (long long)a, (long long)b, (long long)N);
+        prev_end = b;
+    }
+    return BOLT_OK;
+}
+
+extern "C" size_t bolt_scan_topk_ranges_ws_bytes(const int64_t *ranges, int32_t n_ranges, int32_t M, int64_t Q,
+                                                 int32_t k)
+{
+    if (n_ranges <= 0 || !ranges || Q <= 0)
+        return 0;
+    return bolt::ranges_ws_bytes(ranges, n_ranges, M, Q, k);
+}
+
+extern "C" int bolt_scan_topk_ranges(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                                     int64_t Q, int32_t metric, int32_t k, const int64_t *ranges, int32_t n_ranges,
+                                     uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes, void *stream)
+{
+    using namespace bolt;
+    BOLT_TRY(check_M(M));
+    BOLT_TRY(validate_topk(Q, N, k));
+    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT && metric != BOLT_METRIC_L1)
+        return fail(BOLT_ERR_INVALID, "metric must be 0, 1 or 2 (got %d)", metric);
+    BOLT_TRY(validate_ranges(ranges, n_ranges, N));
+    if (Q == 0)
+        return BOLT_OK;
+    if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
+        return fail(BOLT_ERR_INVALID, "bolt_scan_topk_ranges: null pointer");
+    return scan_topk_ranges(codes, N, M, luts_u8, Q, k, metric == BOLT_METRIC_DOT, ranges, n_ranges, vals, idx,
+                            ws, ws_bytes, as_stream(stream));
 }
 
 // Test hook: 1 forces bolt_scan_topk onto the scan-then-select path.

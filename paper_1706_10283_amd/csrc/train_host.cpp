@@ -161,7 +161,8 @@ int learn_quantizer(const float *Qt, int64_t nq, int J, int64_t ldq, const uint8
                 for (int j = 0; j < sub; ++j) {
                     const double qv = Qt[q * ldq + (int64_t)m * sub + j];
                     const double cv = C[((int64_t)m * K + i) * sub + j];
-                    d += metric == BOLT_METRIC_L2 ? (qv - cv) * (qv - cv) : qv * cv;
+                    d += metric == BOLT_METRIC_L2 ? (qv - cv) * (qv - cv)
+                                                  : (metric == BOLT_METRIC_L1 ? std::fabs(qv - cv) : qv * cv);
                 }
                 ws.s.push_back({d, count[(size_t)m * K + i]});
             }
@@ -250,8 +251,8 @@ extern "C" int bolt_learn_quantizer_host(const float *Qt, int64_t nq, int32_t J,
 {
     using namespace bolt;
     BOLT_TRY(check_JM(J, M));
-    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT)
-        return fail(BOLT_ERR_INVALID, "metric must be 0 or 1");
+    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT && metric != BOLT_METRIC_L1)
+        return fail(BOLT_ERR_INVALID, "metric must be 0 (L2), 1 (dot) or 2 (L1)");
     if (nq < 1 || n < 1 || nalpha < 1 || ldq < J)
         return fail(BOLT_ERR_INVALID, "need nq >= 1, n >= 1, nalpha >= 1 and ldq >= J");
     if (!Qt || !codes || !centroids || !alphas || !a || !offsets)

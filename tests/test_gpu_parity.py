@@ -103,7 +103,7 @@ def test_encode_gap_report(bolt):
 
 # ------------------------------------------------------------------ tables
 
-@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("metric", ["l2", "dot", "l1"])
 @pytest.mark.parametrize("Q,J,M", [(1, 32, 8), (17, 128, 32), (100, 64, 16), (5, 256, 16),
                                    (9, 6, 2), (3, 256, 256)])
 def test_luts_parity(bolt, metric, Q, J, M):
@@ -120,7 +120,7 @@ def test_luts_parity(bolt, metric, Q, J, M):
     f32 = f32.cpu().numpy()
     assert np.array_equal(u8.cpu().numpy(), l8)
     assert np.array_equal(f32.view(np.uint32), l32.view(np.uint32))
-    if metric == "l2":
+    if metric in ("l2", "l1"):
         assert (np.abs(f32 - l64) <= 1e-5 * l64 + 1e-30).all()
     else:
         sub = J // M
@@ -248,7 +248,7 @@ def test_amm_parity(bolt, transpose, K):
 
 # ------------------------------------------------------------------ end to end
 
-@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("metric", ["l2", "dot", "l1"])
 def test_end_to_end_tiny_workload(bolt, metric):
     """The tiny workload: 10k x 32 N(0,1), M = 8, 16 queries, top-10, every
     intermediate equal to the oracle."""

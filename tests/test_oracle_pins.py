@@ -445,3 +445,25 @@ def test_topk_f32_lexsort(largest):
     v, i = oracle.topk_f32(d[:, :3], 5, largest)
     assert (i[:, 3:] == -1).all()
     assert (v[:, 3:] == (-np.inf if largest else np.inf)).all()
+
+
+def test_lut_l1_closed_form_and_fp32():
+    """L1 tables (the L_p distance with p = 1, eq. distFuncForm): the fp64
+    entries selected by h(x) sum to ||q - x_hat||_1, and the fp32 entries are
+    the ascending-j fp32 sum of |q_j - c_j|."""
+    J, M = 64, 16
+    X = synth.normal(91, (64, J))
+    Qv = synth.normal(92, (8, J))
+    C = synth.normal(93, (M, 16, J // M))
+    codes = oracle.encode(X, C, M)
+    cu = _unpack(codes, M)
+    xh = _reconstruct(cu, C)
+    l64, l32, _ = oracle.luts(Qv, C, M, "l1")
+    for q in range(len(Qv)):
+        s = l64[q][np.arange(M)[None, :], cu].sum(1)
+        np.testing.assert_allclose(s, np.abs(Qv[q].astype(np.float64)[None] - xh).sum(1), rtol=1e-12)
+    sub = J // M
+    ref = np.zeros((8, M, 16), dtype=np.float32)
+    for j in range(sub):
+        ref = ref + np.abs(Qv.reshape(8, M, 1, sub)[..., j] - C[None, :, :, j]).astype(np.float32)
+    assert np.array_equal(l32.view(np.uint32), ref.view(np.uint32))
