@@ -50,6 +50,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs at 2.4 GHz, 64 lanes per CU and clock (32-bit VALU ops)
 VALU_LANE_OPS = 256 * 64 * 2.4e9
+MFMA_I8_OPS = 5.0e15                 # MI355X dense int8 matrix-core peak (ops/s)
 HBM_PEAK_GBPS = 8000.0
 
 # HBM traffic of the dominant kernel, from two rocprofv3 --pmc runs of this
@@ -186,10 +187,17 @@ def headline(args, torch, B, W, M=None, steps=None, warmup=None, extras=True):
     dists = 2.0 * Q * N
     value = dists / (ms_per_step * 1e-3) / 1e9
 
-    dom = [n for n in ("scan_topk_grouped", "scan_topk_few") if n in prof][0]
+    dom = [n for n in ("scan_topk_mfma", "scan_topk_grouped", "scan_topk_few") if n in prof][0]
     dom_ms = prof[dom][1] / prof[dom][0]
     lookups = float(Q) * N * M                      # one table lookup-and-add per (q, n, m)
-    achieved = lookups / (dom_ms * 1e-3)
+    if dom == "scan_topk_mfma":
+        # the one-hot contraction: 16 M int8 multiply-adds per (query, vector)
+        ops, peak, bound = 2.0 * 16 * lookups, MFMA_I8_OPS, "mfma"
+        op = "int8 matrix-core multiply-add of the one-hot codes with the tables (2 ops, 16 per lookup)"
+    else:
+        ops, peak, bound = lookups, VALU_LANE_OPS, "alu"
+        op = "table lookup-and-add (one per query, vector and subspace)"
+    achieved = ops / (dom_ms * 1e-3)
     enc_ms = prof["encode"][1] / prof["encode"][0]
     traffic = traffic_bytes(dom, {"N": N, "J": J, "M": M, "Q": Q, "k": k})
     res = {
@@ -213,13 +221,14 @@ def headline(args, torch, B, W, M=None, steps=None, warmup=None, extras=True):
         "scan_topk_G_distances_per_s": round(Q * N / (dom_ms * 1e-3) / 1e9, 2),
         "kernels": kern,
         "roofline": {
-            "bound": "alu",
+            "bound": bound,
             "kernel": dom,
             "achieved": round(achieved / 1e12, 3),
-            "peak": round(VALU_LANE_OPS / 1e12, 2),
+            "peak": round(peak / 1e12, 2),
             "unit": "TOP/s",
-            "op": "table lookup-and-add (one per query, vector and subspace)",
-            "frac": round(achieved / VALU_LANE_OPS, 4),
+            "op": op,
+            "frac": round(achieved / peak, 4),
+            "lookups_T_per_s": round(lookups / (dom_ms * 1e-3) / 1e12, 3),
             "traffic": None if traffic is None else round(traffic),
             "traffic_unit": "HBM bytes per launch (fetch + write)",
             "algorithmic_bytes": N * M // 2 + Q * M * 16,
@@ -317,7 +326,8 @@ def run_msweep(args, torch, B, W):
         out["M%d" % M] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
                           "encode_GBps": r["encode_GBps"],
                           "scan_topk_G_distances_per_s": r["scan_topk_G_distances_per_s"],
-                          "kernels": r["kernels"], "lookup_frac": r["roofline"]["frac"]}
+                          "kernels": r["kernels"], "roofline_bound": r["roofline"]["bound"],
+                          "roofline_frac": r["roofline"]["frac"]}
         log("M=%d: %.1f G distances/s" % (M, r["value"]))
     return out
 

@@ -373,12 +373,22 @@ int bolt_prof_read(char *names, size_t cap, int32_t reset);
 
 /*
  * Test hooks (not part of the hot path): pin the scan kernel (-1 automatic,
- * 0 plain loop, 1 pair tables for few queries, 2 grouped) and route
- * bolt_scan_topk through the unfused scan-then-select path (on != 0).
- * Process-wide settings, not thread-safe.
+ * 0 plain loop, 1 pair tables for few queries, 2 grouped), route
+ * bolt_scan_topk through the unfused scan-then-select path (on != 0), and
+ * pin the kernel of fused scans with many queries (-1 automatic, 2 grouped
+ * LDS tables, 3 int8 matrix cores; 3 applies only where k <= 128, otherwise
+ * the grouped kernel runs).  Process-wide settings, not thread-safe.
  */
 int bolt_debug_force_scan_kernel(int32_t kind);
 int bolt_debug_force_unfused_topk(int32_t on);
+int bolt_debug_force_fused_kind(int32_t kind);
+/*
+ * Test hook: speculative starting bounds of fused scans with many queries
+ * over a whole database (-1 automatic from 2^19 rows, 0 off, 1 on from 2^17
+ * rows, 2 as 1 with every bound made to fail, so that every query takes the
+ * exact recomputation).  Results are the same in every mode.
+ */
+int bolt_debug_speculation(int32_t mode);
 
 #ifdef __cplusplus
 }

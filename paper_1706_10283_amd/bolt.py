@@ -74,6 +74,8 @@ _SIGS = {
                                    _P, _P, _P], ctypes.c_int),
     "bolt_debug_force_scan_kernel": ([_I32], ctypes.c_int),
     "bolt_debug_force_unfused_topk": ([_I32], ctypes.c_int),
+    "bolt_debug_force_fused_kind": ([_I32], ctypes.c_int),
+    "bolt_debug_speculation": ([_I32], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -361,6 +363,16 @@ def bolt_learn_quantizer_host(Qt, codes, centroids, metric, alphas=ALPHAS):
 def debug_force_unfused_topk(on: bool):
     """Test hook: route bolt_scan_topk through scan + bolt_topk."""
     _check(_lib.bolt_debug_force_unfused_topk(1 if on else 0))
+
+
+def debug_force_fused_kind(kind: int):
+    """Test hook: many-query fused kernel, -1 automatic, 2 grouped, 3 matrix cores."""
+    _check(_lib.bolt_debug_force_fused_kind(kind))
+
+
+def debug_speculation(mode: int):
+    """Test hook: speculative bounds, -1 automatic, 0 off, 1 on, 2 on and failing."""
+    _check(_lib.bolt_debug_speculation(mode))
 
 
 def debug_force_scan_kernel(kind: int):

@@ -20,6 +20,7 @@
 // Workgroups of one row block are placed on one XCD (consecutive workgroup
 // ids are dispatched round-robin to the 8 XCDs), so each XCD's L2 holds only
 // its share of the codes while all query blocks reuse them.
+#include <cmath>
 #include <vector>
 
 #include "common.hpp"
@@ -33,6 +34,7 @@ using bolt::load_row;
 using bolt::PruneResult;
 
 constexpr int kRowsPerBlock = 16384;      // rows per workgroup (<= 65536: 16-bit local rows)
+constexpr int64_t kMfmaMinQ = 32;         // queries from which the matrix-core tiles are used
 constexpr int64_t kMergeChunk = 16384;    // keys per first-level merge workgroup
 
 // Decode the tile of workgroup `w`: XCD-major placement of row blocks.
@@ -43,19 +45,18 @@ __device__ __forceinline__ void tile_of(int w, int n_qb, int &qb, int &rb)
     rb = (i / n_qb) * 8 + xcd;
 }
 
-template <int MM, int NG>
-__global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
-    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
-    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand,
-    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
+// The tile of workgroup w (qb_size queries, rows of row block rb: the
+// caller's tile list, or span rows from rb * stride); false if the
+// workgroup has no tile (padding of the XCD placement).
+__device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uint8_t *codes, int64_t N,
+                                         const uint8_t *luts, int64_t Q, uint32_t k, int largest, int n_rb,
+                                         uint64_t *cand, uint32_t *gthr, const int64_t *tiles, int64_t stride,
+                                         int64_t span, bolt::TileJob &job)
 {
-    __shared__ bolt::GroupedLds<MM, NG> L;
     int qb, rb;
-    tile_of(blockIdx.x, n_qb, qb, rb);
+    tile_of(w, n_qb, qb, rb);
     if (rb >= n_rb)
-        return;
-    constexpr int QB = 8 * NG;
-    bolt::TileJob job;
+        return false;
     job.codes = codes;
     job.luts = luts;
     job.cand = cand;
@@ -64,16 +65,43 @@ __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
         job.r0 = tiles[2 * rb];
         job.r1 = tiles[2 * rb + 1];
     } else {
-        job.r0 = (int64_t)rb * kRowsPerBlock;
-        job.r1 = (job.r0 + kRowsPerBlock) < N ? (job.r0 + kRowsPerBlock) : N;
+        job.r0 = (int64_t)rb * stride;
+        job.r1 = (job.r0 + span) < N ? (job.r0 + span) : N;
     }
     job.rb = rb;
     job.n_rb = n_rb;
-    job.q0 = (int64_t)qb * QB;
-    job.nq = (int)((Q - job.q0) < QB ? (Q - job.q0) : QB);
+    job.q0 = (int64_t)qb * qb_size;
+    job.nq = (int)((Q - job.q0) < qb_size ? (Q - job.q0) : qb_size);
     job.k = k;
     job.largest = largest;
-    bolt::grouped_tile<MM, NG>(job, L);
+    return true;
+}
+
+template <int MM, int NG>
+__global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
+    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand,
+    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
+{
+    __shared__ bolt::GroupedLds<MM, NG> L;
+    bolt::TileJob job;
+    if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span,
+                 job))
+        bolt::grouped_tile<MM, NG>(job, L);
+}
+
+// Matrix-core tiles: 32 NT queries per workgroup (tables in registers).
+template <int MM, int NT>
+__global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
+    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand,
+    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
+{
+    __shared__ bolt::MfmaLds<NT> L;
+    bolt::TileJob job;
+    if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span,
+                 job))
+        bolt::mfma_tile<MM, NT>(job, L);
 }
 
 // ------------------------------------------------------------------ merge
@@ -137,7 +165,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
                                                          int largest, uint32_t smax, uint64_t *__restrict__ dst,
                                                          uint32_t *__restrict__ dst_cnt,
                                                          uint16_t *__restrict__ vals,
-                                                         int32_t *__restrict__ idx)
+                                                         int32_t *__restrict__ idx, uint32_t *__restrict__ fail)
 {
     __shared__ bolt::MergeLds L;
     const int64_t q = blockIdx.x;
@@ -155,6 +183,8 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
     __syncthreads();
     const uint32_t n = bolt::merge_collect(L, cand + q * per_query, c_lo, c_hi, k, L.misc);
     if (gridDim.y == 1) {
+        if (fail && threadIdx.x == 0 && n < k)
+            fail[q] = 1u;
         bolt::merge_emit(L, n, k, largest, smax, vals + q * k, idx + q * k);
         return;
     }
@@ -171,7 +201,8 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
                                                           const uint32_t *__restrict__ src_cnt, int n_chunks,
                                                           uint32_t k, const uint32_t *__restrict__ gthr,
                                                           int largest, uint32_t smax,
-                                                          uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+                                                          uint16_t *__restrict__ vals, int32_t *__restrict__ idx,
+                                                          uint32_t *__restrict__ fail)
 {
     __shared__ bolt::MergeLds L;
     const int64_t q = blockIdx.x;
@@ -212,6 +243,8 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
         }
     }
     uint32_t n = L.mcnt;
+    if (fail && tid == 0 && n < k)
+        fail[q] = 1u;
     if (tid < 64 && n > k)
         bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
     __syncthreads();
@@ -228,12 +261,16 @@ __global__ void pad_topk_kernel(uint16_t *vals, int32_t *idx, int64_t n, int lar
     }
 }
 
-// Bounds start open (65535: every d passes) and histograms empty.
-__global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, int64_t n_hist)
+// Bounds start open (65535: every d passes), histograms empty and no query
+// failed (fail: the failure flags of speculative bounds, if any).
+__global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, int64_t n_hist, uint32_t *fail)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < Q)
+    if (i < Q) {
         gthr[i] = 0xFFFFu;
+        if (fail)
+            fail[i] = 0u;
+    }
     if (i < n_hist)
         hist[i] = 0;
 }
@@ -263,11 +300,116 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restri
             atomicAdd(&hist[q * bolt::kHistBins + i], h[i]);
 }
 
+// Sample distances (speculative bounds): workgroup (query block, chunk c)
+// writes the d of its queries over rows [c * stride, c * stride + span) to
+// out[q][c * span ...].
+template <int MM, int NT>
+__global__ __launch_bounds__(256) void spec_sample_kernel(const uint8_t *__restrict__ codes,
+                                                          const uint8_t *__restrict__ luts, int64_t Q, int largest,
+                                                          int64_t stride, int64_t span, int64_t S,
+                                                          uint16_t *__restrict__ out)
+{
+    __shared__ uint4 onehot[16];
+    const int64_t q0 = (int64_t)blockIdx.x * 32 * NT;
+    const int nq = (int)((Q - q0) < 32 * NT ? (Q - q0) : 32 * NT);
+    const int64_t c = blockIdx.y;
+    bolt::mfma_sample_tile<MM, NT>(codes, luts, q0, nq, largest, c * stride, span, out, S, c * span, onehot);
+}
+
+// Speculative bound of one query (one workgroup): histogram of its S sample
+// distances and the upper edge of the bin holding the r-th smallest, written
+// as the query's starting bound (0 when a test forces every query onto the
+// recomputation).
+__global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ dists, int64_t S,
+                                                          uint32_t r, int shift, uint32_t *__restrict__ gthr,
+                                                          int force_fail)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+        h[i] = 0;
+    __syncthreads();
+    const int64_t q = blockIdx.x;
+    const uint4 *d = reinterpret_cast<const uint4 *>(dists + q * S);   // 8 distances per load
+    for (int64_t i = threadIdx.x; i < S / 8; i += 256) {
+        const uint4 v = d[i];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            atomicAdd(&h[(w[j] & 0xFFFFu) >> shift], 1u);
+            atomicAdd(&h[(w[j] >> 16) >> shift], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t b = hist_bound(h, r, shift, 0xFFFFu);
+        if (threadIdx.x == 0)
+            gthr[q] = force_fail ? 0u : b;
+    }
+}
+
+// Exact top-k of one query whose speculative bound failed (fewer than k
+// rows passed it): one workgroup scans every row with the query's table in
+// LDS, appends keys (d << 32 | row) below the running bound and prunes by
+// the merge's scheme, then writes the sorted result over the merged one.
+// Workgroups of queries that did not fail return at once.
+__global__ __launch_bounds__(256) void topk_redo_kernel(const uint8_t *__restrict__ codes, int64_t N, int M,
+                                                        const uint8_t *__restrict__ luts, uint32_t k, int largest,
+                                                        const uint32_t *__restrict__ fail,
+                                                        uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    const int64_t q = blockIdx.x;
+    if (!fail[q])
+        return;
+    __shared__ bolt::MergeLds L;
+    __shared__ uint16_t tab[64 * 16];   // d contribution of (subspace, code)
+    const int tid = threadIdx.x;
+    for (int e = tid; e < M * 16; e += 256) {
+        const uint32_t v = luts[q * M * 16 + e];
+        tab[e] = (uint16_t)(largest ? 255u - v : v);
+    }
+    if (tid == 0) {
+        L.mcnt = 0;
+        L.mbound = ~0ull;
+    }
+    __syncthreads();
+    const int half = M / 2;
+    for (int64_t c0 = 0; c0 < N; c0 += 256 * bolt::kMergeE) {
+        const uint64_t bnd = L.mbound;
+        for (int e = 0; e < bolt::kMergeE; ++e) {
+            const int64_t row = c0 + tid + 256 * e;
+            if (row < N) {
+                const uint8_t *pr = codes + row * half;
+                uint32_t d = 0;
+                for (int b = 0; b < half; ++b) {
+                    const uint32_t byte = pr[b];
+                    d += tab[(2 * b) * 16 + (byte & 15u)] + tab[(2 * b + 1) * 16 + (byte >> 4)];
+                }
+                const uint64_t key = ((uint64_t)d << 32) | (uint64_t)row;
+                if (key < bnd) {
+                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                    L.mb[pos] = key;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < 64 && L.mcnt > bolt::kMergeCap - 256 * bolt::kMergeE) {
+            const uint64_t kth = bolt::prune_u64<bolt::kMergeCap>(L.mb, L.mcnt, k);
+            if (tid == 0) {
+                L.mcnt = k;
+                L.mbound = kth + 1;
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t n = L.mcnt;
+    if (tid < 64 && n > k)
+        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
+    __syncthreads();
+    bolt::merge_emit(L, n > k ? k : n, k, largest, 255u * (uint32_t)M, vals + q * k, idx + q * k);
+}
+
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Grouped-kernel shapes: (candidate slots, query groups of 8) such that the
-// tables (NG * M * 256 bytes) and buffers (NG * 8 * CAP * 4 bytes) fit two
-// workgroups per CU.  CAP - 256 bounds k (one pass appends at most 256).
 // Query groups per grouped tile: tables (NG * M * 256 bytes) and candidate
 // buffers (NG * 8 * 512 * 4 bytes) within about 48 KB, three workgroups per CU.
 template <int MM>
@@ -276,13 +418,32 @@ constexpr int ng_for()
     return MM <= 32 ? 2 : 1;
 }
 
+// Speculative bounds (many queries, one whole database).  The r-th smallest
+// d over a sample of S rows (chunks of kSpecSpan rows at a regular stride)
+// bounds the k-th smallest d of the database unless r of the database's k
+// smallest rows fall in the sample; for a random row order that number is
+// binomial(k, S / N), and r is the smallest rank whose tail is below 1e-9
+// (r = k: the bound is certain).  The sample's distances come from the
+// matrix cores (whatever kernel scans), the r-th smallest from a histogram,
+// rounded up to its bin's edge.  The bound only selects candidates: the
+// final merge flags any query with fewer than k candidates and
+// topk_redo_kernel recomputes it exactly, so results never depend on it.
+constexpr int64_t kSpecSpan = 2048;            // rows per sample chunk
+constexpr int64_t kSpecMinRows = 1 << 19;      // smaller databases scan without it
+constexpr int64_t kSpecMinRowsForced = 1 << 17;
+constexpr int64_t kSpecMaxDists = 1 << 26;     // sample distances held at once (128 MB)
+
 struct FusedPlan {
     bool ok = false;
-    int kind = 0;        // 1 few-query, 2 grouped
+    int kind = 0;        // 1 few-query, 2 grouped, 3 matrix cores
     int n_rb = 0, n_qb = 0, qb_size = 0, n_chunks = 1;
     int64_t rpb = 0;     // rows per tile
     int64_t chunk = 0;
     size_t cand_bytes = 0, gthr_bytes = 0, hist_bytes = 0, level2_bytes = 0;
+    bool spec = false;   // speculative bound from a sample
+    int spec_r = 0, spec_nsc = 0;
+    int64_t spec_stride = 0;
+    size_t spec_bytes = 0;   // sample distances [Q][nsc * kSpecSpan] uint16, failure flags [Q]
 };
 
 // The kernel for the shape and its rows per tile (N: rows to scan).
@@ -298,18 +459,63 @@ bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
         p.qb_size = (int)Q;
     } else {
         p.rpb = kRowsPerBlock;
-        p.kind = 2;
-        const int ng = M <= 32 ? 2 : 1;
-        p.qb_size = 8 * ng;
+        const bool mfma_ok = k <= bolt::kMfmaCap - bolt::kMfmaPass;
+        const int force = bolt::g_force_fused_kind;
+        if (mfma_ok && (force == 3 || (force != 2 && Q >= kMfmaMinQ))) {
+            p.kind = 3;
+            p.qb_size = 32 * (M <= 32 ? 2 : 1);
+        } else {
+            p.kind = 2;
+            p.qb_size = 8 * (M <= 32 ? 2 : 1);
+        }
         p.n_qb = (int)((Q + p.qb_size - 1) / p.qb_size);
     }
     return true;
 }
 
+// Smallest r with P(binomial(k, p) >= r) <= 1e-9, at most k.
+static int spec_rank(int k, double pr)
+{
+    std::vector<double> pmf(k + 1);
+    double tail = 0.0;
+    // pmf by the recurrence from j = 0 (pr < 1/16 here, so (1 - pr)^k > 0)
+    pmf[0] = std::pow(1.0 - pr, k);
+    for (int j = 1; j <= k; ++j)
+        pmf[j] = pmf[j - 1] * (double)(k - j + 1) / (double)j * pr / (1.0 - pr);
+    int r = k;
+    for (int j = k; j >= 1; --j) {
+        tail += pmf[j];
+        if (tail > 1e-9)
+            break;
+        r = j;
+    }
+    return r;
+}
+
+// Speculation for a whole-database plan of kind 2 or 3: about N / 32 sample
+// rows (8 to 128 chunks), fewer if Q of them would not fit kSpecMaxDists.
+static void plan_spec(FusedPlan &p, int64_t N, int64_t Q, int k)
+{
+    const int mode = bolt::g_spec_mode;
+    if (p.kind < 2 || mode == 0 || N < (mode > 0 ? kSpecMinRowsForced : kSpecMinRows))
+        return;
+    int64_t nsc = N / 32 / kSpecSpan;
+    nsc = nsc < 8 ? 8 : (nsc > 128 ? 128 : nsc);
+    while (nsc > 8 && Q * nsc * kSpecSpan > kSpecMaxDists)
+        nsc /= 2;
+    if (Q * nsc * kSpecSpan > kSpecMaxDists)
+        return;
+    const int r = spec_rank(k, (double)(nsc * kSpecSpan) / (double)N);
+    p.spec = true;
+    p.spec_r = r;
+    p.spec_nsc = (int)nsc;
+    p.spec_stride = N / nsc;
+}
+
 // Workspace layout once the number of tiles p.n_rb is known.
 FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
 {
-    if (p.kind == 2 && (int64_t)p.n_qb * ((p.n_rb + 7) / 8) * 8 > INT32_MAX)
+    if (p.kind >= 2 && (int64_t)p.n_qb * ((p.n_rb + 7) / 8) * 8 > INT32_MAX)
         return p;
     p.cand_bytes = align256((size_t)Q * p.n_rb * k * sizeof(uint64_t));
     p.gthr_bytes = align256((size_t)Q * sizeof(uint32_t));
@@ -326,6 +532,9 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
                                     : 0;
     if (p.n_chunks > 65535)
         return p;
+    p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * kSpecSpan * sizeof(uint16_t)) +
+                                align256((size_t)Q * sizeof(uint32_t))
+                          : 0;
     p.ok = true;
     return p;
 }
@@ -336,23 +545,73 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
     if (!plan_kind(N, M, Q, k, vec_ok, p))
         return p;
     p.n_rb = (int)((N + p.rpb - 1) / p.rpb);
+    plan_spec(p, N, Q, k);
     return plan_finish(p, Q, k);
 }
 
+// One scan + candidate launch of the planned kind: n_rb tiles of the caller's
+// list, or of span rows every stride rows; k candidates per tile and query.
 template <int MM>
-void launch_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
-                  int k, int largest, uint64_t *cand, uint32_t *gthr, const int64_t *tiles, hipStream_t s)
+void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k,
+                 int largest, int n_rb, uint64_t *cand, uint32_t *gthr, const int64_t *tiles, int64_t stride,
+                 int64_t span, const char *prof_name, hipStream_t s)
 {
     if (p.kind == 1) {
-        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, p.n_rb, cand, gthr, tiles, s);
+        bolt::ProfScope prof_(prof_name, s);
+        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, gthr, tiles, s);
         return;
     }
-    const unsigned grid = (unsigned)(p.n_qb * ((p.n_rb + 7) / 8 * 8));
-    {
-        bolt::ProfScope prof_("scan_topk_grouped", s);
-        hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes,
-                           N, luts, Q, (uint32_t)k, largest, p.n_rb, p.n_qb, cand, gthr, tiles);
+    const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
+    bolt::ProfScope prof_(prof_name, s);
+    if (p.kind == 3)
+        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1>), dim3(grid), dim3(256), 0, s, codes, N,
+                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, gthr, tiles, stride, span);
+    else
+        hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes, N,
+                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, gthr, tiles, stride, span);
+}
+
+void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
+                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *gthr, const int64_t *tiles,
+                   int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
+{
+    switch (M) {
+    case 8: launch_scan<8>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
+    case 16: launch_scan<16>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
+    case 32: launch_scan<32>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
+    case 64: launch_scan<64>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
     }
+}
+
+void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_t Q, int largest, int64_t stride,
+                        int64_t S, int nsc, uint16_t *out, hipStream_t s)
+{
+    const int nt = M <= 32 ? 2 : 1;
+    const dim3 grid((unsigned)((Q + 32 * nt - 1) / (32 * nt)), (unsigned)nsc);
+    const int64_t span = kSpecSpan;
+    switch (M) {
+    case 8:
+        hipLaunchKernelGGL((spec_sample_kernel<8, 2>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+                           S, out);
+        break;
+    case 16:
+        hipLaunchKernelGGL((spec_sample_kernel<16, 2>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+                           S, out);
+        break;
+    case 32:
+        hipLaunchKernelGGL((spec_sample_kernel<32, 2>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+                           S, out);
+        break;
+    case 64:
+        hipLaunchKernelGGL((spec_sample_kernel<64, 1>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+                           S, out);
+        break;
+    }
+}
+
+const char *scan_prof_name(int kind)
+{
+    return kind == 1 ? "scan_topk_few" : (kind == 3 ? "scan_topk_mfma" : "scan_topk_grouped");
 }
 
 }  // namespace
@@ -364,12 +623,17 @@ bool fused_supported(int64_t N, int M, int64_t Q, int k, bool vec_ok)
     return plan_fused(N, M, Q, k, vec_ok).ok;
 }
 
+static size_t plan_bytes(const FusedPlan &p)
+{
+    return p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes + p.spec_bytes;
+}
+
 size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
 {
     FusedPlan p = plan_fused(N, M, Q, k, true);
     if (!p.ok)
         return 0;
-    return p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
+    return plan_bytes(p);
 }
 
 // Launches of a planned fused scan + top-k (tiles: null, or the caller's
@@ -384,15 +648,26 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     uint64_t *level2 = reinterpret_cast<uint64_t *>(w + p.cand_bytes + p.gthr_bytes + p.hist_bytes);
     uint32_t *level2_cnt = reinterpret_cast<uint32_t *>(
         w + p.cand_bytes + p.gthr_bytes + p.hist_bytes + align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)));
+    char *ws_spec = w + p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
+    const int64_t S = (int64_t)p.spec_nsc * kSpecSpan;
+    uint16_t *sdist = p.spec ? reinterpret_cast<uint16_t *>(ws_spec) : nullptr;
+    uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * S * sizeof(uint16_t)))
+                            : nullptr;
     const int64_t n_hist = Q * bolt::kHistBins;
     hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
-                       hist, n_hist);
-    switch (M) {
-    case 8: launch_fused<8>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
-    case 16: launch_fused<16>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
-    case 32: launch_fused<32>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
-    case 64: launch_fused<64>(p, codes, N, luts, Q, k, largest, cand, gthr, tiles, s); break;
+                       hist, n_hist, fail);
+    if (p.spec) {
+        // sample distances, then each query's starting bound
+        {
+            bolt::ProfScope prof_("spec_sample", s);
+            launch_spec_sample(M, codes, luts, Q, (int)largest, p.spec_stride, S, p.spec_nsc, sdist, s);
+        }
+        bolt::ProfScope prof_("spec_select", s);
+        hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, sdist, S, (uint32_t)p.spec_r,
+                           bolt::hist_shift(M), gthr, bolt::g_spec_mode == 2 ? 1 : 0);
     }
+    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, gthr, tiles, kRowsPerBlock,
+                  kRowsPerBlock, scan_prof_name(p.kind), s);
     const int64_t per_query = (int64_t)p.n_rb * k;
     {
         bolt::ProfScope prof_("cand_hist", s);
@@ -401,17 +676,24 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
                            dim3(256), 0, s, cand, per_query, hchunk, bolt::hist_shift(M), hist);
     }
     const uint32_t smax = 255u * (uint32_t)M;
-    bolt::ProfScope prof_("topk_merge", s);
-    hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand,
-                       per_query, p.n_chunks > 1 ? p.chunk : per_query, (uint32_t)k, gthr, hist,
-                       bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx);
-    if (p.n_chunks > 1)
-        hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
-                           p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx);
+    {
+        bolt::ProfScope prof_("topk_merge", s);
+        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand,
+                           per_query, p.n_chunks > 1 ? p.chunk : per_query, (uint32_t)k, gthr, hist,
+                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx,
+                           p.n_chunks > 1 ? nullptr : fail);
+        if (p.n_chunks > 1)
+            hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
+                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, fail);
+    }
+    if (p.spec) {
+        bolt::ProfScope prof_("topk_redo", s);
+        hipLaunchKernelGGL(topk_redo_kernel, dim3((unsigned)Q), dim3(256), 0, s, codes, N, M, luts, (uint32_t)k,
+                           (int)largest, fail, vals, idx);
+    }
     return check_launch("bolt_scan_topk (fused)");
 }
 
-static size_t plan_bytes(const FusedPlan &p) { return p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes; }
 
 // Fused scan + top-k; returns BOLT_ERR_UNSUPPORTED when the shape has no fused kernel.
 int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,

@@ -43,6 +43,8 @@ int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, i
 
 // Test hook: 1 forces the unfused scan-then-select path of bolt_scan_topk.
 extern int g_force_unfused_topk;
+extern int g_force_fused_kind;   // -1 automatic, 2 grouped, 3 matrix cores
+extern int g_spec_mode;           // speculative bounds: -1 automatic, 0 off, 1 on, 2 on and failing
 
 // Top-k of the rows of a uint16 matrix (arguments already validated).
 int topk_u16(const uint16_t *d, int64_t Q, int64_t N, int64_t ldd, int k, int largest,

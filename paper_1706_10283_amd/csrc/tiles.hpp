@@ -154,16 +154,29 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
     const char *tabb = reinterpret_cast<const char *>(L.tab);
     const uint32_t *bnd2 = reinterpret_cast<const uint32_t *>(L.bnd16);
     int pass = 0;
+    // codes are loaded one pass ahead, clamped to the last row so that the
+    // load is unconditional and in flight during the whole pass
+    uint32_t nxt[NW];
+    if (r0 < r1) {
+        const int64_t n = r0 + tid;
+        load_row<MM>(job.codes, n < r1 ? n : r1 - 1, nxt);
+    }
     for (int64_t base = r0; base < r1; base += 256, ++pass) {
         const int64_t n = base + tid;
         const bool valid = n < r1;
         uint32_t cw[NW];
-        if (valid)
-            load_row<MM>(job.codes, n, cw);
-        else
 #pragma unroll
-            for (int v = 0; v < NW; ++v)
-                cw[v] = 0;
+        for (int v = 0; v < NW; ++v)
+            cw[v] = nxt[v];
+        {
+            const int64_t nn = n + 256;
+            load_row<MM>(job.codes, nn < r1 ? nn : r1 - 1, nxt);
+        }
+        // the published bounds are read at the start of every pass (an
+        // unconditional load, so nothing waits for it early) and folded in at
+        // the end of every kRefresh-th pass: the read's latency overlaps the pass
+        const bool refresh = (pass % kRefresh) == kRefresh - 1;
+        const uint32_t gpre = read_bound(&job.gthr[q0 + (tid < nq ? tid : nq - 1)]);
         const uint32_t local = (uint32_t)(n - r0);
 #pragma unroll 1
         for (int g = 0; g < NG; g += GU) {
@@ -202,26 +215,29 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
                 for (int v = 0; v < 4; ++v)
                     dd[v] = largest ? sub_sat_u16x2(SMAX2, acc[u][v]) : acc[u][v];
                 const uint4 bp = *reinterpret_cast<const uint4 *>(&bnd2[gg * 4]);
-                const uint32_t hit = sub_sat_u16x2(bp.x, dd[0]) | sub_sat_u16x2(bp.y, dd[1]) |
-                                     sub_sat_u16x2(bp.z, dd[2]) | sub_sat_u16x2(bp.w, dd[3]);
-                if (valid && hit) {
-#pragma unroll
-                    for (int qq = 0; qq < 8; ++qq) {
-                        const int q = gg * QG + qq;
-                        const uint32_t d = (dd[qq >> 1] >> (16 * (qq & 1))) & 0xFFFFu;
-                        if (d < (uint32_t)L.bnd16[q]) {
-                            const uint32_t pos = atomicAdd(&L.cnt[q], 1u);
-                            L.buf[q * CAP + pos] = local_key(d, local);
-                        }
+                const uint32_t h0 = sub_sat_u16x2(bp.x, dd[0]), h1 = sub_sat_u16x2(bp.y, dd[1]);
+                const uint32_t h2 = sub_sat_u16x2(bp.z, dd[2]), h3 = sub_sat_u16x2(bp.w, dd[3]);
+                if (valid && (h0 | h1 | h2 | h3)) {
+                    // one bit per query of the group whose d passes its bound
+                    uint32_t hm = (h0 & 0xFFFFu ? 1u : 0u) | (h0 >> 16 ? 2u : 0u) | (h1 & 0xFFFFu ? 4u : 0u) |
+                                  (h1 >> 16 ? 8u : 0u) | (h2 & 0xFFFFu ? 16u : 0u) | (h2 >> 16 ? 32u : 0u) |
+                                  (h3 & 0xFFFFu ? 64u : 0u) | (h3 >> 16 ? 128u : 0u);
+                    const uint64_t dlo = (uint64_t)dd[0] | ((uint64_t)dd[1] << 32);
+                    const uint64_t dhi = (uint64_t)dd[2] | ((uint64_t)dd[3] << 32);
+                    while (hm) {
+                        const uint32_t qq = (uint32_t)__builtin_ctz(hm);
+                        hm &= hm - 1u;
+                        const uint32_t d = (uint32_t)(((qq < 4 ? dlo : dhi) >> (16 * (qq & 3))) & 0xFFFFu);
+                        const int q = gg * QG + (int)qq;
+                        const uint32_t pos = atomicAdd(&L.cnt[q], 1u);
+                        L.buf[q * CAP + pos] = local_key(d, local);
                     }
                 }
             }
         }
         __syncthreads();
-        const bool refresh = (pass % kRefresh) == kRefresh - 1;
         for (int q = wave; q < nq; q += 4) {
             const uint32_t c = L.cnt[q];
-            uint32_t nb = 0xFFFFFFFFu;
             if (c > CAP - 256) {
                 PruneResult pr = prune_local<CAP>(L.buf + q * CAP, c, k, false);
                 if (pr.count > CAP - 256)
@@ -229,16 +245,21 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
                 if (lane == 0) {
                     L.cnt[q] = pr.count;
                     publish(&job.gthr[q0 + q], pr.T, L.bnd[q]);
+                    uint32_t b = L.bnd[q];
+                    b = pr.T < b ? pr.T : b;
+                    L.bnd[q] = b;
+                    L.bnd16[q] = (uint16_t)(b < 0xFFFFu ? b : 0xFFFFu);
                 }
-                nb = pr.T;
             }
-            if (lane == 0 && (nb != 0xFFFFFFFFu || refresh)) {
-                uint32_t b = L.bnd[q];
-                b = nb < b ? nb : b;
-                const uint32_t gb = read_bound(&job.gthr[q0 + q]) + 1u;
+        }
+        if (refresh) {
+            __syncthreads();
+            if (tid < nq) {
+                uint32_t b = L.bnd[tid];
+                const uint32_t gb = gpre + 1u;
                 b = gb < b ? gb : b;
-                L.bnd[q] = b;
-                L.bnd16[q] = (uint16_t)(b < 0xFFFFu ? b : 0xFFFFu);
+                L.bnd[tid] = b;
+                L.bnd16[tid] = (uint16_t)(b < 0xFFFFu ? b : 0xFFFFu);
             }
         }
         __syncthreads();
@@ -247,6 +268,274 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
                                      &job.gthr[q0 + q], L.bnd[q]);
+}
+
+// ------------------------------------------------------------------ matrix cores
+//
+// With many queries the scan is a matrix product (Sec. 3.1 written as a
+// contraction): write row n's codes one-hot, 16 entries per subspace of
+// which the code's entry is 1; the sum of query q over row n is the dot
+// product of that 16M-entry row with column q of the tables.  The int8
+// matrix cores evaluate it exactly in int32.  A table entry T enters as the
+// int8 value T - 128, or (255 - T) - 128 when the largest sums are wanted,
+// so that acc + 128 M is d itself: the sum, or 255 M - sum (M entries of
+// each one-hot row are 1).
+//
+// v_mfma_i32_32x32x32_i8: lane l supplies row l % 32 of the one-hot codes
+// and column l % 32 of the tables, both over the same 16 K entries of its
+// half l / 32 (here the 16 centroids of subspace 2 s + l / 32 at step s),
+// and receives rows 8 (v / 4) + 4 (l / 32) + v % 4 of column l % 32 in
+// accumulator v.  A wave holds the tables of its NT query tiles (32 queries
+// each) in registers for the whole tile and takes 32 rows per pass; the
+// one-hot operand comes from a 16-entry LDS table, conflict free.
+
+constexpr int kMfmaCap = 256;    // candidate slots per query: k <= kMfmaCap - kMfmaPass
+constexpr int kMfmaPass = 128;   // rows per pass: 4 waves x 32
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+template <int NT>
+struct MfmaLds {
+    uint32_t buf[NT * 32 * kMfmaCap];
+    uint32_t cnt[NT * 32];
+    uint32_t bnd[NT * 32];
+    uint4 onehot[16];
+};
+
+// Entry c of the one-hot table (16 x 16 bytes): byte c is 1.  Threads 0-63.
+__device__ __forceinline__ void mfma_onehot_init(uint4 *onehot)
+{
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const int c = tid >> 2, j = tid & 3;
+        reinterpret_cast<uint32_t *>(onehot)[tid] = (c >> 2) == j ? (1u << (8 * (c & 3))) : 0u;
+    }
+}
+
+// This lane's table columns (queries q0 + 32 t + l % 32, subspace 2 s + l / 32)
+// as int8 T - 128 (or (255 - T) - 128 for the largest sums); queries at or
+// beyond nq get zeros.  The loads are unconditional (clamped query) so that
+// all of them are in flight together.
+template <int MM, int NT>
+__device__ __forceinline__ void mfma_load_tables(const uint8_t *__restrict__ luts, int64_t q0, int nq,
+                                                 int largest, i32x4 (&tb)[NT][MM / 2])
+{
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    const uint32_t flip = largest ? 0x7F7F7F7Fu : 0x80808080u;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int q = 32 * t + col;
+        const uint32_t keep = q < nq ? 0xFFFFFFFFu : 0u;
+        const uint8_t *src = luts + ((q0 + (q < nq ? q : nq - 1)) * MM + half) * 16;
+#pragma unroll
+        for (int s = 0; s < MM / 2; ++s) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(src + 2 * s * 16);
+            tb[t][s] = i32x4{(int)((v.x ^ flip) & keep), (int)((v.y ^ flip) & keep), (int)((v.z ^ flip) & keep),
+                             (int)((v.w ^ flip) & keep)};
+        }
+    }
+}
+
+// acc[t] = d - 128 M of this lane's 16 rows (its code row cw is row l % 32 of
+// the wave's 32) against the queries of table tile t.
+template <int MM, int NT>
+__device__ __forceinline__ void mfma_pass(const uint32_t (&cw)[MM / 8], const char *oh,
+                                          const i32x4 (&tb)[NT][MM / 2], i32x16 (&acc)[NT])
+{
+    constexpr int NW = MM / 8;
+    const int half = (threadIdx.x & 63) >> 5;
+    // byte s of wa: the LDS offset (16 x code) of subspace 2 s + half
+    uint32_t wa[NW];
+#pragma unroll
+    for (int v = 0; v < NW; ++v)
+        wa[v] = (cw[v] << (4 - 4 * half)) & 0xF0F0F0F0u;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        acc[t] = i32x16{};
+#pragma unroll
+    for (int s = 0; s < MM / 2; ++s) {
+        const uint32_t a = (wa[s >> 2] >> (8 * (s & 3))) & 0xFFu;
+        const i32x4 av = *reinterpret_cast<const i32x4 *>(oh + a);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, tb[t][s], acc[t], 0, 0, 0);
+    }
+}
+
+template <int MM, int NT>
+__device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
+{
+    constexpr int KS = MM / 2;       // matrix-core steps per row, two subspaces each
+    constexpr int NW = MM / 8;       // code dwords per row
+    constexpr int QB = 32 * NT;
+    constexpr int CAP = kMfmaCap;
+    constexpr int OFF = 128 * MM;
+    constexpr int PER_WAVE = QB / 4;  // queries each wave checks for pruning
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, col = lane & 31;
+    const int nq = job.nq;
+    const uint32_t k = job.k;
+    const int64_t q0 = job.q0;
+
+    mfma_onehot_init(L.onehot);
+    for (int q = tid; q < QB; q += 256) {
+        L.cnt[q] = 0;
+        L.bnd[q] = q < nq ? read_bound(&job.gthr[q0 + q]) + 1u : 0u;
+    }
+    // absent queries: zero tables and bound 0
+    i32x4 tb[NT][KS];
+    mfma_load_tables<MM, NT>(job.luts, q0, nq, job.largest, tb);
+    __syncthreads();
+
+    const int64_t r0 = job.r0, r1 = job.r1;
+    const char *oh = reinterpret_cast<const char *>(L.onehot);
+    // codes one pass ahead, clamped to the last row (unconditional loads)
+    uint32_t nxt[NW];
+    if (r0 < r1) {
+        const int64_t n = r0 + 32 * wave + col;
+        load_row<MM>(job.codes, n < r1 ? n : r1 - 1, nxt);
+    }
+    int pass = 0;
+    for (int64_t base = r0; base < r1; base += kMfmaPass, ++pass) {
+        // published bounds: read at the start of every pass (unconditional,
+        // before the code prefetch), folded in at the end of every
+        // kRefresh-th pass
+        const bool refresh = (pass % kRefresh) == kRefresh - 1;
+        const uint32_t gpre = read_bound(&job.gthr[q0 + (tid < nq ? tid : nq - 1)]);
+        uint32_t cw[NW];
+#pragma unroll
+        for (int v = 0; v < NW; ++v)
+            cw[v] = nxt[v];
+        {
+            const int64_t nn = base + kMfmaPass + 32 * wave + col;
+            load_row<MM>(job.codes, nn < r1 ? nn : r1 - 1, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the pass
+        // hit iff d = acc + OFF < bound
+        int thr[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            thr[t] = (int)L.bnd[32 * t + col] - OFF;
+
+        i32x16 acc[NT];
+        mfma_pass<MM, NT>(cw, oh, tb, acc);
+
+        // rows of accumulator v: rb + 8 (v / 4) + v % 4
+        const int64_t rb = base + 32 * wave + 4 * half;
+        if (base + kMfmaPass > r1) {   // ragged last pass: rows past the tile never pass
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                if (rb + 8 * (v >> 2) + (v & 3) >= r1)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[t][v] = 1 << 30;
+        }
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            int mn = acc[t][0];
+#pragma unroll
+            for (int v = 1; v < 16; ++v)
+                mn = acc[t][v] < mn ? acc[t][v] : mn;
+            any = any || mn < thr[t];
+        }
+        if (__ballot(any)) {
+            const uint32_t lbase = (uint32_t)(rb - r0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int q = 32 * t + col;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    if (acc[t][v] < thr[t]) {
+                        const uint32_t d = (uint32_t)(acc[t][v] + OFF);
+                        const uint32_t pos = atomicAdd(&L.cnt[q], 1u);
+                        L.buf[q * CAP + pos] = local_key(d, lbase + 8 * (v >> 2) + (v & 3));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        {
+            const int qw = wave * PER_WAVE;
+            const uint32_t c = lane < PER_WAVE ? L.cnt[qw + lane] : 0u;
+            uint64_t full = __ballot(c > CAP - kMfmaPass);
+            while (full) {
+                const int q = qw + (int)__builtin_ctzll(full);
+                full &= full - 1;
+                PruneResult pr = prune_local<CAP>(L.buf + q * CAP, L.cnt[q], k, false);
+                if (pr.count > CAP - kMfmaPass)
+                    pr = prune_local<CAP>(L.buf + q * CAP, pr.count, k, true);
+                if (lane == 0) {
+                    L.cnt[q] = pr.count;
+                    publish(&job.gthr[q0 + q], pr.T, L.bnd[q]);
+                    const uint32_t b = L.bnd[q];
+                    L.bnd[q] = pr.T < b ? pr.T : b;
+                }
+            }
+        }
+        if (refresh) {
+            __syncthreads();
+            if (tid < nq && tid < QB) {
+                const uint32_t b = L.bnd[tid], gb = gpre + 1u;
+                L.bnd[tid] = gb < b ? gb : b;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = wave; q < nq && q < QB; q += 4)
+        write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
+                                     job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
+                                     &job.gthr[q0 + q], L.bnd[q]);
+}
+
+// Sample distances for the speculative bounds: the d of every (query, row)
+// of span consecutive rows from r0, written as uint16 to out[q][s0 + row - r0]
+// (out has S entries per query).  Each lane's accumulators hold four runs of
+// four consecutive rows of one query, written as 8-byte words.
+template <int MM, int NT>
+__device__ void mfma_sample_tile(const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t q0,
+                                 int nq, int largest, int64_t r0, int64_t span, uint16_t *__restrict__ out,
+                                 int64_t S, int64_t s0, uint4 *onehot)
+{
+    constexpr int NW = MM / 8;
+    constexpr int OFF = 128 * MM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, col = lane & 31;
+    mfma_onehot_init(onehot);
+    i32x4 tb[NT][MM / 2];
+    mfma_load_tables<MM, NT>(luts, q0, nq, largest, tb);
+    __syncthreads();
+    const char *oh = reinterpret_cast<const char *>(onehot);
+    // codes one pass ahead (the last pass re-reads its own rows)
+    uint32_t nxt[NW];
+    load_row<MM>(codes, r0 + 32 * wave + col, nxt);
+    for (int64_t base = 0; base < span; base += kMfmaPass) {
+        uint32_t cw[NW];
+#pragma unroll
+        for (int v = 0; v < NW; ++v)
+            cw[v] = nxt[v];
+        const int64_t ahead = base + kMfmaPass < span ? base + kMfmaPass : base;
+        load_row<MM>(codes, r0 + ahead + 32 * wave + col, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        i32x16 acc[NT];
+        mfma_pass<MM, NT>(cw, oh, tb, acc);
+        const int64_t rl = base + 32 * wave + 4 * half;   // first row of this lane's runs, from r0
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int q = 32 * t + col;
+            if (q < nq) {
+                uint16_t *dst = out + (q0 + q) * S + s0 + rl;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t lo = (uint32_t)(acc[t][4 * j] + OFF) | ((uint32_t)(acc[t][4 * j + 1] + OFF) << 16);
+                    const uint32_t hi =
+                        (uint32_t)(acc[t][4 * j + 2] + OFF) | ((uint32_t)(acc[t][4 * j + 3] + OFF) << 16);
+                    *reinterpret_cast<uint2 *>(dst + 8 * j) = make_uint2(lo, hi);
+                }
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ few queries

@@ -265,6 +265,8 @@ static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 namespace bolt {
 int g_force_unfused_topk = 0;
+int g_force_fused_kind = -1;
+int g_spec_mode = -1;
 }
 
 static size_t unfused_ws_bytes(int64_t N, int64_t Q)
@@ -370,5 +372,25 @@ extern "C" int bolt_scan_topk_ranges(const uint8_t *codes, int64_t N, int32_t M,
 extern "C" int bolt_debug_force_unfused_topk(int32_t on)
 {
     bolt::g_force_unfused_topk = on ? 1 : 0;
+    return BOLT_OK;
+}
+
+// Test hook: speculative bounds of many-query scans (-1 automatic, 0 off,
+// 1 on from 2^17 rows, 2 as 1 with every bound failing: all queries are
+// recomputed by the exact fallback).
+extern "C" int bolt_debug_speculation(int32_t mode)
+{
+    if (mode < -1 || mode > 2)
+        return bolt::fail(BOLT_ERR_INVALID, "speculation mode must be -1, 0, 1 or 2 (got %d)", mode);
+    bolt::g_spec_mode = mode;
+    return BOLT_OK;
+}
+
+// Test hook: the many-query fused kernel (-1 automatic, 2 grouped, 3 matrix cores).
+extern "C" int bolt_debug_force_fused_kind(int32_t kind)
+{
+    if (kind != -1 && kind != 2 && kind != 3)
+        return bolt::fail(BOLT_ERR_INVALID, "fused kind must be -1, 2 or 3 (got %d)", kind);
+    bolt::g_force_fused_kind = kind;
     return BOLT_OK;
 }

@@ -342,6 +342,81 @@ def test_scan_topk_fused_parity(bolt, metric, M, Q, N, k, kind):
     assert np.array_equal(iu.cpu().numpy(), ir)
 
 
+# many queries: the grouped LDS-table kernel and the int8 matrix-core kernel
+# (kind 3 falls back to the grouped kernel for k > 128)
+MANY_CASES = [
+    # (M, Q, N, k, lut kind)
+    (32, 64, 16384 * 2 + 77, 100, "rand"), (32, 100, 50_000, 128, "coarse"), (16, 65, 33_000, 100, "rand"),
+    (8, 40, 20_000, 10, "const"), (64, 33, 40_001, 100, "rand"), (64, 96, 16_384, 1, "coarse"),
+    (32, 200, 5, 100, "rand"), (32, 37, 1, 7, "rand"), (16, 128, 70_000, 129, "rand"),
+    (8, 300, 9_000, 64, "coarse"), (32, 36, 700_000, 128, "rand"), (64, 32, 129, 100, "const"),
+]
+
+
+@pytest.mark.parametrize("kernel", [2, 3])
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("M,Q,N,k,kind", MANY_CASES)
+def test_scan_topk_many_queries_parity(bolt, kernel, metric, M, Q, N, k, kind):
+    """Both many-query kernels give exactly the oracle's top-k: ragged query
+    blocks and passes, N < k, ties (coarse / constant tables), two-level merge."""
+    seed = 13 * M + 7 * Q + N + k
+    _say("many-query scan_topk kernel", kernel, metric, kind, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    elif kind == "const":
+        luts = np.full_like(luts, 3)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    bolt.debug_force_fused_kind(kernel)
+    try:
+        v, i = bolt.bolt_scan_topk(cd, ld, metric, k)
+        torch.cuda.synchronize()
+    finally:
+        bolt.debug_force_fused_kind(-1)
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
+
+
+# speculative starting bounds from a row sample (mode 1), and the same with
+# every bound failing so that each query takes the exact recomputation (mode 2)
+SPEC_CASES = [
+    # (M, Q, N, k, lut kind)
+    (32, 64, 200_000, 100, "rand"), (16, 40, 150_000, 10, "coarse"), (64, 33, 140_000, 128, "rand"),
+    (8, 100, 131_072, 1, "const"), (32, 48, 300_001, 256, "rand"), (32, 70, 180_000, 64, "coarse"),
+]
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("kernel", [2, 3])
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("M,Q,N,k,kind", SPEC_CASES)
+def test_scan_topk_speculation_parity(bolt, mode, kernel, metric, M, Q, N, k, kind):
+    """Sampled starting bounds select candidates only: the result equals the
+    oracle's whether the bounds hold or all fail (exact recomputation)."""
+    seed = 11 * M + 5 * Q + N + k
+    _say("speculation mode", mode, "kernel", kernel, metric, kind, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    elif kind == "const":
+        luts = np.full_like(luts, 3)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    bolt.debug_force_fused_kind(kernel)
+    bolt.debug_speculation(mode)
+    try:
+        v, i = bolt.bolt_scan_topk(cd, ld, metric, k)
+        torch.cuda.synchronize()
+    finally:
+        bolt.debug_speculation(-1)
+        bolt.debug_force_fused_kind(-1)
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
+
+
 def test_scan_topk_fused_repeatable(bolt):
     """Cross-workgroup bounds depend on timing; the answer must not."""
     M, Q, N, k = 32, 24, 200_000, 100
