@@ -373,7 +373,8 @@ int bolt_prof_read(char *names, size_t cap, int32_t reset);
 
 /*
  * Test hooks (not part of the hot path): pin the scan kernel (-1 automatic,
- * 0 plain loop, 1 pair tables for few queries, 2 grouped), route
+ * 0 plain loop, 1 pair tables for few queries, 2 grouped, 3 int8 matrix
+ * cores for M in {8, 16, 32, 64}), route
  * bolt_scan_topk through the unfused scan-then-select path (on != 0), and
  * pin the kernel of fused scans with many queries (-1 automatic, 2 grouped
  * LDS tables, 3 int8 matrix cores; 3 applies only where k <= 128, otherwise

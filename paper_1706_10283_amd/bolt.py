@@ -376,7 +376,7 @@ def debug_speculation(mode: int):
 
 
 def debug_force_scan_kernel(kind: int):
-    """Test hook: -1 automatic, 0 generic, 1 few-query, 2 grouped."""
+    """Test hook: -1 automatic, 0 generic, 1 few-query, 2 grouped, 3 matrix cores."""
     _check(_lib.bolt_debug_force_scan_kernel(kind))
 
 

@@ -35,7 +35,6 @@ using bolt::PruneResult;
 
 constexpr int kRowsPerBlock = 16384;      // rows per workgroup (<= 65536: 16-bit local rows)
 constexpr int64_t kMfmaMinQ = 32;         // queries from which the matrix-core tiles are used
-constexpr int64_t kMergeChunk = 16384;    // keys per first-level merge workgroup
 
 // Decode the tile of workgroup `w`: XCD-major placement of row blocks.
 __device__ __forceinline__ void tile_of(int w, int n_qb, int &qb, int &rb)
@@ -50,8 +49,8 @@ __device__ __forceinline__ void tile_of(int w, int n_qb, int &qb, int &rb)
 // workgroup has no tile (padding of the XCD placement).
 __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uint8_t *codes, int64_t N,
                                          const uint8_t *luts, int64_t Q, uint32_t k, int largest, int n_rb,
-                                         uint64_t *cand, uint32_t *gthr, const int64_t *tiles, int64_t stride,
-                                         int64_t span, bolt::TileJob &job)
+                                         uint64_t *cand, uint32_t *ccnt, uint32_t *gthr, const int64_t *tiles,
+                                         int64_t stride, int64_t span, bolt::TileJob &job)
 {
     int qb, rb;
     tile_of(w, n_qb, qb, rb);
@@ -60,6 +59,7 @@ __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uin
     job.codes = codes;
     job.luts = luts;
     job.cand = cand;
+    job.ccnt = ccnt;
     job.gthr = gthr;
     if (tiles) {   // row ranges given by the caller, cut into tiles
         job.r0 = tiles[2 * rb];
@@ -80,13 +80,13 @@ __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uin
 template <int MM, int NG>
 __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
-    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand,
+    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
     uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
 {
     __shared__ bolt::GroupedLds<MM, NG> L;
     bolt::TileJob job;
-    if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span,
-                 job))
+    if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, gthr, tiles, stride,
+                 span, job))
         bolt::grouped_tile<MM, NG>(job, L);
 }
 
@@ -94,13 +94,13 @@ __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
 template <int MM, int NT>
 __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
-    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand,
+    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
     uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
 {
     __shared__ bolt::MfmaLds<NT> L;
     bolt::TileJob job;
-    if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span,
-                 job))
+    if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, gthr, tiles, stride,
+                 span, job))
         bolt::mfma_tile<MM, NT>(job, L);
 }
 
@@ -152,14 +152,84 @@ __device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int 
     return edge < bound ? edge : bound;
 }
 
-// Merge, level 1: one workgroup per (query, chunk of the query's candidate
-// keys).  Keys with d above the query's final bound cannot be in its top-k
-// and are skipped.  With one chunk the workgroup writes the sorted values and
-// rows; with several, the chunk's exact k smallest survivors go to its slot
-// dst[q][chunk][k] and their number to dst_cnt[q][chunk].  No atomics: the
-// slots are fixed.
+// Appends to L every key below L.mbound from slots [s_lo, s_hi) (slot s:
+// cnt[s] keys at src + s * k), pruning to the k smallest whenever the
+// buffer could overflow; returns the number of keys held.  The slots are
+// taken 256 at a time: an exclusive prefix sum of their counts (pre, 257
+// entries of LDS) numbers their keys 0..total-1, and every thread takes
+// four of those numbers per round, finding its slot by binary search.
+__device__ uint32_t merge_walk(bolt::MergeLds &L, uint32_t *pre, const uint64_t *__restrict__ src,
+                               const uint32_t *__restrict__ cnt, int64_t s_lo, int64_t s_hi, uint32_t k)
+{
+    __shared__ uint32_t wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int64_t c0 = s_lo; c0 < s_hi; c0 += 256) {
+        const int ns = (int)((s_hi - c0) < 256 ? (s_hi - c0) : 256);
+        uint32_t c = tid < ns ? cnt[c0 + tid] : 0u;
+        c = c < k ? c : k;   // a slot never holds more than k keys
+        uint32_t inc = c;    // inclusive scan within the wave, then across waves
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o)
+                inc += t;
+        }
+        if (lane == 63)
+            wsum[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w)
+            before += wsum[w];
+        pre[tid] = before + inc - c;
+        if (tid == 255)
+            pre[256] = before + inc;
+        __syncthreads();
+        const uint32_t total = pre[256];
+        for (uint32_t b0 = 0; b0 < total; b0 += 256 * 4) {
+            const uint64_t bnd = L.mbound;
+#pragma unroll 1
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t i = b0 + tid + 256 * e;
+                if (i < total) {
+                    int lo = 0, hi = ns - 1;   // last slot with pre[slot] <= i
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (pre[mid] <= i)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    const uint64_t key = src[(c0 + lo) * k + (i - pre[lo])];
+                    if (key < bnd) {
+                        const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                        L.mb[pos] = key;
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < 64 && L.mcnt > bolt::kMergeCap - 256 * 4) {
+                const uint64_t kth = bolt::prune_u64<bolt::kMergeCap>(L.mb, L.mcnt, k);
+                if (tid == 0) {
+                    L.mcnt = k;
+                    L.mbound = kth + 1;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return L.mcnt;
+}
+
+// Merge, level 1: one workgroup per (query, chunk of the query's tile
+// slots).  Keys with d above the bound from the query's candidate histogram
+// cannot be in its top-k and are skipped.  With one chunk the workgroup
+// writes the sorted values and rows (and flags the query in fail, if given,
+// when fewer than k keys passed); with several, the chunk's exact k smallest
+// survivors go to its slot dst[q][chunk][k] and their number to
+// dst_cnt[q][chunk].  No atomics outside LDS: the slots are fixed.
 __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restrict__ cand,
-                                                         int64_t per_query, int64_t chunk, uint32_t k,
+                                                         const uint32_t *__restrict__ ccnt, int64_t n_rb,
+                                                         int64_t slots_per_chunk, uint32_t k,
                                                          uint32_t *__restrict__ gthr,
                                                          const uint32_t *__restrict__ hist, int shift,
                                                          int largest, uint32_t smax, uint64_t *__restrict__ dst,
@@ -168,26 +238,32 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
                                                          int32_t *__restrict__ idx, uint32_t *__restrict__ fail)
 {
     __shared__ bolt::MergeLds L;
+    __shared__ uint32_t pre[257];
     const int64_t q = blockIdx.x;
-    const int64_t c_lo = (int64_t)blockIdx.y * chunk;
-    const int64_t c_hi = (c_lo + chunk) < per_query ? (c_lo + chunk) : per_query;
+    const int64_t s_lo = (int64_t)blockIdx.y * slots_per_chunk;
+    const int64_t s_hi = (s_lo + slots_per_chunk) < n_rb ? (s_lo + slots_per_chunk) : n_rb;
     if (threadIdx.x < 64) {
         const uint32_t b = hist_bound(hist + q * bolt::kHistBins, k, shift, gthr[q]);
         if (threadIdx.x == 0) {
-            L.misc = b;
+            L.mcnt = 0;
+            L.mbound = ((uint64_t)b + 1u) << 32;   // keys with d <= b
             // every workgroup of the query stores the same value (for level 2)
             if (blockIdx.y == 0)
                 gthr[q] = b;
         }
     }
     __syncthreads();
-    const uint32_t n = bolt::merge_collect(L, cand + q * per_query, c_lo, c_hi, k, L.misc);
+    uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, s_lo, s_hi, k);
+    if (threadIdx.x < 64 && n > k)
+        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
+    __syncthreads();
     if (gridDim.y == 1) {
         if (fail && threadIdx.x == 0 && n < k)
             fail[q] = 1u;
-        bolt::merge_emit(L, n, k, largest, smax, vals + q * k, idx + q * k);
+        bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
         return;
     }
+    n = n > k ? k : n;
     const int64_t slot = q * gridDim.y + blockIdx.y;
     for (uint32_t r = threadIdx.x; r < n; r += 256)
         dst[slot * k + r] = L.mb[r];
@@ -205,6 +281,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
                                                           uint32_t *__restrict__ fail)
 {
     __shared__ bolt::MergeLds L;
+    __shared__ uint32_t pre[257];
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -212,37 +289,8 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
         L.mbound = ((uint64_t)gthr[q] + 1u) << 32;
     }
     __syncthreads();
-    const uint64_t *sq = src + q * (int64_t)n_chunks * k;
-    const uint32_t *cq = src_cnt + q * (int64_t)n_chunks;
-    // each thread walks its chunks; a full buffer is pruned between rounds
-    for (int c0 = 0; c0 < n_chunks; c0 += 256) {
-        const int c = c0 + tid;
-        const uint32_t nc = c < n_chunks ? cq[c] : 0u;
-        uint32_t j = 0;
-        for (;;) {
-            const uint64_t bnd = L.mbound;
-            // at most 4 keys per thread per round keep the buffer within bounds
-            for (int e = 0; e < 4 && j < nc; ++e, ++j) {
-                const uint64_t key = sq[(int64_t)c * k + j];
-                if (key < bnd) {
-                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
-                    L.mb[pos] = key;
-                }
-            }
-            const int more = __syncthreads_or(j < nc);
-            if (tid < 64 && L.mcnt > bolt::kMergeCap - 256 * 4) {
-                const uint64_t kth = bolt::prune_u64<bolt::kMergeCap>(L.mb, L.mcnt, k);
-                if (tid == 0) {
-                    L.mcnt = k;
-                    L.mbound = kth + 1;
-                }
-            }
-            __syncthreads();
-            if (!more)
-                break;
-        }
-    }
-    uint32_t n = L.mcnt;
+    const uint32_t n = merge_walk(L, pre, src + q * (int64_t)n_chunks * k, src_cnt + q * (int64_t)n_chunks, 0,
+                                  n_chunks, k);
     if (fail && tid == 0 && n < k)
         fail[q] = 1u;
     if (tid < 64 && n > k)
@@ -275,24 +323,25 @@ __global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, in
         hist[i] = 0;
 }
 
-// Histogram of the d values of the candidate keys (padding ~0 skipped), one
-// workgroup per (query, chunk): counted in LDS, nonzero bins added to the
-// query's global histogram.
-__global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restrict__ cand, int64_t per_query,
-                                                        int64_t chunk, int shift, uint32_t *__restrict__ hist)
+// Histogram of the d values of the candidate keys: one workgroup per
+// (query, 256 tile slots), one slot per thread; counted in LDS, nonzero bins
+// added to the query's global histogram.
+__global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restrict__ cand,
+                                                        const uint32_t *__restrict__ ccnt, int64_t n_rb, uint32_t k,
+                                                        int shift, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[bolt::kHistBins];
     for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
         h[i] = 0;
     __syncthreads();
     const int64_t q = blockIdx.x;
-    const int64_t lo = (int64_t)blockIdx.y * chunk;
-    const int64_t hi = (lo + chunk) < per_query ? (lo + chunk) : per_query;
-    const uint64_t *c = cand + q * per_query;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
-        const uint64_t key = c[i];
-        if (key != ~0ull)
-            atomicAdd(&h[(uint32_t)(key >> 32) >> shift], 1u);
+    const int64_t slot = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    if (slot < n_rb) {
+        uint32_t m = ccnt[q * n_rb + slot];
+        m = m < k ? m : k;
+        const uint64_t *c = cand + (q * n_rb + slot) * k;
+        for (uint32_t j = 0; j < m; ++j)
+            atomicAdd(&h[(uint32_t)(c[j] >> 32) >> shift], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
@@ -304,7 +353,7 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restri
 // writes the d of its queries over rows [c * stride, c * stride + span) to
 // out[q][c * span ...].
 template <int MM, int NT>
-__global__ __launch_bounds__(256) void spec_sample_kernel(const uint8_t *__restrict__ codes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void spec_sample_kernel(const uint8_t *__restrict__ codes,
                                                           const uint8_t *__restrict__ luts, int64_t Q, int largest,
                                                           int64_t stride, int64_t span, int64_t S,
                                                           uint16_t *__restrict__ out)
@@ -438,8 +487,8 @@ struct FusedPlan {
     int kind = 0;        // 1 few-query, 2 grouped, 3 matrix cores
     int n_rb = 0, n_qb = 0, qb_size = 0, n_chunks = 1;
     int64_t rpb = 0;     // rows per tile
-    int64_t chunk = 0;
-    size_t cand_bytes = 0, gthr_bytes = 0, hist_bytes = 0, level2_bytes = 0;
+    int64_t chunk = 0;   // tile slots per first-level merge workgroup
+    size_t cand_bytes = 0, ccnt_bytes = 0, gthr_bytes = 0, hist_bytes = 0, level2_bytes = 0;
     bool spec = false;   // speculative bound from a sample
     int spec_r = 0, spec_nsc = 0;
     int64_t spec_stride = 0;
@@ -518,15 +567,14 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
     if (p.kind >= 2 && (int64_t)p.n_qb * ((p.n_rb + 7) / 8) * 8 > INT32_MAX)
         return p;
     p.cand_bytes = align256((size_t)Q * p.n_rb * k * sizeof(uint64_t));
+    p.ccnt_bytes = align256((size_t)Q * p.n_rb * sizeof(uint32_t));
     p.gthr_bytes = align256((size_t)Q * sizeof(uint32_t));
     p.hist_bytes = align256((size_t)Q * bolt::kHistBins * sizeof(uint32_t));
-    const int64_t per_query = (int64_t)p.n_rb * k;
-    // first-level chunks: enough workgroups to fill the GPU, 2048..16384 keys each
-    int64_t chunk = per_query * Q / 512;
-    chunk = chunk < 2048 ? 2048 : (chunk > kMergeChunk ? kMergeChunk : chunk);
-    chunk = (chunk + 1023) / 1024 * 1024;
+    // first-level merge chunks: enough workgroups to fill the GPU, 32..256 slots each
+    int64_t chunk = (int64_t)p.n_rb * Q / 512;
+    chunk = chunk < 32 ? 32 : (chunk > 256 ? 256 : chunk);
     p.chunk = chunk;
-    p.n_chunks = per_query > 2 * chunk ? (int)((per_query + chunk - 1) / chunk) : 1;
+    p.n_chunks = p.n_rb > chunk ? (int)((p.n_rb + chunk - 1) / chunk) : 1;
     p.level2_bytes = p.n_chunks > 1 ? align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)) +
                                           align256((size_t)Q * p.n_chunks * sizeof(uint32_t))
                                     : 0;
@@ -553,34 +601,36 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 // list, or of span rows every stride rows; k candidates per tile and query.
 template <int MM>
 void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k,
-                 int largest, int n_rb, uint64_t *cand, uint32_t *gthr, const int64_t *tiles, int64_t stride,
-                 int64_t span, const char *prof_name, hipStream_t s)
+                 int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr, const int64_t *tiles,
+                 int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
 {
-    if (p.kind == 1) {
-        bolt::ProfScope prof_(prof_name, s);
-        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, gthr, tiles, s);
+    if (p.kind == 1) {   // profiled inside under its own name
+        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, ccnt, gthr, tiles, s);
         return;
     }
     const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
     bolt::ProfScope prof_(prof_name, s);
     if (p.kind == 3)
         hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1>), dim3(grid), dim3(256), 0, s, codes, N,
-                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, gthr, tiles, stride, span);
+                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, gthr, tiles, stride, span);
     else
         hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes, N,
-                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, gthr, tiles, stride, span);
+                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, gthr, tiles, stride, span);
 }
 
 void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
-                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *gthr, const int64_t *tiles,
-                   int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
+                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
+                   const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
 {
+#define BOLT_SCAN_M(MMV)                                                                                         \
+    launch_scan<MMV>(p, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, gthr, tiles, stride, span, prof_name, s)
     switch (M) {
-    case 8: launch_scan<8>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
-    case 16: launch_scan<16>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
-    case 32: launch_scan<32>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
-    case 64: launch_scan<64>(p, codes, N, luts, Q, k, largest, n_rb, cand, gthr, tiles, stride, span, prof_name, s); break;
+    case 8: BOLT_SCAN_M(8); break;
+    case 16: BOLT_SCAN_M(16); break;
+    case 32: BOLT_SCAN_M(32); break;
+    case 64: BOLT_SCAN_M(64); break;
     }
+#undef BOLT_SCAN_M
 }
 
 void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_t Q, int largest, int64_t stride,
@@ -625,7 +675,7 @@ bool fused_supported(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 
 static size_t plan_bytes(const FusedPlan &p)
 {
-    return p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes + p.spec_bytes;
+    return p.cand_bytes + p.ccnt_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes + p.spec_bytes;
 }
 
 size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
@@ -643,12 +693,15 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
                      const int64_t *tiles, hipStream_t s)
 {
     uint64_t *cand = reinterpret_cast<uint64_t *>(w);
-    uint32_t *gthr = reinterpret_cast<uint32_t *>(w + p.cand_bytes);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(w + p.cand_bytes + p.gthr_bytes);
-    uint64_t *level2 = reinterpret_cast<uint64_t *>(w + p.cand_bytes + p.gthr_bytes + p.hist_bytes);
-    uint32_t *level2_cnt = reinterpret_cast<uint32_t *>(
-        w + p.cand_bytes + p.gthr_bytes + p.hist_bytes + align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)));
-    char *ws_spec = w + p.cand_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
+    w += p.cand_bytes;
+    uint32_t *ccnt = reinterpret_cast<uint32_t *>(w);
+    w += p.ccnt_bytes;
+    uint32_t *gthr = reinterpret_cast<uint32_t *>(w);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w + p.gthr_bytes);
+    uint64_t *level2 = reinterpret_cast<uint64_t *>(w + p.gthr_bytes + p.hist_bytes);
+    uint32_t *level2_cnt = reinterpret_cast<uint32_t *>(w + p.gthr_bytes + p.hist_bytes +
+                                                        align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)));
+    char *ws_spec = w + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
     const int64_t S = (int64_t)p.spec_nsc * kSpecSpan;
     uint16_t *sdist = p.spec ? reinterpret_cast<uint16_t *>(ws_spec) : nullptr;
     uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * S * sizeof(uint16_t)))
@@ -666,20 +719,18 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, sdist, S, (uint32_t)p.spec_r,
                            bolt::hist_shift(M), gthr, bolt::g_spec_mode == 2 ? 1 : 0);
     }
-    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, gthr, tiles, kRowsPerBlock,
+    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, gthr, tiles, kRowsPerBlock,
                   kRowsPerBlock, scan_prof_name(p.kind), s);
-    const int64_t per_query = (int64_t)p.n_rb * k;
     {
         bolt::ProfScope prof_("cand_hist", s);
-        const int64_t hchunk = 4096;
-        hipLaunchKernelGGL(cand_hist_kernel, dim3((unsigned)Q, (unsigned)((per_query + hchunk - 1) / hchunk)),
-                           dim3(256), 0, s, cand, per_query, hchunk, bolt::hist_shift(M), hist);
+        hipLaunchKernelGGL(cand_hist_kernel, dim3((unsigned)Q, (unsigned)((p.n_rb + 255) / 256)), dim3(256), 0, s,
+                           cand, ccnt, (int64_t)p.n_rb, (uint32_t)k, bolt::hist_shift(M), hist);
     }
     const uint32_t smax = 255u * (uint32_t)M;
     {
         bolt::ProfScope prof_("topk_merge", s);
-        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand,
-                           per_query, p.n_chunks > 1 ? p.chunk : per_query, (uint32_t)k, gthr, hist,
+        hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand, ccnt,
+                           (int64_t)p.n_rb, p.n_chunks > 1 ? p.chunk : (int64_t)p.n_rb, (uint32_t)k, gthr, hist,
                            bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx,
                            p.n_chunks > 1 ? nullptr : fail);
         if (p.n_chunks > 1)

@@ -25,6 +25,7 @@
 // [N][ldo] for the approximate matrix product (out = (S + bias) * scale).
 #include "common.hpp"
 #include "scan_common.hpp"
+#include "tiles.hpp"
 
 namespace {
 
@@ -187,6 +188,106 @@ void launch_grouped(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_
     }
 }
 
+// ---------------------------------------------------------------- matrix cores
+
+// Many queries on the int8 matrix cores (the one-hot contraction of
+// tiles.hpp with tables as T - 128, so acc + 128 M is the exact sum):
+// workgroup (row block, block of 32 NT queries), passes of 128 rows with
+// the codes one pass ahead.  Each lane holds four runs of four consecutive
+// rows of one query: written as 8-byte (uint16) or 16-byte (fp32) words
+// when the layout allows (vec), else element by element; the transposed
+// fp32 layout writes 32 consecutive queries of a row per store.
+template <int MM, int NT, OutMode OUT>
+__global__ __launch_bounds__(256) void scan_mfma_kernel(const uint8_t *__restrict__ codes, int64_t N,
+                                                        const uint8_t *__restrict__ luts, int64_t Q, int64_t rpb,
+                                                        uint16_t *__restrict__ out, float *__restrict__ outf,
+                                                        int64_t ldo, float bias, float scale, int vec)
+{
+    constexpr int NW = MM / 8;
+    constexpr int OFF = 128 * MM;
+    __shared__ uint4 onehot[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, col = lane & 31;
+    const int64_t q0 = (int64_t)blockIdx.y * 32 * NT;
+    const int nq = (int)((Q - q0) < 32 * NT ? (Q - q0) : 32 * NT);
+    const int64_t r0 = (int64_t)blockIdx.x * rpb;
+    const int64_t r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
+    bolt::mfma_onehot_init(onehot);
+    bolt::i32x4 tb[NT][MM / 2];
+    bolt::mfma_load_tables<MM, NT>(luts, q0, nq, 0, tb);
+    __syncthreads();
+    const char *oh = reinterpret_cast<const char *>(onehot);
+    uint32_t nxt[NW];
+    {
+        const int64_t n = r0 + 32 * wave + col;
+        load_row<MM>(codes, n < r1 ? n : r1 - 1, nxt);
+    }
+    for (int64_t base = r0; base < r1; base += bolt::kMfmaPass) {
+        uint32_t cw[NW];
+#pragma unroll
+        for (int v = 0; v < NW; ++v)
+            cw[v] = nxt[v];
+        {
+            const int64_t nn = base + bolt::kMfmaPass + 32 * wave + col;
+            load_row<MM>(codes, nn < r1 ? nn : r1 - 1, nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        bolt::i32x16 acc[NT];
+        bolt::mfma_pass<MM, NT>(cw, oh, tb, acc);
+        const int64_t rl = base + 32 * wave + 4 * half;   // first row of this lane's runs
+        const bool full = base + bolt::kMfmaPass <= r1;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t q = q0 + 32 * t + col;
+            if (32 * t + col >= nq)
+                continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = rl + 8 * j;
+                uint32_t sv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    sv[i] = (uint32_t)(acc[t][4 * j + i] + OFF);
+                if (full && vec && OUT == OutMode::U16) {
+                    *reinterpret_cast<uint2 *>(out + q * ldo + row) =
+                        make_uint2(sv[0] | (sv[1] << 16), sv[2] | (sv[3] << 16));
+                } else if (full && vec && OUT == OutMode::F32) {
+                    float f[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float tt = (float)sv[i] + bias;
+                        f[i] = tt * scale;
+                    }
+                    *reinterpret_cast<float4 *>(outf + q * ldo + row) = make_float4(f[0], f[1], f[2], f[3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (full || row + i < r1)
+                            emit<OUT>(sv[i], q, row + i, out, outf, ldo, bias, scale);
+                }
+            }
+        }
+    }
+}
+
+template <int MM, OutMode OUT>
+void launch_mfma(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, uint16_t *out, float *outf,
+                 int64_t ldo, float bias, float scale, hipStream_t s)
+{
+    constexpr int NT = MM <= 32 ? 2 : 1;
+    const int64_t qblocks = (Q + 32 * NT - 1) / (32 * NT);
+    // about 2048 workgroups, whole passes, 512..16384 rows each
+    int64_t rpb = (N * qblocks + 2047) / 2048;
+    rpb = (rpb + bolt::kMfmaPass - 1) / bolt::kMfmaPass * bolt::kMfmaPass;
+    rpb = rpb < 512 ? 512 : (rpb > 16384 ? 16384 : rpb);
+    const int vec = OUT == OutMode::U16 ? (ldo % 4 == 0 && bolt::aligned(out, 8))
+                                        : (OUT == OutMode::F32 ? (ldo % 4 == 0 && bolt::aligned(outf, 16)) : 0);
+    dim3 grid((unsigned)((N + rpb - 1) / rpb), (unsigned)qblocks);
+    bolt::ProfScope prof_("scan_mfma", s);
+    hipLaunchKernelGGL((scan_mfma_kernel<MM, NT, OUT>), grid, dim3(256), 0, s, codes, N, luts, Q, rpb, out, outf,
+                       ldo, bias, scale, vec);
+}
+
 template <OutMode OUT>
 int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q,
                   uint16_t *out, float *outf, int64_t ldo, float bias, float scale, hipStream_t s,
@@ -208,14 +309,17 @@ int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, i
         return BOLT_OK;
     }
     const bool vec_ok = bolt::aligned(codes, 16) && bolt::aligned(luts, 16);
-    // force_kernel: -1 automatic, 0 generic, 1 small, 2 grouped (tests)
+    // force_kernel: -1 automatic, 0 generic, 1 small, 2 grouped, 3 matrix cores (tests)
     int kind = force_kernel;
     const bool tuned_M = (M == 8 || M == 16 || M == 32 || M == 64 || M == 128 || M == 256);
     const bool few_M = (M == 8 || M == 16 || M == 32 || M == 64);
     if (kind < 0)
-        kind = (!tuned_M || !vec_ok) ? 0 : (Q < bolt::kSmallQ ? (few_M ? 1 : 2) : 2);
-    if ((kind == 1 && (!few_M || !vec_ok)) || (kind == 2 && (!tuned_M || !vec_ok)))
-        return bolt::fail(BOLT_ERR_UNSUPPORTED, "tuned scan kernels need a power-of-two M (8..64 for few queries, 8..256 otherwise) and 16-byte aligned codes/tables");
+        kind = (!tuned_M || !vec_ok) ? 0 : (Q < bolt::kSmallQ ? (few_M ? 1 : 2) : (few_M && Q >= 32 ? 3 : 2));
+    if ((kind == 1 && (!few_M || !vec_ok)) || (kind == 2 && (!tuned_M || !vec_ok)) ||
+        (kind == 3 && (!few_M || !vec_ok)))
+        return bolt::fail(BOLT_ERR_UNSUPPORTED, "tuned scan kernels need a power-of-two M (8..64 for few queries "
+                                                "and the matrix cores, 8..256 otherwise) and 16-byte aligned "
+                                                "codes/tables");
     if (kind == 1 && Q >= bolt::kSmallQ)
         return bolt::fail(BOLT_ERR_UNSUPPORTED, "small-Q scan handles at most %d queries", bolt::kSmallQ - 1);
     if (kind == 0) {
@@ -232,6 +336,13 @@ int scan_dispatch(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, i
         }
     } else if (kind == 1) {
         return bolt::few_scan<OUT>(codes, N, M, luts, Q, out, outf, ldo, bias, scale, s);
+    } else if (kind == 3) {
+        switch (M) {
+        case 8: launch_mfma<8, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 16: launch_mfma<16, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 32: launch_mfma<32, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        case 64: launch_mfma<64, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
+        }
     } else {
         switch (M) {
         case 8: launch_grouped<8, 16, OUT>(codes, N, luts, Q, out, outf, ldo, bias, scale, s); break;
@@ -311,11 +422,12 @@ extern "C" int bolt_amm(const uint8_t *codes, int64_t N, int32_t M, const uint8_
                                        g_force_scan_kernel);
 }
 
-// Test hook: pin the scan kernel choice (-1 automatic, 0 generic, 1 few-query, 2 grouped).
+// Test hook: pin the scan kernel choice (-1 automatic, 0 generic, 1 few-query, 2 grouped,
+// 3 matrix cores).
 extern "C" int bolt_debug_force_scan_kernel(int32_t kind)
 {
-    if (kind < -1 || kind > 2)
-        return bolt::fail(BOLT_ERR_INVALID, "kind must be -1..2");
+    if (kind < -1 || kind > 3)
+        return bolt::fail(BOLT_ERR_INVALID, "kind must be -1..3");
     bolt::g_force_scan_kernel = kind;
     return BOLT_OK;
 }

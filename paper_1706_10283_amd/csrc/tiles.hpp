@@ -47,6 +47,7 @@ struct TileJob {
     const uint8_t *codes;   // the database's codes [N][M/2]
     const uint8_t *luts;    // the database's tables [Q][M][16]
     uint64_t *cand;         // the database's candidates [Q][n_rb][k]
+    uint32_t *ccnt = nullptr;   // their counts [Q][n_rb] (packed slots), or null: padded slots
     uint32_t *gthr;         // the database's bounds [Q]
     int64_t r0, r1;         // rows of the tile
     int64_t rb;             // row-block index of the tile
@@ -79,13 +80,16 @@ __device__ __forceinline__ void publish(uint32_t *g, uint32_t T, uint32_t known)
 
 // Final exact local top-k of one query (one wave), written as 48-bit keys.
 // known: the exclusive bound the tile holds (see publish).  Keys above the
-// published bound as read now cannot be in the top-k and are written as
-// padding (~0), which the readers skip; the tile that published the final
-// bound still writes its k keys at or below it, so the histogram built from
-// the written keys always reaches k.
+// published bound as read now cannot be in the top-k; the tile that
+// published the final bound still writes its k keys at or below it, so the
+// histogram built from the written keys always reaches k.  With cnt_dst the
+// kept keys are packed at the front of dst and their number goes to
+// *cnt_dst (readers walk only that part); without it all k slots are
+// written, the dropped keys as padding (~0) that the readers skip.
 template <int CAP, bool LDS_PRUNE>
 __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t r0,
-                                 uint64_t *__restrict__ dst, uint32_t *gthr_q, uint32_t known)
+                                 uint64_t *__restrict__ dst, uint32_t *gthr_q, uint32_t known,
+                                 uint32_t *cnt_dst = nullptr)
 {
     const int lane = threadIdx.x & 63;
     if (n > k) {
@@ -96,6 +100,21 @@ __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t 
             publish(gthr_q, pr.T, known);
     }
     const uint32_t g = __builtin_amdgcn_readfirstlane(read_bound(gthr_q));
+    if (cnt_dst) {
+        uint32_t m = 0;
+        for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const uint32_t lk = j < n ? buf[j] : 0xFFFFFFFFu;
+            const bool keep = j < n && (lk >> 16) <= g;
+            const uint32_t r = ballot_rank(keep);
+            if (keep)
+                dst[m + r] = ((uint64_t)(lk >> 16) << 32) | (uint64_t)(r0 + (lk & 0xFFFFu));
+            m += ballot_count(keep);
+        }
+        if (lane == 0)
+            *cnt_dst = m;
+        return;
+    }
     for (uint32_t j = lane; j < k; j += 64) {
         uint64_t key = ~0ull;
         if (j < n) {
@@ -267,7 +286,8 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
     for (int q = wave; q < nq; q += 4)
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
-                                     &job.gthr[q0 + q], L.bnd[q]);
+                                     &job.gthr[q0 + q], L.bnd[q],
+                                     job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr);
 }
 
 // ------------------------------------------------------------------ matrix cores
@@ -486,7 +506,8 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
     for (int q = wave; q < nq && q < QB; q += 4)
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
-                                     &job.gthr[q0 + q], L.bnd[q]);
+                                     &job.gthr[q0 + q], L.bnd[q],
+                                     job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr);
 }
 
 // Sample distances for the speculative bounds: the d of every (query, row)
@@ -795,7 +816,8 @@ __device__ void few_tile_impl(const TileJob &job, char *lds)
     for (int q = wave; q < nq; q += 4)
         write_local_topk<CAP, true>(buf + q * CAP, cnt[q], k, r0,
                                     job.cand + ((job.q0 + q) * job.n_rb + job.rb) * (int64_t)k,
-                                    &gthr[q], bnd[q]);
+                                    &gthr[q], bnd[q],
+                                    job.ccnt ? job.ccnt + (job.q0 + q) * job.n_rb + job.rb : nullptr);
 }
 
 // A few-query tile; ONE requires job.nq == 1.

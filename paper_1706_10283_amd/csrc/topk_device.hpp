@@ -172,7 +172,7 @@ __device__ PruneResult prune_local(uint32_t *keys, uint32_t n, uint32_t k, bool 
 // keeps exactly the k smallest.  Returns the k-th smallest key (or ~0 if the
 // buffer held at most k keys); the caller stores count = min(n, k).
 template <int CAP>
-__device__ uint64_t prune_u64(uint64_t *keys, uint32_t n, uint32_t k)
+__device__ __attribute__((noinline)) uint64_t prune_u64(uint64_t *keys, uint32_t n, uint32_t k)
 {
     constexpr int PER = (CAP + 63) / 64;
     const int lane = threadIdx.x & 63;

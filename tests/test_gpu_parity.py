@@ -133,13 +133,15 @@ def test_luts_parity(bolt, metric, Q, J, M):
 SCAN_M = [2, 4, 6, 8, 16, 32, 64, 128, 256]
 
 
-@pytest.mark.parametrize("kind", [-1, 0, 1, 2])
+@pytest.mark.parametrize("kind", [-1, 0, 1, 2, 3])
 @pytest.mark.parametrize("M", SCAN_M)
 @pytest.mark.parametrize("Q", [1, 3, 7, 8, 9, 33, 70])
 def test_scan_parity(bolt, kind, M, Q):
     tuned = M in (8, 16, 32, 64, 128, 256)
     if kind == 2 and not tuned:
         pytest.skip("the grouped kernel takes power-of-two M in 8..256")
+    if kind == 3 and M not in (8, 16, 32, 64):
+        pytest.skip("the matrix-core kernel takes M in {8, 16, 32, 64}")
     if kind == 1 and M not in (8, 16, 32, 64):
         pytest.skip("the few-query kernel takes M in {8, 16, 32, 64}")
     if kind == 1 and Q >= 8:
@@ -229,18 +231,25 @@ def test_scan_topk_parity(bolt, metric, M, Q, k):
 
 # ------------------------------------------------------------------ approximate matrix product
 
+@pytest.mark.parametrize("kernel", [-1, 2, 3])
 @pytest.mark.parametrize("transpose", [False, True])
-@pytest.mark.parametrize("K", [1, 5, 64])
-def test_amm_parity(bolt, transpose, K):
+@pytest.mark.parametrize("K", [1, 5, 64, 97])
+def test_amm_parity(bolt, kernel, transpose, K):
     N, M = 2345, 32
-    _say("amm", "N", N, "M", M, "K", K, "transpose", transpose)
+    if kernel >= 2 and K < 8:
+        pytest.skip("the grouped and matrix-core kernels are for 8 or more queries")
+    _say("amm", "N", N, "M", M, "K", K, "transpose", transpose, "kernel", kernel)
     codes = synth.random_codes(K, N, M)
     luts = synth.random_luts(K + 1, K, M)
     bias, scale = np.float32(-311.25), np.float32(1.0 / 3.3)
     S = oracle.scan(codes, luts)
     ref = oracle.rescale_f32(S, float(bias), float(scale))
-    got = bolt.bolt_amm(torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV), float(bias),
-                        float(scale), transpose=transpose).cpu().numpy()
+    bolt.debug_force_scan_kernel(kernel)
+    try:
+        got = bolt.bolt_amm(torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV), float(bias),
+                            float(scale), transpose=transpose).cpu().numpy()
+    finally:
+        bolt.debug_force_scan_kernel(-1)
     if transpose:
         got = got.T
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
