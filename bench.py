@@ -63,14 +63,15 @@ HBM_PEAK_GBPS = 8000.0
 FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC = {
-    "scan_topk_grouped": {
+    "scan_topk_mfma": {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 13069.3,
-        "write_kib": 49929.8,
-        "sources_sha256": "34cacd3ffcd72a257b3be44e1394d7b62529550922c6edca78d0087fb96d08bb",
+        "fetch_kib": 9899.3,
+        "write_kib": 8721.0,
+        "sources_sha256": "16b56773cdcb9f2d23b530aa4e78ba3f4e7d822656369e0c9759df9ed86c5be0",
     },
 }
 TRAFFIC_SOURCES = {
+    "scan_topk_mfma": ["fused.hip", "tiles.hpp", "topk_device.hpp", "scan_common.hpp"],
     "scan_topk_grouped": ["fused.hip", "tiles.hpp", "topk_device.hpp", "scan_common.hpp"],
 }
 

@@ -477,7 +477,7 @@ constexpr int ng_for()
 // rounded up to its bin's edge.  The bound only selects candidates: the
 // final merge flags any query with fewer than k candidates and
 // topk_redo_kernel recomputes it exactly, so results never depend on it.
-constexpr int64_t kSpecSpan = 2048;            // rows per sample chunk
+constexpr int64_t kSpecSpan = 1024;            // rows per sample chunk
 constexpr int64_t kSpecMinRows = 1 << 19;      // smaller databases scan without it
 constexpr int64_t kSpecMinRowsForced = 1 << 17;
 constexpr int64_t kSpecMaxDists = 1 << 26;     // sample distances held at once (128 MB)
@@ -542,15 +542,15 @@ static int spec_rank(int k, double pr)
 }
 
 // Speculation for a whole-database plan of kind 2 or 3: about N / 32 sample
-// rows (8 to 128 chunks), fewer if Q of them would not fit kSpecMaxDists.
+// rows (16 to 256 chunks), fewer if Q of them would not fit kSpecMaxDists.
 static void plan_spec(FusedPlan &p, int64_t N, int64_t Q, int k)
 {
     const int mode = bolt::g_spec_mode;
     if (p.kind < 2 || mode == 0 || N < (mode > 0 ? kSpecMinRowsForced : kSpecMinRows))
         return;
     int64_t nsc = N / 32 / kSpecSpan;
-    nsc = nsc < 8 ? 8 : (nsc > 128 ? 128 : nsc);
-    while (nsc > 8 && Q * nsc * kSpecSpan > kSpecMaxDists)
+    nsc = nsc < 16 ? 16 : (nsc > 256 ? 256 : nsc);
+    while (nsc > 16 && Q * nsc * kSpecSpan > kSpecMaxDists)
         nsc /= 2;
     if (Q * nsc * kSpecSpan > kSpecMaxDists)
         return;
