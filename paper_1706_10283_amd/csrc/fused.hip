@@ -471,7 +471,7 @@ constexpr int ng_for()
 // d over a sample of S rows (chunks of kSpecSpan rows at a regular stride)
 // bounds the k-th smallest d of the database unless r of the database's k
 // smallest rows fall in the sample; for a random row order that number is
-// binomial(k, S / N), and r is the smallest rank whose tail is below 1e-9
+// binomial(k, S / N), and r is the smallest rank whose tail is below 1e-7
 // (r = k: the bound is certain).  The sample's distances come from the
 // matrix cores (whatever kernel scans), the r-th smallest from a histogram,
 // rounded up to its bin's edge.  The bound only selects candidates: the
@@ -522,7 +522,7 @@ bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
     return true;
 }
 
-// Smallest r with P(binomial(k, p) >= r) <= 1e-9, at most k.
+// Smallest r with P(binomial(k, p) >= r) <= 1e-7, at most k.
 static int spec_rank(int k, double pr)
 {
     std::vector<double> pmf(k + 1);
@@ -534,7 +534,7 @@ static int spec_rank(int k, double pr)
     int r = k;
     for (int j = k; j >= 1; --j) {
         tail += pmf[j];
-        if (tail > 1e-9)
+        if (tail > 1e-7)
             break;
         r = j;
     }
