@@ -87,7 +87,7 @@ template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void few_scan_topk_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int nq, uint32_t k,
     int largest, int64_t rows_per_block, int n_rb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
 {
     extern __shared__ __attribute__((aligned(16))) char few_lds[];
     bolt::TileJob job;
@@ -95,6 +95,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     job.luts = luts;
     job.cand = cand;
     job.ccnt = ccnt;
+    job.hist = hist;
+    job.hist_shift = bolt::hist_shift(MM);
     job.gthr = gthr;
     job.rb = blockIdx.x;
     if (tiles) {   // row ranges given by the caller, cut into tiles
@@ -118,12 +120,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
 // are loaded with a uniform base and 32-bit lane offsets, unconditionally,
 // so the next pass stays in flight while this one is computed.  Each tile
 // writes its exact local top-k to cand[tile][k] (packed, count in
-// ccnt[tile], when ccnt is given).
+// ccnt[tile] and keys counted in hist, when ccnt is given).
 template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void one_scan_topk_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k,
     int largest, int64_t tile_rows, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
 {
     constexpr int R = bolt::few_r(MM);
     constexpr int PASS = bolt::few_pass(MM);
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void o
     }
     if (wave == 0)
         bolt::write_local_topk<CAP, true>(buf, s_cnt, k, r0, cand + tile * k, gthr, s_bnd,
-                                          ccnt ? ccnt + tile : nullptr);
+                                          ccnt ? ccnt + tile : nullptr, hist, bolt::hist_shift(MM));
 }
 
 size_t few_lds_bytes(int M, int nq, bool fused)
@@ -213,15 +215,16 @@ void launch_few_scan(const uint8_t *codes, int64_t N, const uint8_t *luts, int n
 
 template <int MM>
 void launch_few_scan_topk(const uint8_t *codes, int64_t N, const uint8_t *luts, int nq, int k, bool largest,
-                          int64_t rpb, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
+                          int64_t rpb, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
                           const int64_t *tiles, hipStream_t s)
 {
     if (nq == 1)
         hipLaunchKernelGGL(one_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), 0, s, codes, N, luts, (uint32_t)k,
-                           (int)largest, rpb, cand, ccnt, gthr, tiles);
+                           (int)largest, rpb, cand, ccnt, hist, gthr, tiles);
     else
         hipLaunchKernelGGL(few_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), few_lds_bytes(MM, nq, true), s,
-                           codes, N, luts, nq, (uint32_t)k, (int)largest, rpb, n_rb, cand, ccnt, gthr, tiles);
+                           codes, N, luts, nq, (uint32_t)k, (int)largest, rpb, n_rb, cand, ccnt, hist, gthr,
+                           tiles);
 }
 
 template <int MM>
@@ -325,19 +328,19 @@ int64_t few_rows_per_block(int64_t N, int M, int nq)
 }
 
 // Stage 1 of the fused few-query path: candidates [Q][n_rb][k] (packed,
-// counts [Q][n_rb] in ccnt, if given) and bounds.
+// counts [Q][n_rb] in ccnt and histograms in hist, if given) and bounds.
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                  bool largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr, const int64_t *tiles,
-                  hipStream_t s)
+                  bool largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
+                  const int64_t *tiles, hipStream_t s)
 {
     const int nq = (int)Q;
     const int64_t rpb = few_rows_per_block(N, M, nq);
     bolt::ProfScope prof_("scan_topk_few", s);
     switch (M) {
-    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, gthr, tiles, s); break;
-    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, gthr, tiles, s); break;
-    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, gthr, tiles, s); break;
-    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, gthr, tiles, s); break;
+    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
+    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
+    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
+    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
     default: return fail(BOLT_ERR_UNSUPPORTED, "few-query scan takes M in {8, 16, 32, 64}");
     }
     return BOLT_OK;

@@ -49,8 +49,9 @@ __device__ __forceinline__ void tile_of(int w, int n_qb, int &qb, int &rb)
 // workgroup has no tile (padding of the XCD placement).
 __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uint8_t *codes, int64_t N,
                                          const uint8_t *luts, int64_t Q, uint32_t k, int largest, int n_rb,
-                                         uint64_t *cand, uint32_t *ccnt, uint32_t *gthr, const int64_t *tiles,
-                                         int64_t stride, int64_t span, bolt::TileJob &job)
+                                         uint64_t *cand, uint32_t *ccnt, uint32_t *hist, int shift,
+                                         uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span,
+                                         bolt::TileJob &job)
 {
     int qb, rb;
     tile_of(w, n_qb, qb, rb);
@@ -60,6 +61,8 @@ __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uin
     job.luts = luts;
     job.cand = cand;
     job.ccnt = ccnt;
+    job.hist = hist;
+    job.hist_shift = shift;
     job.gthr = gthr;
     if (tiles) {   // row ranges given by the caller, cut into tiles
         job.r0 = tiles[2 * rb];
@@ -81,12 +84,13 @@ template <int MM, int NG>
 __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride,
+    int64_t span)
 {
     __shared__ bolt::GroupedLds<MM, NG> L;
     bolt::TileJob job;
-    if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, gthr, tiles, stride,
-                 span, job))
+    if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
+                 bolt::hist_shift(MM), gthr, tiles, stride, span, job))
         bolt::grouped_tile<MM, NG>(job, L);
 }
 
@@ -95,12 +99,13 @@ template <int MM, int NT>
 __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride,
+    int64_t span)
 {
     __shared__ bolt::MfmaLds<NT> L;
     bolt::TileJob job;
-    if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, gthr, tiles, stride,
-                 span, job))
+    if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
+                 bolt::hist_shift(MM), gthr, tiles, stride, span, job))
         bolt::mfma_tile<MM, NT>(job, L);
 }
 
@@ -150,6 +155,62 @@ __device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int 
     }
     const uint32_t edge = (((uint32_t)__shfl(bin, first) + 1u) << shift) - 1u;
     return edge < bound ? edge : bound;
+}
+
+// Exact top-k of one query whose speculative bound failed (fewer than k
+// rows passed it), by the merging workgroup itself: it scans every row with
+// the query's table in LDS, appends keys (d << 32 | row) below the running
+// bound and prunes by the merge's scheme, then writes the sorted result.
+__device__ void redo_query(bolt::MergeLds &L, const uint8_t *__restrict__ codes, int64_t N, int M,
+                           const uint8_t *__restrict__ luts, int64_t q, uint32_t k, int largest,
+                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    __shared__ uint16_t tab[64 * 16];   // d contribution of (subspace, code)
+    const int tid = threadIdx.x;
+    __syncthreads();   // the caller is done with L
+    for (int e = tid; e < M * 16; e += 256) {
+        const uint32_t v = luts[q * M * 16 + e];
+        tab[e] = (uint16_t)(largest ? 255u - v : v);
+    }
+    if (tid == 0) {
+        L.mcnt = 0;
+        L.mbound = ~0ull;
+    }
+    __syncthreads();
+    const int half = M / 2;
+    for (int64_t c0 = 0; c0 < N; c0 += 256 * bolt::kMergeE) {
+        const uint64_t bnd = L.mbound;
+        for (int e = 0; e < bolt::kMergeE; ++e) {
+            const int64_t row = c0 + tid + 256 * e;
+            if (row < N) {
+                const uint8_t *pr = codes + row * half;
+                uint32_t d = 0;
+                for (int b = 0; b < half; ++b) {
+                    const uint32_t byte = pr[b];
+                    d += tab[(2 * b) * 16 + (byte & 15u)] + tab[(2 * b + 1) * 16 + (byte >> 4)];
+                }
+                const uint64_t key = ((uint64_t)d << 32) | (uint64_t)row;
+                if (key < bnd) {
+                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                    L.mb[pos] = key;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < 64 && L.mcnt > bolt::kMergeCap - 256 * bolt::kMergeE) {
+            const uint64_t kth = bolt::prune_u64<bolt::kMergeCap>(L.mb, L.mcnt, k);
+            if (tid == 0) {
+                L.mcnt = k;
+                L.mbound = kth + 1;
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t n = L.mcnt;
+    if (tid < 64 && n > k)
+        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
+    __syncthreads();
+    bolt::merge_emit(L, n > k ? k : n, k, largest, 255u * (uint32_t)M, vals + q * k, idx + q * k);
 }
 
 // Appends to L every key below L.mbound from slots [s_lo, s_hi) (slot s:
@@ -223,10 +284,11 @@ __device__ uint32_t merge_walk(bolt::MergeLds &L, uint32_t *pre, const uint64_t 
 // Merge, level 1: one workgroup per (query, chunk of the query's tile
 // slots).  Keys with d above the bound from the query's candidate histogram
 // cannot be in its top-k and are skipped.  With one chunk the workgroup
-// writes the sorted values and rows (and flags the query in fail, if given,
-// when fewer than k keys passed); with several, the chunk's exact k smallest
+// writes the sorted values and rows; with several, the chunk's exact k smallest
 // survivors go to its slot dst[q][chunk][k] and their number to
-// dst_cnt[q][chunk].  No atomics outside LDS: the slots are fixed.
+// dst_cnt[q][chunk].  No atomics outside LDS: the slots are fixed.  With
+// spec (speculative starting bounds), the workgroup that finds fewer than k
+// keys for its query recomputes the query exactly (redo_query).
 __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restrict__ cand,
                                                          const uint32_t *__restrict__ ccnt, int64_t n_rb,
                                                          int64_t slots_per_chunk, uint32_t k,
@@ -235,7 +297,9 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
                                                          int largest, uint32_t smax, uint64_t *__restrict__ dst,
                                                          uint32_t *__restrict__ dst_cnt,
                                                          uint16_t *__restrict__ vals,
-                                                         int32_t *__restrict__ idx, uint32_t *__restrict__ fail)
+                                                         int32_t *__restrict__ idx, int spec,
+                                                         const uint8_t *__restrict__ codes, int64_t N, int M,
+                                                         const uint8_t *__restrict__ luts)
 {
     __shared__ bolt::MergeLds L;
     __shared__ uint32_t pre[257];
@@ -258,9 +322,10 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
         bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
     __syncthreads();
     if (gridDim.y == 1) {
-        if (fail && threadIdx.x == 0 && n < k)
-            fail[q] = 1u;
-        bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
+        if (spec && n < k)
+            redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
+        else
+            bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
         return;
     }
     n = n > k ? k : n;
@@ -278,7 +343,8 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
                                                           uint32_t k, const uint32_t *__restrict__ gthr,
                                                           int largest, uint32_t smax,
                                                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx,
-                                                          uint32_t *__restrict__ fail)
+                                                          int spec, const uint8_t *__restrict__ codes, int64_t N,
+                                                          int M, const uint8_t *__restrict__ luts)
 {
     __shared__ bolt::MergeLds L;
     __shared__ uint32_t pre[257];
@@ -291,8 +357,10 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     __syncthreads();
     const uint32_t n = merge_walk(L, pre, src + q * (int64_t)n_chunks * k, src_cnt + q * (int64_t)n_chunks, 0,
                                   n_chunks, k);
-    if (fail && tid == 0 && n < k)
-        fail[q] = 1u;
+    if (spec && n < k) {
+        redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
+        return;
+    }
     if (tid < 64 && n > k)
         bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
     __syncthreads();
@@ -309,44 +377,14 @@ __global__ void pad_topk_kernel(uint16_t *vals, int32_t *idx, int64_t n, int lar
     }
 }
 
-// Bounds start open (65535: every d passes), histograms empty and no query
-// failed (fail: the failure flags of speculative bounds, if any).
-__global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, int64_t n_hist, uint32_t *fail)
+// Bounds start open (65535: every d passes) and histograms empty.
+__global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, int64_t n_hist)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < Q) {
+    if (i < Q)
         gthr[i] = 0xFFFFu;
-        if (fail)
-            fail[i] = 0u;
-    }
     if (i < n_hist)
         hist[i] = 0;
-}
-
-// Histogram of the d values of the candidate keys: one workgroup per
-// (query, 256 tile slots), one slot per thread; counted in LDS, nonzero bins
-// added to the query's global histogram.
-__global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restrict__ cand,
-                                                        const uint32_t *__restrict__ ccnt, int64_t n_rb, uint32_t k,
-                                                        int shift, uint32_t *__restrict__ hist)
-{
-    __shared__ uint32_t h[bolt::kHistBins];
-    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
-        h[i] = 0;
-    __syncthreads();
-    const int64_t q = blockIdx.x;
-    const int64_t slot = (int64_t)blockIdx.y * 256 + threadIdx.x;
-    if (slot < n_rb) {
-        uint32_t m = ccnt[q * n_rb + slot];
-        m = m < k ? m : k;
-        const uint64_t *c = cand + (q * n_rb + slot) * k;
-        for (uint32_t j = 0; j < m; ++j)
-            atomicAdd(&h[(uint32_t)(c[j] >> 32) >> shift], 1u);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
-        if (h[i])
-            atomicAdd(&hist[q * bolt::kHistBins + i], h[i]);
 }
 
 // Sample distances (speculative bounds): workgroup (query block, chunk c)
@@ -368,16 +406,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
 // Speculative bound of one query (one workgroup): histogram of its S sample
 // distances and the upper edge of the bin holding the r-th smallest, written
 // as the query's starting bound (0 when a test forces every query onto the
-// recomputation).
+// recomputation).  Also clears the query's candidate histogram (this kernel
+// replaces the initialisation when the bounds are speculative).
 __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ dists, int64_t S,
                                                           uint32_t r, int shift, uint32_t *__restrict__ gthr,
-                                                          int force_fail)
+                                                          uint32_t *__restrict__ hist, int force_fail)
 {
     __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
-    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
-        h[i] = 0;
-    __syncthreads();
     const int64_t q = blockIdx.x;
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256) {
+        h[i] = 0;
+        hist[q * bolt::kHistBins + i] = 0;
+    }
+    __syncthreads();
     const uint4 *d = reinterpret_cast<const uint4 *>(dists + q * S);   // 8 distances per load
     for (int64_t i = threadIdx.x; i < S / 8; i += 256) {
         const uint4 v = d[i];
@@ -394,67 +435,6 @@ __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__rest
         if (threadIdx.x == 0)
             gthr[q] = force_fail ? 0u : b;
     }
-}
-
-// Exact top-k of one query whose speculative bound failed (fewer than k
-// rows passed it): one workgroup scans every row with the query's table in
-// LDS, appends keys (d << 32 | row) below the running bound and prunes by
-// the merge's scheme, then writes the sorted result over the merged one.
-// Workgroups of queries that did not fail return at once.
-__global__ __launch_bounds__(256) void topk_redo_kernel(const uint8_t *__restrict__ codes, int64_t N, int M,
-                                                        const uint8_t *__restrict__ luts, uint32_t k, int largest,
-                                                        const uint32_t *__restrict__ fail,
-                                                        uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
-{
-    const int64_t q = blockIdx.x;
-    if (!fail[q])
-        return;
-    __shared__ bolt::MergeLds L;
-    __shared__ uint16_t tab[64 * 16];   // d contribution of (subspace, code)
-    const int tid = threadIdx.x;
-    for (int e = tid; e < M * 16; e += 256) {
-        const uint32_t v = luts[q * M * 16 + e];
-        tab[e] = (uint16_t)(largest ? 255u - v : v);
-    }
-    if (tid == 0) {
-        L.mcnt = 0;
-        L.mbound = ~0ull;
-    }
-    __syncthreads();
-    const int half = M / 2;
-    for (int64_t c0 = 0; c0 < N; c0 += 256 * bolt::kMergeE) {
-        const uint64_t bnd = L.mbound;
-        for (int e = 0; e < bolt::kMergeE; ++e) {
-            const int64_t row = c0 + tid + 256 * e;
-            if (row < N) {
-                const uint8_t *pr = codes + row * half;
-                uint32_t d = 0;
-                for (int b = 0; b < half; ++b) {
-                    const uint32_t byte = pr[b];
-                    d += tab[(2 * b) * 16 + (byte & 15u)] + tab[(2 * b + 1) * 16 + (byte >> 4)];
-                }
-                const uint64_t key = ((uint64_t)d << 32) | (uint64_t)row;
-                if (key < bnd) {
-                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
-                    L.mb[pos] = key;
-                }
-            }
-        }
-        __syncthreads();
-        if (tid < 64 && L.mcnt > bolt::kMergeCap - 256 * bolt::kMergeE) {
-            const uint64_t kth = bolt::prune_u64<bolt::kMergeCap>(L.mb, L.mcnt, k);
-            if (tid == 0) {
-                L.mcnt = k;
-                L.mbound = kth + 1;
-            }
-        }
-        __syncthreads();
-    }
-    const uint32_t n = L.mcnt;
-    if (tid < 64 && n > k)
-        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
-    __syncthreads();
-    bolt::merge_emit(L, n > k ? k : n, k, largest, 255u * (uint32_t)M, vals + q * k, idx + q * k);
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -476,7 +456,7 @@ constexpr int ng_for()
 // matrix cores (whatever kernel scans), the r-th smallest from a histogram,
 // rounded up to its bin's edge.  The bound only selects candidates: the
 // final merge flags any query with fewer than k candidates and
-// topk_redo_kernel recomputes it exactly, so results never depend on it.
+// redo_query recomputes it exactly, so results never depend on it.
 constexpr int64_t kSpecSpan = 1024;            // rows per sample chunk
 constexpr int64_t kSpecMinRows = 1 << 19;      // smaller databases scan without it
 constexpr int64_t kSpecMinRowsForced = 1 << 17;
@@ -492,7 +472,7 @@ struct FusedPlan {
     bool spec = false;   // speculative bound from a sample
     int spec_r = 0, spec_nsc = 0;
     int64_t spec_stride = 0;
-    size_t spec_bytes = 0;   // sample distances [Q][nsc * kSpecSpan] uint16, failure flags [Q]
+    size_t spec_bytes = 0;   // sample distances [Q][nsc * kSpecSpan] uint16
 };
 
 // The kernel for the shape and its rows per tile (N: rows to scan).
@@ -580,9 +560,7 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
                                     : 0;
     if (p.n_chunks > 65535)
         return p;
-    p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * kSpecSpan * sizeof(uint16_t)) +
-                                align256((size_t)Q * sizeof(uint32_t))
-                          : 0;
+    p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * kSpecSpan * sizeof(uint16_t)) : 0;
     p.ok = true;
     return p;
 }
@@ -601,29 +579,32 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 // list, or of span rows every stride rows; k candidates per tile and query.
 template <int MM>
 void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k,
-                 int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr, const int64_t *tiles,
-                 int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
+                 int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
+                 const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
 {
     if (p.kind == 1) {   // profiled inside under its own name
-        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, ccnt, gthr, tiles, s);
+        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, ccnt, hist, gthr, tiles, s);
         return;
     }
     const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
     bolt::ProfScope prof_(prof_name, s);
     if (p.kind == 3)
         hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1>), dim3(grid), dim3(256), 0, s, codes, N,
-                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, gthr, tiles, stride, span);
+                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, gthr, tiles, stride,
+                           span);
     else
         hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes, N,
-                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, gthr, tiles, stride, span);
+                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, gthr, tiles, stride,
+                           span);
 }
 
 void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
-                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
+                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
                    const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
 {
 #define BOLT_SCAN_M(MMV)                                                                                         \
-    launch_scan<MMV>(p, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, gthr, tiles, stride, span, prof_name, s)
+    launch_scan<MMV>(p, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist, gthr, tiles, stride, span,        \
+                     prof_name, s)
     switch (M) {
     case 8: BOLT_SCAN_M(8); break;
     case 16: BOLT_SCAN_M(16); break;
@@ -704,43 +685,35 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     char *ws_spec = w + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
     const int64_t S = (int64_t)p.spec_nsc * kSpecSpan;
     uint16_t *sdist = p.spec ? reinterpret_cast<uint16_t *>(ws_spec) : nullptr;
-    uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * S * sizeof(uint16_t)))
-                            : nullptr;
-    const int64_t n_hist = Q * bolt::kHistBins;
-    hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
-                       hist, n_hist, fail);
     if (p.spec) {
-        // sample distances, then each query's starting bound
+        // sample distances, then each query's starting bound (and cleared histogram)
         {
             bolt::ProfScope prof_("spec_sample", s);
             launch_spec_sample(M, codes, luts, Q, (int)largest, p.spec_stride, S, p.spec_nsc, sdist, s);
         }
         bolt::ProfScope prof_("spec_select", s);
         hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, sdist, S, (uint32_t)p.spec_r,
-                           bolt::hist_shift(M), gthr, bolt::g_spec_mode == 2 ? 1 : 0);
+                           bolt::hist_shift(M), gthr, hist, bolt::g_spec_mode == 2 ? 1 : 0);
+    } else {
+        const int64_t n_hist = Q * bolt::kHistBins;
+        hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
+                           hist, n_hist);
     }
-    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, gthr, tiles, kRowsPerBlock,
+    // the tiles count their kept keys into hist as they write them
+    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, hist, gthr, tiles, kRowsPerBlock,
                   kRowsPerBlock, scan_prof_name(p.kind), s);
-    {
-        bolt::ProfScope prof_("cand_hist", s);
-        hipLaunchKernelGGL(cand_hist_kernel, dim3((unsigned)Q, (unsigned)((p.n_rb + 255) / 256)), dim3(256), 0, s,
-                           cand, ccnt, (int64_t)p.n_rb, (uint32_t)k, bolt::hist_shift(M), hist);
-    }
     const uint32_t smax = 255u * (uint32_t)M;
+    const int spec = p.spec ? 1 : 0;
     {
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand, ccnt,
                            (int64_t)p.n_rb, p.n_chunks > 1 ? p.chunk : (int64_t)p.n_rb, (uint32_t)k, gthr, hist,
-                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx,
-                           p.n_chunks > 1 ? nullptr : fail);
+                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, spec, codes, N,
+                           M, luts);
         if (p.n_chunks > 1)
             hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
-                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, fail);
-    }
-    if (p.spec) {
-        bolt::ProfScope prof_("topk_redo", s);
-        hipLaunchKernelGGL(topk_redo_kernel, dim3((unsigned)Q), dim3(256), 0, s, codes, N, M, luts, (uint32_t)k,
-                           (int)largest, fail, vals, idx);
+                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, spec, codes, N, M,
+                               luts);
     }
     return check_launch("bolt_scan_topk (fused)");
 }

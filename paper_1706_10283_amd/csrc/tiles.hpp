@@ -48,6 +48,8 @@ struct TileJob {
     const uint8_t *luts;    // the database's tables [Q][M][16]
     uint64_t *cand;         // the database's candidates [Q][n_rb][k]
     uint32_t *ccnt = nullptr;   // their counts [Q][n_rb] (packed slots), or null: padded slots
+    uint32_t *hist = nullptr;   // with ccnt: per-query histograms [Q][kHistBins] of the kept keys
+    int hist_shift = 0;
     uint32_t *gthr;         // the database's bounds [Q]
     int64_t r0, r1;         // rows of the tile
     int64_t rb;             // row-block index of the tile
@@ -84,12 +86,14 @@ __device__ __forceinline__ void publish(uint32_t *g, uint32_t T, uint32_t known)
 // published the final bound still writes its k keys at or below it, so the
 // histogram built from the written keys always reaches k.  With cnt_dst the
 // kept keys are packed at the front of dst and their number goes to
-// *cnt_dst (readers walk only that part); without it all k slots are
-// written, the dropped keys as padding (~0) that the readers skip.
+// *cnt_dst (readers walk only that part), and with hist_q each kept key is
+// also counted in the query's histogram (bin d >> shift); without cnt_dst
+// all k slots are written, the dropped keys as padding (~0) that the
+// readers skip.
 template <int CAP, bool LDS_PRUNE>
 __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t r0,
                                  uint64_t *__restrict__ dst, uint32_t *gthr_q, uint32_t known,
-                                 uint32_t *cnt_dst = nullptr)
+                                 uint32_t *cnt_dst = nullptr, uint32_t *hist_q = nullptr, int shift = 0)
 {
     const int lane = threadIdx.x & 63;
     if (n > k) {
@@ -107,8 +111,11 @@ __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t 
             const uint32_t lk = j < n ? buf[j] : 0xFFFFFFFFu;
             const bool keep = j < n && (lk >> 16) <= g;
             const uint32_t r = ballot_rank(keep);
-            if (keep)
+            if (keep) {
                 dst[m + r] = ((uint64_t)(lk >> 16) << 32) | (uint64_t)(r0 + (lk & 0xFFFFu));
+                if (hist_q)
+                    atomicAdd(&hist_q[(lk >> 16) >> shift], 1u);
+            }
             m += ballot_count(keep);
         }
         if (lane == 0)
@@ -287,7 +294,8 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
                                      &job.gthr[q0 + q], L.bnd[q],
-                                     job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr);
+                                     job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr,
+                                     job.hist ? job.hist + (q0 + q) * kHistBins : nullptr, job.hist_shift);
 }
 
 // ------------------------------------------------------------------ matrix cores
@@ -507,7 +515,8 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
                                      &job.gthr[q0 + q], L.bnd[q],
-                                     job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr);
+                                     job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr,
+                                     job.hist ? job.hist + (q0 + q) * kHistBins : nullptr, job.hist_shift);
 }
 
 // Sample distances for the speculative bounds: the d of every (query, row)
@@ -817,7 +826,8 @@ __device__ void few_tile_impl(const TileJob &job, char *lds)
         write_local_topk<CAP, true>(buf + q * CAP, cnt[q], k, r0,
                                     job.cand + ((job.q0 + q) * job.n_rb + job.rb) * (int64_t)k,
                                     &gthr[q], bnd[q],
-                                    job.ccnt ? job.ccnt + (job.q0 + q) * job.n_rb + job.rb : nullptr);
+                                    job.ccnt ? job.ccnt + (job.q0 + q) * job.n_rb + job.rb : nullptr,
+                                    job.hist ? job.hist + (job.q0 + q) * kHistBins : nullptr, job.hist_shift);
 }
 
 // A few-query tile; ONE requires job.nq == 1.
