@@ -50,8 +50,8 @@ __device__ __forceinline__ void tile_of(int w, int n_qb, int &qb, int &rb)
 __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uint8_t *codes, int64_t N,
                                          const uint8_t *luts, int64_t Q, uint32_t k, int largest, int n_rb,
                                          uint64_t *cand, uint32_t *ccnt, uint32_t *hist, int shift,
-                                         uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span,
-                                         bolt::TileJob &job)
+                                         uint32_t *fail, uint32_t *gthr, const int64_t *tiles, int64_t stride,
+                                         int64_t span, bolt::TileJob &job)
 {
     int qb, rb;
     tile_of(w, n_qb, qb, rb);
@@ -63,6 +63,7 @@ __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uin
     job.ccnt = ccnt;
     job.hist = hist;
     job.hist_shift = shift;
+    job.fail = fail;
     job.gthr = gthr;
     if (tiles) {   // row ranges given by the caller, cut into tiles
         job.r0 = tiles[2 * rb];
@@ -84,29 +85,30 @@ template <int MM, int NG>
 __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride,
-    int64_t span)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ fail, uint32_t *__restrict__ gthr,
+    const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
 {
     __shared__ bolt::GroupedLds<MM, NG> L;
     bolt::TileJob job;
     if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
-                 bolt::hist_shift(MM), gthr, tiles, stride, span, job))
+                 bolt::hist_shift(MM), fail, gthr, tiles, stride, span, job))
         bolt::grouped_tile<MM, NG>(job, L);
 }
 
-// Matrix-core tiles: 32 NT queries per workgroup (tables in registers).
-template <int MM, int NT>
+// Matrix-core tiles: 32 NT queries per workgroup (tables in registers);
+// FREE: barrier-free passes under speculative bounds (see mfma_tile).
+template <int MM, int NT, bool FREE>
 __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles, int64_t stride,
-    int64_t span)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ fail, uint32_t *__restrict__ gthr,
+    const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
 {
     __shared__ bolt::MfmaLds<NT> L;
     bolt::TileJob job;
     if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
-                 bolt::hist_shift(MM), gthr, tiles, stride, span, job))
-        bolt::mfma_tile<MM, NT>(job, L);
+                 bolt::hist_shift(MM), fail, gthr, tiles, stride, span, job))
+        bolt::mfma_tile<MM, NT, FREE>(job, L);
 }
 
 // ------------------------------------------------------------------ merge
@@ -287,8 +289,9 @@ __device__ uint32_t merge_walk(bolt::MergeLds &L, uint32_t *pre, const uint64_t 
 // writes the sorted values and rows; with several, the chunk's exact k smallest
 // survivors go to its slot dst[q][chunk][k] and their number to
 // dst_cnt[q][chunk].  No atomics outside LDS: the slots are fixed.  With
-// spec (speculative starting bounds), the workgroup that finds fewer than k
-// keys for its query recomputes the query exactly (redo_query).
+// fail (speculative starting bounds), the workgroup that finds fewer than k
+// keys for its query, or its overflow flag set, recomputes the query exactly
+// (redo_query).
 __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restrict__ cand,
                                                          const uint32_t *__restrict__ ccnt, int64_t n_rb,
                                                          int64_t slots_per_chunk, uint32_t k,
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
                                                          int largest, uint32_t smax, uint64_t *__restrict__ dst,
                                                          uint32_t *__restrict__ dst_cnt,
                                                          uint16_t *__restrict__ vals,
-                                                         int32_t *__restrict__ idx, int spec,
+                                                         int32_t *__restrict__ idx, const uint32_t *__restrict__ fail,
                                                          const uint8_t *__restrict__ codes, int64_t N, int M,
                                                          const uint8_t *__restrict__ luts)
 {
@@ -322,7 +325,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
         bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
     __syncthreads();
     if (gridDim.y == 1) {
-        if (spec && n < k)
+        if (fail && (n < k || fail[q]))
             redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
         else
             bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
@@ -343,8 +346,9 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
                                                           uint32_t k, const uint32_t *__restrict__ gthr,
                                                           int largest, uint32_t smax,
                                                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx,
-                                                          int spec, const uint8_t *__restrict__ codes, int64_t N,
-                                                          int M, const uint8_t *__restrict__ luts)
+                                                          const uint32_t *__restrict__ fail,
+                                                          const uint8_t *__restrict__ codes, int64_t N, int M,
+                                                          const uint8_t *__restrict__ luts)
 {
     __shared__ bolt::MergeLds L;
     __shared__ uint32_t pre[257];
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     __syncthreads();
     const uint32_t n = merge_walk(L, pre, src + q * (int64_t)n_chunks * k, src_cnt + q * (int64_t)n_chunks, 0,
                                   n_chunks, k);
-    if (spec && n < k) {
+    if (fail && (n < k || fail[q])) {
         redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
         return;
     }
@@ -406,11 +410,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
 // Speculative bound of one query (one workgroup): histogram of its S sample
 // distances and the upper edge of the bin holding the r-th smallest, written
 // as the query's starting bound (0 when a test forces every query onto the
-// recomputation).  Also clears the query's candidate histogram (this kernel
-// replaces the initialisation when the bounds are speculative).
+// recomputation).  Also clears the query's candidate histogram and overflow
+// flag (this kernel replaces the initialisation when the bounds are
+// speculative).
 __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ dists, int64_t S,
                                                           uint32_t r, int shift, uint32_t *__restrict__ gthr,
-                                                          uint32_t *__restrict__ hist, int force_fail)
+                                                          uint32_t *__restrict__ hist, uint32_t *__restrict__ fail,
+                                                          int force_fail)
 {
     __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
     const int64_t q = blockIdx.x;
@@ -432,8 +438,10 @@ __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__rest
     __syncthreads();
     if (threadIdx.x < 64) {
         const uint32_t b = hist_bound(h, r, shift, 0xFFFFu);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             gthr[q] = force_fail ? 0u : b;
+            fail[q] = 0u;
+        }
     }
 }
 
@@ -472,7 +480,7 @@ struct FusedPlan {
     bool spec = false;   // speculative bound from a sample
     int spec_r = 0, spec_nsc = 0;
     int64_t spec_stride = 0;
-    size_t spec_bytes = 0;   // sample distances [Q][nsc * kSpecSpan] uint16
+    size_t spec_bytes = 0;   // sample distances [Q][nsc * kSpecSpan] uint16, overflow flags [Q]
 };
 
 // The kernel for the shape and its rows per tile (N: rows to scan).
@@ -488,9 +496,10 @@ bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
         p.qb_size = (int)Q;
     } else {
         p.rpb = kRowsPerBlock;
+        // the matrix cores from M = 16 (at M = 8 the grouped kernel's lookups are cheaper)
         const bool mfma_ok = k <= bolt::kMfmaCap - bolt::kMfmaPass;
         const int force = bolt::g_force_fused_kind;
-        if (mfma_ok && (force == 3 || (force != 2 && Q >= kMfmaMinQ))) {
+        if (mfma_ok && (force == 3 || (force != 2 && Q >= kMfmaMinQ && M >= 16))) {
             p.kind = 3;
             p.qb_size = 32 * (M <= 32 ? 2 : 1);
         } else {
@@ -560,7 +569,9 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
                                     : 0;
     if (p.n_chunks > 65535)
         return p;
-    p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * kSpecSpan * sizeof(uint16_t)) : 0;
+    p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * kSpecSpan * sizeof(uint16_t)) +
+                                align256((size_t)Q * sizeof(uint32_t))
+                          : 0;
     p.ok = true;
     return p;
 }
@@ -579,8 +590,9 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 // list, or of span rows every stride rows; k candidates per tile and query.
 template <int MM>
 void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k,
-                 int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
-                 const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
+                 int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *fail,
+                 uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name,
+                 hipStream_t s)
 {
     if (p.kind == 1) {   // profiled inside under its own name
         bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, ccnt, hist, gthr, tiles, s);
@@ -588,22 +600,27 @@ void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint
     }
     const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
     bolt::ProfScope prof_(prof_name, s);
-    if (p.kind == 3)
-        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1>), dim3(grid), dim3(256), 0, s, codes, N,
-                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, gthr, tiles, stride,
-                           span);
+    if (p.kind == 3 && p.spec)
+        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1, true>), dim3(grid), dim3(256), 0, s, codes,
+                           N, luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles,
+                           stride, span);
+    else if (p.kind == 3)
+        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1, false>), dim3(grid), dim3(256), 0, s,
+                           codes, N, luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr,
+                           tiles, stride, span);
     else
         hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes, N,
-                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, gthr, tiles, stride,
-                           span);
+                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles,
+                           stride, span);
 }
 
 void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
-                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
-                   const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name, hipStream_t s)
+                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *fail,
+                   uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name,
+                   hipStream_t s)
 {
 #define BOLT_SCAN_M(MMV)                                                                                         \
-    launch_scan<MMV>(p, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist, gthr, tiles, stride, span,        \
+    launch_scan<MMV>(p, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist, fail, gthr, tiles, stride, span,  \
                      prof_name, s)
     switch (M) {
     case 8: BOLT_SCAN_M(8); break;
@@ -685,6 +702,8 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     char *ws_spec = w + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
     const int64_t S = (int64_t)p.spec_nsc * kSpecSpan;
     uint16_t *sdist = p.spec ? reinterpret_cast<uint16_t *>(ws_spec) : nullptr;
+    uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * S * sizeof(uint16_t)))
+                            : nullptr;
     if (p.spec) {
         // sample distances, then each query's starting bound (and cleared histogram)
         {
@@ -693,26 +712,25 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         }
         bolt::ProfScope prof_("spec_select", s);
         hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, sdist, S, (uint32_t)p.spec_r,
-                           bolt::hist_shift(M), gthr, hist, bolt::g_spec_mode == 2 ? 1 : 0);
+                           bolt::hist_shift(M), gthr, hist, fail, bolt::g_spec_mode == 2 ? 1 : 0);
     } else {
         const int64_t n_hist = Q * bolt::kHistBins;
         hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
                            hist, n_hist);
     }
     // the tiles count their kept keys into hist as they write them
-    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, hist, gthr, tiles, kRowsPerBlock,
-                  kRowsPerBlock, scan_prof_name(p.kind), s);
+    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, hist, fail, gthr, tiles,
+                  kRowsPerBlock, kRowsPerBlock, scan_prof_name(p.kind), s);
     const uint32_t smax = 255u * (uint32_t)M;
-    const int spec = p.spec ? 1 : 0;
     {
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand, ccnt,
                            (int64_t)p.n_rb, p.n_chunks > 1 ? p.chunk : (int64_t)p.n_rb, (uint32_t)k, gthr, hist,
-                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, spec, codes, N,
+                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, fail, codes, N,
                            M, luts);
         if (p.n_chunks > 1)
             hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
-                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, spec, codes, N, M,
+                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, fail, codes, N, M,
                                luts);
     }
     return check_launch("bolt_scan_topk (fused)");

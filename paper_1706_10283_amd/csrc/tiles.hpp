@@ -50,6 +50,7 @@ struct TileJob {
     uint32_t *ccnt = nullptr;   // their counts [Q][n_rb] (packed slots), or null: padded slots
     uint32_t *hist = nullptr;   // with ccnt: per-query histograms [Q][kHistBins] of the kept keys
     int hist_shift = 0;
+    uint32_t *fail = nullptr;   // per-query flags [Q]: set when a barrier-free tile overflows
     uint32_t *gthr;         // the database's bounds [Q]
     int64_t r0, r1;         // rows of the tile
     int64_t rb;             // row-block index of the tile
@@ -316,6 +317,13 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
 // accumulator v.  A wave holds the tables of its NT query tiles (32 queries
 // each) in registers for the whole tile and takes 32 rows per pass; the
 // one-hot operand comes from a 16-entry LDS table, conflict free.
+//
+// FREE (with speculative starting bounds only): the bounds are taken as
+// they are and never tightened, so the waves need no barriers between
+// passes: appends take slots with LDS atomics, and a query whose buffer
+// would overflow (never in practice: the bound admits a few rows per tile)
+// is flagged in job.fail, writes no keys, and is recomputed exactly by the
+// final merge.
 
 constexpr int kMfmaCap = 256;    // candidate slots per query: k <= kMfmaCap - kMfmaPass
 constexpr int kMfmaPass = 128;   // rows per pass: 4 waves x 32
@@ -391,7 +399,7 @@ __device__ __forceinline__ void mfma_pass(const uint32_t (&cw)[MM / 8], const ch
     }
 }
 
-template <int MM, int NT>
+template <int MM, int NT, bool FREE>
 __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
 {
     constexpr int KS = MM / 2;       // matrix-core steps per row, two subspaces each
@@ -424,13 +432,18 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
         const int64_t n = r0 + 32 * wave + col;
         load_row<MM>(job.codes, n < r1 ? n : r1 - 1, nxt);
     }
+    // hit iff d = acc + OFF < bound (FREE: the bounds never change)
+    int thr[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        thr[t] = (int)L.bnd[32 * t + col] - OFF;
     int pass = 0;
     for (int64_t base = r0; base < r1; base += kMfmaPass, ++pass) {
         // published bounds: read at the start of every pass (unconditional,
         // before the code prefetch), folded in at the end of every
         // kRefresh-th pass
-        const bool refresh = (pass % kRefresh) == kRefresh - 1;
-        const uint32_t gpre = read_bound(&job.gthr[q0 + (tid < nq ? tid : nq - 1)]);
+        const bool refresh = !FREE && (pass % kRefresh) == kRefresh - 1;
+        const uint32_t gpre = FREE ? 0u : read_bound(&job.gthr[q0 + (tid < nq ? tid : nq - 1)]);
         uint32_t cw[NW];
 #pragma unroll
         for (int v = 0; v < NW; ++v)
@@ -440,11 +453,11 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
             load_row<MM>(job.codes, nn < r1 ? nn : r1 - 1, nxt);
         }
         __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the pass
-        // hit iff d = acc + OFF < bound
-        int thr[NT];
+        if (!FREE) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-            thr[t] = (int)L.bnd[32 * t + col] - OFF;
+            for (int t = 0; t < NT; ++t)
+                thr[t] = (int)L.bnd[32 * t + col] - OFF;
+        }
 
         i32x16 acc[NT];
         mfma_pass<MM, NT>(cw, oh, tb, acc);
@@ -478,11 +491,14 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
                     if (acc[t][v] < thr[t]) {
                         const uint32_t d = (uint32_t)(acc[t][v] + OFF);
                         const uint32_t pos = atomicAdd(&L.cnt[q], 1u);
-                        L.buf[q * CAP + pos] = local_key(d, lbase + 8 * (v >> 2) + (v & 3));
+                        if (!FREE || pos < CAP)
+                            L.buf[q * CAP + pos] = local_key(d, lbase + 8 * (v >> 2) + (v & 3));
                     }
                 }
             }
         }
+        if (FREE)
+            continue;
         __syncthreads();
         {
             const int qw = wave * PER_WAVE;
@@ -511,12 +527,22 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
         }
         __syncthreads();
     }
-    for (int q = wave; q < nq && q < QB; q += 4)
+    if (FREE)
+        __syncthreads();   // every append is done
+    for (int q = wave; q < nq && q < QB; q += 4) {
+        if (FREE && L.cnt[q] > CAP) {   // overflowed: no keys, the merge recomputes the query
+            if (lane == 0) {
+                job.fail[q0 + q] = 1u;
+                job.ccnt[(q0 + q) * job.n_rb + job.rb] = 0u;
+            }
+            continue;
+        }
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
                                      &job.gthr[q0 + q], L.bnd[q],
                                      job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr,
                                      job.hist ? job.hist + (q0 + q) * kHistBins : nullptr, job.hist_shift);
+    }
 }
 
 // Sample distances for the speculative bounds: the d of every (query, row)
