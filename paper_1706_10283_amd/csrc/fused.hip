@@ -35,6 +35,10 @@ using bolt::PruneResult;
 
 constexpr int kRowsPerBlock = 16384;      // rows per workgroup (<= 65536: 16-bit local rows)
 constexpr int64_t kMfmaMinQ = 32;         // queries from which the matrix-core tiles are used
+// 32-query tiles per matrix-core workgroup: with one, the tables take half
+// the registers of two and four waves per SIMD fit (beside 33 KB of LDS),
+// which more than pays for reading the one-hot operand once per instruction
+constexpr int kMfmaNT = 1;
 
 // Decode the tile of workgroup `w`: XCD-major placement of row blocks.
 __device__ __forceinline__ void tile_of(int w, int n_qb, int &qb, int &rb)
@@ -395,7 +399,7 @@ __global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, in
 // writes the d of its queries over rows [c * stride, c * stride + span) to
 // out[q][c * span ...].
 template <int MM, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void spec_sample_kernel(const uint8_t *__restrict__ codes,
+__global__ __launch_bounds__(256) void spec_sample_kernel(const uint8_t *__restrict__ codes,
                                                           const uint8_t *__restrict__ luts, int64_t Q, int largest,
                                                           int64_t stride, int64_t span, int64_t S,
                                                           uint16_t *__restrict__ out)
@@ -496,12 +500,11 @@ bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
         p.qb_size = (int)Q;
     } else {
         p.rpb = kRowsPerBlock;
-        // the matrix cores from M = 16 (at M = 8 the grouped kernel's lookups are cheaper)
         const bool mfma_ok = k <= bolt::kMfmaCap - bolt::kMfmaPass;
         const int force = bolt::g_force_fused_kind;
-        if (mfma_ok && (force == 3 || (force != 2 && Q >= kMfmaMinQ && M >= 16))) {
+        if (mfma_ok && (force == 3 || (force != 2 && Q >= kMfmaMinQ))) {
             p.kind = 3;
-            p.qb_size = 32 * (M <= 32 ? 2 : 1);
+            p.qb_size = 32 * kMfmaNT;
         } else {
             p.kind = 2;
             p.qb_size = 8 * (M <= 32 ? 2 : 1);
@@ -601,11 +604,11 @@ void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint
     const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
     bolt::ProfScope prof_(prof_name, s);
     if (p.kind == 3 && p.spec)
-        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1, true>), dim3(grid), dim3(256), 0, s, codes,
+        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, kMfmaNT, true>), dim3(grid), dim3(256), 0, s, codes,
                            N, luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles,
                            stride, span);
     else if (p.kind == 3)
-        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, MM <= 32 ? 2 : 1, false>), dim3(grid), dim3(256), 0, s,
+        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, kMfmaNT, false>), dim3(grid), dim3(256), 0, s,
                            codes, N, luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr,
                            tiles, stride, span);
     else
@@ -634,24 +637,24 @@ void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, c
 void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_t Q, int largest, int64_t stride,
                         int64_t S, int nsc, uint16_t *out, hipStream_t s)
 {
-    const int nt = M <= 32 ? 2 : 1;
+    const int nt = kMfmaNT;
     const dim3 grid((unsigned)((Q + 32 * nt - 1) / (32 * nt)), (unsigned)nsc);
     const int64_t span = kSpecSpan;
     switch (M) {
     case 8:
-        hipLaunchKernelGGL((spec_sample_kernel<8, 2>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+        hipLaunchKernelGGL((spec_sample_kernel<8, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
                            S, out);
         break;
     case 16:
-        hipLaunchKernelGGL((spec_sample_kernel<16, 2>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+        hipLaunchKernelGGL((spec_sample_kernel<16, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
                            S, out);
         break;
     case 32:
-        hipLaunchKernelGGL((spec_sample_kernel<32, 2>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+        hipLaunchKernelGGL((spec_sample_kernel<32, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
                            S, out);
         break;
     case 64:
-        hipLaunchKernelGGL((spec_sample_kernel<64, 1>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
+        hipLaunchKernelGGL((spec_sample_kernel<64, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
                            S, out);
         break;
     }

@@ -274,7 +274,7 @@ template <int MM, OutMode OUT>
 void launch_mfma(const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, uint16_t *out, float *outf,
                  int64_t ldo, float bias, float scale, hipStream_t s)
 {
-    constexpr int NT = MM <= 32 ? 2 : 1;
+    constexpr int NT = 1;   // one 32-query tile per wave: half the table registers, twice the waves
     const int64_t qblocks = (Q + 32 * NT - 1) / (32 * NT);
     // about 2048 workgroups, whole passes, 512..16384 rows each
     int64_t rpb = (N * qblocks + 2047) / 2048;
