@@ -399,10 +399,9 @@ __global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, in
 // writes the d of its queries over rows [c * stride, c * stride + span) to
 // out[q][c * span ...].
 template <int MM, int NT>
-__global__ __launch_bounds__(256) void spec_sample_kernel(const uint8_t *__restrict__ codes,
-                                                          const uint8_t *__restrict__ luts, int64_t Q, int largest,
-                                                          int64_t stride, int64_t span, int64_t S,
-                                                          uint16_t *__restrict__ out)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void spec_sample_kernel(
+    const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t Q, int largest, int64_t stride,
+    int64_t span, int64_t S, uint16_t *__restrict__ out)
 {
     __shared__ uint4 onehot[16];
     const int64_t q0 = (int64_t)blockIdx.x * 32 * NT;
