@@ -395,6 +395,35 @@ __global__ void init_bounds_kernel(uint32_t *gthr, int64_t Q, uint32_t *hist, in
         hist[i] = 0;
 }
 
+// Histogram of the d values of the candidate keys: one workgroup per
+// (query, 256 tile slots), one slot per thread; counted in LDS, nonzero bins
+// added to the query's global histogram.  Used when the tiles do not count
+// their keys themselves: without speculative bounds a query may receive up
+// to k keys from each of thousands of tiles, all in a few bins, and global
+// atomics on one address serialise.
+__global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restrict__ cand,
+                                                        const uint32_t *__restrict__ ccnt, int64_t n_rb, uint32_t k,
+                                                        int shift, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[bolt::kHistBins];
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+        h[i] = 0;
+    __syncthreads();
+    const int64_t q = blockIdx.x;
+    const int64_t slot = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    if (slot < n_rb) {
+        uint32_t m = ccnt[q * n_rb + slot];
+        m = m < k ? m : k;
+        const uint64_t *c = cand + (q * n_rb + slot) * k;
+        for (uint32_t j = 0; j < m; ++j)
+            atomicAdd(&h[(uint32_t)(c[j] >> 32) >> shift], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+        if (h[i])
+            atomicAdd(&hist[q * bolt::kHistBins + i], h[i]);
+}
+
 // Sample distances (speculative bounds): workgroup (query block, chunk c)
 // writes the d of its queries over rows [c * stride, c * stride + span) to
 // out[q][c * span ...].
@@ -720,9 +749,16 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
                            hist, n_hist);
     }
-    // the tiles count their kept keys into hist as they write them
-    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, hist, fail, gthr, tiles,
-                  kRowsPerBlock, kRowsPerBlock, scan_prof_name(p.kind), s);
+    // with speculative bounds (a few keys per tile and query) the tiles count
+    // their kept keys into hist as they write them; otherwise a separate
+    // kernel aggregates the counts per workgroup first
+    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, p.spec ? hist : nullptr, fail,
+                  gthr, tiles, kRowsPerBlock, kRowsPerBlock, scan_prof_name(p.kind), s);
+    if (!p.spec) {
+        bolt::ProfScope prof_("cand_hist", s);
+        hipLaunchKernelGGL(cand_hist_kernel, dim3((unsigned)Q, (unsigned)((p.n_rb + 255) / 256)), dim3(256), 0, s,
+                           cand, ccnt, (int64_t)p.n_rb, (uint32_t)k, bolt::hist_shift(M), hist);
+    }
     const uint32_t smax = 255u * (uint32_t)M;
     {
         bolt::ProfScope prof_("topk_merge", s);
