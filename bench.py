@@ -65,9 +65,9 @@ WRITE_FACTOR = 1.0
 TRAFFIC = {
     "scan_topk_mfma": {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 9899.3,
-        "write_kib": 8721.0,
-        "sources_sha256": "16b56773cdcb9f2d23b530aa4e78ba3f4e7d822656369e0c9759df9ed86c5be0",
+        "fetch_kib": 9874.1,
+        "write_kib": 18713.3,
+        "sources_sha256": "9d388ff9ab8bb1032b381a314e72d5aeec217331da9dad02fc6a0f786c31f5f1",
     },
 }
 TRAFFIC_SOURCES = {
