@@ -3,19 +3,21 @@
 // Sec. 1.2).
 //
 // Plan (host): every database is cut into tiles (query block x row block):
-// query blocks of 16 (8 for M = 64) on the grouped path, or all of a
+// query blocks of 32 on the int8 matrix cores (M = 16 or 32, 32 or more
+// queries, k <= 128), of 16 (8 for M = 64) on the grouped path, or all of a
 // database's queries on the pair-table path when they are few; row blocks
 // of `rows_per_tile` rows.  Tiles are sorted by decreasing work so that the
 // dynamic schedule hands out the longest tiles first.  The descriptors, the
 // per-database candidate lists and per-query bounds live in one caller-owned
 // workspace.
 //
-// Run (device): a fill kernel resets the tile counter and the bounds; the
-// persistent kernel (a few workgroups per CU) pulls tiles from the counter
-// until it passes the tile count, so every wave exits; a merge kernel then
-// turns each query's candidate lists into its sorted top k.  The three
-// launches depend only on the plan, so they can be captured once in a HIP
-// graph and replayed with new query tables in place.  Results are
+// Run (device): a fill kernel resets the tile counters and the bounds; a
+// persistent kernel (a few workgroups per CU) pulls the matrix-core tiles
+// from one counter and a second one the other tiles from another, each
+// until it passes its tile count, so every wave exits; a merge kernel then
+// turns each query's candidate lists into its sorted top k.  The launches
+// depend only on the plan, so they can be captured once in a HIP graph and
+// replayed with new query tables in place.  Results are
 // bit-identical to bolt_scan_topk on each database alone: the sums are exact
 // integers and the keys totally ordered.
 #include <algorithm>
@@ -45,7 +47,7 @@ struct DevDb {
 
 struct DevTile {
     int32_t db;
-    int32_t kind;   // 1 pair tables (few queries), 2 grouped
+    int32_t kind;   // 1 pair tables (few queries), 2 grouped, 3 matrix cores
     int32_t q0;
     int32_t nq;
     int64_t rb;
@@ -56,20 +58,20 @@ struct DevQuery {
     int32_t q;
 };
 
-// Largest LDS footprint of any tile: GroupedLds<32, 2> or a few-query tile
-// of at most this many bytes.
+// Largest LDS footprint of any tile: GroupedLds<32, 2>, MfmaLds<1> or a
+// few-query tile of at most this many bytes.
 constexpr size_t kBatchLds = 49664;
 
 __global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i == 0)
-        *counter = 0;
+    if (i < 2)
+        counter[i] = 0;   // matrix-core tiles, other tiles
     if (i < n)
         gthr[i] = 0xFFFFu;
 }
 
-template <int MM>
+template <int MM, bool MF>
 __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_tile, char *lds)
 {
     bolt::TileJob job;
@@ -85,7 +87,9 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     job.nq = t.nq;
     job.k = (uint32_t)db.k;
     job.largest = db.largest;
-    if (t.kind == 1) {
+    if (MF) {
+        bolt::mfma_tile<MM, 1, false>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
+    } else if (t.kind == 1) {
         bolt::few_tile<MM, false>(job, lds);
     } else {
         constexpr int NG = MM <= 32 ? 2 : 1;
@@ -93,6 +97,10 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     }
 }
 
+// MF: the matrix-core tiles (a launch of their own, so that the other
+// tiles keep their own register budget), else the pair-table and grouped
+// tiles.
+template <bool MF>
 __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict__ dbs,
                                                          const DevTile *__restrict__ tiles,
                                                          int32_t n_tiles, int64_t rows_per_tile,
@@ -102,7 +110,8 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict
     static_assert(sizeof(bolt::GroupedLds<64, 1>) <= kBatchLds, "grouped tile LDS");
     static_assert(sizeof(bolt::GroupedLds<16, 2>) <= kBatchLds, "grouped tile LDS");
     static_assert(sizeof(bolt::GroupedLds<8, 2>) <= kBatchLds, "grouped tile LDS");
-    __shared__ __attribute__((aligned(16))) char lds[kBatchLds];
+    static_assert(sizeof(bolt::MfmaLds<1>) <= kBatchLds, "matrix-core tile LDS");
+    __shared__ __attribute__((aligned(16))) char lds[MF ? sizeof(bolt::MfmaLds<1>) : kBatchLds];
     __shared__ int32_t sh_tile;
     for (;;) {
         if (threadIdx.x == 0)
@@ -114,11 +123,18 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict
             break;
         const DevTile t = tiles[ti];
         const DevDb db = dbs[t.db];
+        if (MF) {   // M = 16 or 32 only (see tile_kind)
+            if (db.M == 16)
+                run_tile<16, true>(db, t, rows_per_tile, lds);
+            else
+                run_tile<32, true>(db, t, rows_per_tile, lds);
+            continue;
+        }
         switch (db.M) {
-        case 8: run_tile<8>(db, t, rows_per_tile, lds); break;
-        case 16: run_tile<16>(db, t, rows_per_tile, lds); break;
-        case 32: run_tile<32>(db, t, rows_per_tile, lds); break;
-        default: run_tile<64>(db, t, rows_per_tile, lds); break;
+        case 8: run_tile<8, false>(db, t, rows_per_tile, lds); break;
+        case 16: run_tile<16, false>(db, t, rows_per_tile, lds); break;
+        case 32: run_tile<32, false>(db, t, rows_per_tile, lds); break;
+        default: run_tile<64, false>(db, t, rows_per_tile, lds); break;
         }
     }
 }
@@ -158,6 +174,19 @@ int resolve(const bolt_batch_tuning *tuning, int32_t &rows, int32_t &few_max, in
 // Pair-table tiles need their LDS to fit the persistent kernel's buffer.
 bool few_fits(int M, int nq) { return bolt::few_tile_lds_bytes(M, nq) <= kBatchLds; }
 
+// Tile kind of a database: 1 pair tables (few queries), 3 matrix cores
+// (M = 16 or 32, 32 or more queries, k within the tile's candidate buffer;
+// at M = 64 the tables alone would take 128 registers of every tile of the
+// persistent kernel), else 2 grouped.
+int tile_kind(const bolt_batch_db &d, int few_max)
+{
+    if (d.Q <= few_max && few_fits(d.M, d.Q))
+        return 1;
+    if ((d.M == 16 || d.M == 32) && d.Q >= 32 && d.k <= bolt::kMfmaCap - bolt::kMfmaPass)
+        return 3;
+    return 2;
+}
+
 int validate(const bolt_batch_db *dbs, int32_t n_db)
 {
     if (n_db < 0 || (n_db > 0 && !dbs))
@@ -190,9 +219,9 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
         if (d.Q == 0)
             continue;
         const int64_t n_rb = (d.N + rows - 1) / rows;   // 0 for an empty database: padding only
-        const bool few = d.Q <= few_max && few_fits(d.M, d.Q);
-        const int qb = d.M <= 32 ? 16 : 8;
-        const int64_t n_qb = few ? 1 : (d.Q + qb - 1) / qb;
+        const int kind = tile_kind(d, few_max);
+        const int qb = kind == 3 ? 32 : (d.M <= 32 ? 16 : 8);
+        const int64_t n_qb = kind == 1 ? 1 : (d.Q + qb - 1) / qb;
         tiles += n_rb * n_qb;
         queries += d.Q;
         cand += align256((size_t)d.Q * n_rb * d.k * sizeof(uint64_t));
@@ -221,6 +250,7 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
 struct bolt_batch_plan {
     char *ws = nullptr;
     int64_t n_tiles = 0, n_queries = 0;
+    int64_t n_mfma = 0;   // the first n_mfma tiles are matrix-core tiles
     int32_t rows_per_tile = 0, grid = 0;
     std::vector<char> host;   // staged descriptors (kept until the plan is destroyed)
     DevDb *dbs = nullptr;
@@ -299,30 +329,39 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
         cand_off += align256((size_t)d.Q * o.n_rb * d.k * sizeof(uint64_t));
         o.gthr = p->gthr + qbase;
         qbase += d.Q;
-        const bool few = d.Q <= few_max && few_fits(d.M, d.Q);
-        const int qb = few ? d.Q : (d.M <= 32 ? 16 : 8);
+        const int kind = tile_kind(d, few_max);
+        const int qb = kind == 1 ? d.Q : (kind == 3 ? 32 : (d.M <= 32 ? 16 : 8));
         for (int64_t rb = 0; rb < o.n_rb; ++rb) {
             const int64_t r = std::min<int64_t>(rows, d.N - rb * rows);
             for (int q0 = 0; q0 < d.Q; q0 += qb) {
                 DevTile t;
                 t.db = i;
-                t.kind = few ? 1 : 2;
+                t.kind = kind;
                 t.q0 = q0;
                 t.nq = std::min(qb, d.Q - q0);
                 t.rb = rb;
                 ht.push_back(t);
-                // grouped tiles pay for a full query block whatever nq is
-                cost.push_back((double)r * d.M * (few ? t.nq : qb));
+                // grouped and matrix-core tiles pay for a full query block
+                // whatever nq is; a matrix-core lookup costs about 1/4 of a
+                // grouped one
+                const double w = kind == 3 ? 0.25 : 1.0;
+                cost.push_back(w * (double)r * d.M * (kind == 1 ? t.nq : qb));
             }
         }
         for (int q = 0; q < d.Q; ++q)
             hq.push_back({i, q});
     }
-    // longest tiles first
+    // matrix-core tiles first (their own launch), each group longest first
     std::vector<int64_t> order(ht.size());
     for (size_t e = 0; e < order.size(); ++e)
         order[e] = (int64_t)e;
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        const bool ma = ht[a].kind == 3, mb = ht[b].kind == 3;
+        return ma != mb ? ma : cost[a] > cost[b];
+    });
+    p->n_mfma = 0;
+    for (const DevTile &t : ht)
+        p->n_mfma += t.kind == 3;
     const size_t nb_db = sizeof(DevDb) * hd.size(), nb_t = sizeof(DevTile) * ht.size(),
                  nb_q = sizeof(DevQuery) * hq.size();
     p->host.resize(nb_db + nb_t + nb_q + 1);
@@ -357,8 +396,13 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
                        p->gthr, nz);
     {
         bolt::ProfScope prof_("batch_scan", s);
-        hipLaunchKernelGGL(batch_scan_kernel, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs, p->tiles,
-                           (int32_t)p->n_tiles, (int64_t)p->rows_per_tile, p->counter);
+        if (p->n_mfma > 0)
+            hipLaunchKernelGGL(batch_scan_kernel<true>, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs, p->tiles,
+                               (int32_t)p->n_mfma, (int64_t)p->rows_per_tile, p->counter);
+        if (p->n_tiles > p->n_mfma)
+            hipLaunchKernelGGL(batch_scan_kernel<false>, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs,
+                               p->tiles + p->n_mfma, (int32_t)(p->n_tiles - p->n_mfma),
+                               (int64_t)p->rows_per_tile, p->counter + 1);
     }
     {
         bolt::ProfScope prof_("batch_merge", s);
