@@ -43,6 +43,20 @@ struct DevDb {
     int32_t Q;
     int32_t k;
     int32_t largest;
+    // speculative starting bounds (matrix-core databases from kSpecMinRows rows)
+    uint16_t *sdist;   // sample distances [Q][S], or null: no speculation
+    int64_t S;         // sample rows: S / kSpecSpan chunks at a stride of `stride` rows
+    int64_t stride;
+    int32_t spec_r;    // rank of the sample distance taken as the bound
+    int32_t pad;
+};
+
+// One sample work item: queries [q0, q0 + 32) of a database over one chunk.
+struct DevSample {
+    int32_t db;
+    int32_t q0;
+    int32_t chunk;
+    int32_t pad;
 };
 
 struct DevTile {
@@ -139,23 +153,96 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict
     }
 }
 
+// Sample distances of the speculative bounds (as in the one-database path):
+// one workgroup per work item.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_sample_kernel(
+    const DevDb *__restrict__ dbs, const DevSample *__restrict__ items)
+{
+    __shared__ uint4 onehot[16];
+    const DevSample it = items[blockIdx.x];
+    const DevDb db = dbs[it.db];
+    const int nq = (db.Q - it.q0) < 32 ? (db.Q - it.q0) : 32;
+    const int64_t r0 = (int64_t)it.chunk * db.stride, s0 = (int64_t)it.chunk * bolt::kSpecSpan;
+    if (db.M == 16)
+        bolt::mfma_sample_tile<16, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, bolt::kSpecSpan, db.sdist,
+                                      db.S, s0, onehot);
+    else
+        bolt::mfma_sample_tile<32, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, bolt::kSpecSpan, db.sdist,
+                                      db.S, s0, onehot);
+}
+
+// Starting bound of each query of a speculative database: the upper edge of
+// the histogram bin holding the r-th smallest sample distance (0 when a test
+// forces the recomputation); other queries keep the open bound.
+__global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restrict__ dbs,
+                                                           const DevQuery *__restrict__ queries, int force_fail)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
+    const DevQuery qq = queries[blockIdx.x];
+    const DevDb db = dbs[qq.db];
+    if (!db.sdist)
+        return;
+    const int shift = bolt::hist_shift(db.M);
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+        h[i] = 0;
+    __syncthreads();
+    const uint4 *d = reinterpret_cast<const uint4 *>(db.sdist + (int64_t)qq.q * db.S);   // 8 distances per load
+    for (int64_t i = threadIdx.x; i < db.S / 8; i += 256) {
+        const uint4 v = d[i];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            atomicAdd(&h[(w[j] & 0xFFFFu) >> shift], 1u);
+            atomicAdd(&h[(w[j] >> 16) >> shift], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t b = bolt::hist_bound(h, (uint32_t)db.spec_r, shift, 0xFFFFu);
+        if (threadIdx.x == 0)
+            db.gthr[qq.q] = force_fail ? 0u : b;
+    }
+}
+
+// Top k of one query from its candidate lists; a query of a speculative
+// database with fewer than k candidates is recomputed exactly.
 __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restrict__ dbs,
                                                           const DevQuery *__restrict__ queries)
 {
+    __shared__ bolt::MergeLds L;
     const DevQuery qq = queries[blockIdx.x];
     const DevDb db = dbs[qq.db];
     const int64_t per_query = db.n_rb * db.k;
-    bolt::merge_keys(db.cand + (int64_t)qq.q * per_query, 0, per_query, (uint32_t)db.k, db.gthr[qq.q],
-                     nullptr, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
+    const uint32_t k = (uint32_t)db.k;
+    const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k, db.gthr[qq.q]);
+    if (db.sdist && n < k) {
+        bolt::redo_query(L, db.codes, db.N, db.M, db.luts, qq.q, k, db.largest, db.vals, db.idx);
+        return;
+    }
+    bolt::merge_emit(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
                      db.idx + (int64_t)qq.q * db.k);
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    size_t dbs_off, tiles_off, queries_off, gthr_off, counter_off, cand_off, total;
-    int64_t n_tiles, n_queries;
+    size_t dbs_off, tiles_off, queries_off, gthr_off, counter_off, samples_off, cand_off, total;
+    int64_t n_tiles, n_queries, n_samples;
 };
+
+// Speculative bounds of a matrix-core database (as the one-database path
+// decides them): the number of sample chunks, or 0 for none.
+int64_t spec_chunks(const bolt_batch_db &d, int kind)
+{
+    const int mode = bolt::g_spec_mode;
+    if (kind != 3 || mode == 0 || d.N < (mode > 0 ? bolt::kSpecMinRowsForced : bolt::kSpecMinRows))
+        return 0;
+    int64_t nsc = d.N / 32 / bolt::kSpecSpan;
+    nsc = nsc < 16 ? 16 : (nsc > 256 ? 256 : nsc);
+    while (nsc > 16 && (int64_t)d.Q * nsc * bolt::kSpecSpan > bolt::kSpecMaxDists)
+        nsc /= 2;
+    return (int64_t)d.Q * nsc * bolt::kSpecSpan > bolt::kSpecMaxDists ? 0 : nsc;
+}
 
 int resolve(const bolt_batch_tuning *tuning, int32_t &rows, int32_t &few_max, int32_t &per_cu)
 {
@@ -212,7 +299,7 @@ int validate(const bolt_batch_db *dbs, int32_t n_db)
 Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t few_max)
 {
     Layout L{};
-    int64_t tiles = 0, queries = 0;
+    int64_t tiles = 0, queries = 0, samples = 0;
     size_t cand = 0;
     for (int i = 0; i < n_db; ++i) {
         const bolt_batch_db &d = dbs[i];
@@ -225,9 +312,15 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
         tiles += n_rb * n_qb;
         queries += d.Q;
         cand += align256((size_t)d.Q * n_rb * d.k * sizeof(uint64_t));
+        const int64_t nsc = spec_chunks(d, kind);
+        if (nsc) {
+            samples += (d.Q + 31) / 32 * nsc;
+            cand += align256((size_t)d.Q * nsc * bolt::kSpecSpan * sizeof(uint16_t));
+        }
     }
     L.n_tiles = tiles;
     L.n_queries = queries;
+    L.n_samples = samples;
     size_t off = 0;
     L.dbs_off = off;
     off += align256(sizeof(DevDb) * (size_t)(n_db > 0 ? n_db : 1));
@@ -239,6 +332,8 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
     off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
     L.counter_off = off;
     off += 256;
+    L.samples_off = off;
+    off += align256(sizeof(DevSample) * (size_t)(samples > 0 ? samples : 1));
     L.cand_off = off;
     off += cand;
     L.total = off;
@@ -251,6 +346,7 @@ struct bolt_batch_plan {
     char *ws = nullptr;
     int64_t n_tiles = 0, n_queries = 0;
     int64_t n_mfma = 0;   // the first n_mfma tiles are matrix-core tiles
+    int64_t n_samples = 0;
     int32_t rows_per_tile = 0, grid = 0;
     std::vector<char> host;   // staged descriptors (kept until the plan is destroyed)
     DevDb *dbs = nullptr;
@@ -258,6 +354,7 @@ struct bolt_batch_plan {
     DevQuery *queries = nullptr;
     uint32_t *gthr = nullptr;
     uint32_t *counter = nullptr;
+    DevSample *samples = nullptr;
 };
 
 extern "C" size_t bolt_batch_ws_bytes(const bolt_batch_db *dbs, int32_t n_db, const bolt_batch_tuning *tuning)
@@ -299,11 +396,15 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
     p->queries = reinterpret_cast<DevQuery *>(p->ws + L.queries_off);
     p->gthr = reinterpret_cast<uint32_t *>(p->ws + L.gthr_off);
     p->counter = reinterpret_cast<uint32_t *>(p->ws + L.counter_off);
+    p->samples = reinterpret_cast<DevSample *>(p->ws + L.samples_off);
+    p->n_samples = L.n_samples;
 
     std::vector<DevDb> hd(n_db);
     std::vector<DevTile> ht;
     std::vector<double> cost;
     std::vector<DevQuery> hq;
+    std::vector<DevSample> hs;
+    hs.reserve(L.n_samples);
     ht.reserve(L.n_tiles);
     cost.reserve(L.n_tiles);
     hq.reserve(L.n_queries);
@@ -330,6 +431,17 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
         o.gthr = p->gthr + qbase;
         qbase += d.Q;
         const int kind = tile_kind(d, few_max);
+        const int64_t nsc = spec_chunks(d, kind);
+        if (nsc) {
+            o.sdist = reinterpret_cast<uint16_t *>(p->ws + cand_off);
+            cand_off += align256((size_t)d.Q * nsc * bolt::kSpecSpan * sizeof(uint16_t));
+            o.S = nsc * bolt::kSpecSpan;
+            o.stride = d.N / nsc;
+            o.spec_r = bolt::spec_rank(d.k, (double)o.S / (double)d.N);
+            for (int q0 = 0; q0 < d.Q; q0 += 32)
+                for (int64_t c = 0; c < nsc; ++c)
+                    hs.push_back({i, q0, (int32_t)c, 0});
+        }
         const int qb = kind == 1 ? d.Q : (kind == 3 ? 32 : (d.M <= 32 ? 16 : 8));
         for (int64_t rb = 0; rb < o.n_rb; ++rb) {
             const int64_t r = std::min<int64_t>(rows, d.N - rb * rows);
@@ -363,19 +475,24 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
     for (const DevTile &t : ht)
         p->n_mfma += t.kind == 3;
     const size_t nb_db = sizeof(DevDb) * hd.size(), nb_t = sizeof(DevTile) * ht.size(),
-                 nb_q = sizeof(DevQuery) * hq.size();
-    p->host.resize(nb_db + nb_t + nb_q + 1);
+                 nb_q = sizeof(DevQuery) * hq.size(), nb_s = sizeof(DevSample) * hs.size();
+    p->host.resize(nb_db + nb_t + nb_q + nb_s + 1);
     std::memcpy(p->host.data(), hd.data(), nb_db);
     DevTile *st = reinterpret_cast<DevTile *>(p->host.data() + nb_db);
     for (size_t e = 0; e < order.size(); ++e)
         st[e] = ht[order[e]];
     std::memcpy(p->host.data() + nb_db + nb_t, hq.data(), nb_q);
+    if (nb_s)
+        std::memcpy(p->host.data() + nb_db + nb_t + nb_q, hs.data(), nb_s);
     hipStream_t s = as_stream(stream);
     hipError_t e1 = hipMemcpyAsync(p->dbs, p->host.data(), nb_db, hipMemcpyHostToDevice, s);
     hipError_t e2 = hipMemcpyAsync(p->tiles, p->host.data() + nb_db, nb_t, hipMemcpyHostToDevice, s);
     hipError_t e3 = hipMemcpyAsync(p->queries, p->host.data() + nb_db + nb_t, nb_q, hipMemcpyHostToDevice, s);
+    hipError_t e5 = nb_s ? hipMemcpyAsync(p->samples, p->host.data() + nb_db + nb_t + nb_q, nb_s,
+                                          hipMemcpyHostToDevice, s)
+                         : hipSuccess;
     hipError_t e4 = hipStreamSynchronize(s);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
         delete p;
         return fail(BOLT_ERR_DEVICE, "uploading the batch plan failed");
     }
@@ -394,6 +511,12 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
     const int64_t nz = p->n_queries;
     hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, p->counter,
                        p->gthr, nz);
+    if (p->n_samples > 0) {   // speculative starting bounds
+        bolt::ProfScope prof_("batch_spec", s);
+        hipLaunchKernelGGL(batch_sample_kernel, dim3((unsigned)p->n_samples), dim3(256), 0, s, p->dbs, p->samples);
+        hipLaunchKernelGGL(batch_select_kernel, dim3((unsigned)p->n_queries), dim3(256), 0, s, p->dbs, p->queries,
+                           bolt::g_spec_mode == 2 ? 1 : 0);
+    }
     {
         bolt::ProfScope prof_("batch_scan", s);
         if (p->n_mfma > 0)

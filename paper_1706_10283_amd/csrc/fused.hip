@@ -32,6 +32,7 @@ namespace {
 using bolt::code_at;
 using bolt::load_row;
 using bolt::PruneResult;
+using bolt::hist_bound;
 
 constexpr int kRowsPerBlock = 16384;      // rows per workgroup (<= 65536: 16-bit local rows)
 constexpr int64_t kMfmaMinQ = 32;         // queries from which the matrix-core tiles are used
@@ -117,107 +118,6 @@ __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
 
 // ------------------------------------------------------------------ merge
 
-// The first histogram bin at which the running count of candidate keys
-// reaches k; its upper edge bounds the query's k-th smallest d (that many
-// distinct rows have d at or below it).  One wave; returns `bound` lowered to
-// that edge (unchanged if fewer than k keys were counted).
-__device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int shift, uint32_t bound)
-{
-    constexpr int PER = bolt::kHistBins / 64;
-    const int lane = threadIdx.x & 63;
-    const uint4 *h = reinterpret_cast<const uint4 *>(hq + lane * PER);
-    uint32_t b[PER];
-#pragma unroll
-    for (int v = 0; v < PER / 4; ++v) {
-        const uint4 t = h[v];
-        b[4 * v + 0] = t.x;
-        b[4 * v + 1] = t.y;
-        b[4 * v + 2] = t.z;
-        b[4 * v + 3] = t.w;
-    }
-    uint32_t own = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-        own += b[i];
-    uint32_t inc = own;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(inc, o);
-        if (lane >= o)
-            inc += t;
-    }
-    const uint64_t hit = __ballot(inc >= k);
-    if (hit == 0)
-        return bound;
-    const int first = (int)__builtin_ctzll(hit);
-    int bin = lane * PER + PER - 1;
-    uint32_t run = inc - own;
-    for (int i = 0; i < PER; ++i) {
-        run += b[i];
-        if (run >= k) {
-            bin = lane * PER + i;
-            break;
-        }
-    }
-    const uint32_t edge = (((uint32_t)__shfl(bin, first) + 1u) << shift) - 1u;
-    return edge < bound ? edge : bound;
-}
-
-// Exact top-k of one query whose speculative bound failed (fewer than k
-// rows passed it), by the merging workgroup itself: it scans every row with
-// the query's table in LDS, appends keys (d << 32 | row) below the running
-// bound and prunes by the merge's scheme, then writes the sorted result.
-__device__ void redo_query(bolt::MergeLds &L, const uint8_t *__restrict__ codes, int64_t N, int M,
-                           const uint8_t *__restrict__ luts, int64_t q, uint32_t k, int largest,
-                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
-{
-    __shared__ uint16_t tab[64 * 16];   // d contribution of (subspace, code)
-    const int tid = threadIdx.x;
-    __syncthreads();   // the caller is done with L
-    for (int e = tid; e < M * 16; e += 256) {
-        const uint32_t v = luts[q * M * 16 + e];
-        tab[e] = (uint16_t)(largest ? 255u - v : v);
-    }
-    if (tid == 0) {
-        L.mcnt = 0;
-        L.mbound = ~0ull;
-    }
-    __syncthreads();
-    const int half = M / 2;
-    for (int64_t c0 = 0; c0 < N; c0 += 256 * bolt::kMergeE) {
-        const uint64_t bnd = L.mbound;
-        for (int e = 0; e < bolt::kMergeE; ++e) {
-            const int64_t row = c0 + tid + 256 * e;
-            if (row < N) {
-                const uint8_t *pr = codes + row * half;
-                uint32_t d = 0;
-                for (int b = 0; b < half; ++b) {
-                    const uint32_t byte = pr[b];
-                    d += tab[(2 * b) * 16 + (byte & 15u)] + tab[(2 * b + 1) * 16 + (byte >> 4)];
-                }
-                const uint64_t key = ((uint64_t)d << 32) | (uint64_t)row;
-                if (key < bnd) {
-                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
-                    L.mb[pos] = key;
-                }
-            }
-        }
-        __syncthreads();
-        if (tid < 64 && L.mcnt > bolt::kMergeCap - 256 * bolt::kMergeE) {
-            const uint64_t kth = bolt::prune_u64<bolt::kMergeCap>(L.mb, L.mcnt, k);
-            if (tid == 0) {
-                L.mcnt = k;
-                L.mbound = kth + 1;
-            }
-        }
-        __syncthreads();
-    }
-    const uint32_t n = L.mcnt;
-    if (tid < 64 && n > k)
-        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
-    __syncthreads();
-    bolt::merge_emit(L, n > k ? k : n, k, largest, 255u * (uint32_t)M, vals + q * k, idx + q * k);
-}
 
 // Appends to L every key below L.mbound from slots [s_lo, s_hi) (slot s:
 // cnt[s] keys at src + s * k), pruning to the k smallest whenever the
@@ -330,7 +230,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
     __syncthreads();
     if (gridDim.y == 1) {
         if (fail && (n < k || fail[q]))
-            redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
+            bolt::redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
         else
             bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
         return;
@@ -366,7 +266,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     const uint32_t n = merge_walk(L, pre, src + q * (int64_t)n_chunks * k, src_cnt + q * (int64_t)n_chunks, 0,
                                   n_chunks, k);
     if (fail && (n < k || fail[q])) {
-        redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
+        bolt::redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
         return;
     }
     if (tid < 64 && n > k)
@@ -497,10 +397,10 @@ constexpr int ng_for()
 // rounded up to its bin's edge.  The bound only selects candidates: the
 // final merge flags any query with fewer than k candidates and
 // redo_query recomputes it exactly, so results never depend on it.
-constexpr int64_t kSpecSpan = 1024;            // rows per sample chunk
-constexpr int64_t kSpecMinRows = 1 << 19;      // smaller databases scan without it
-constexpr int64_t kSpecMinRowsForced = 1 << 17;
-constexpr int64_t kSpecMaxDists = 1 << 26;     // sample distances held at once (128 MB)
+using bolt::kSpecSpan;
+using bolt::kSpecMinRows;
+using bolt::kSpecMinRowsForced;
+using bolt::kSpecMaxDists;
 
 struct FusedPlan {
     bool ok = false;
@@ -542,25 +442,6 @@ bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
     return true;
 }
 
-// Smallest r with P(binomial(k, p) >= r) <= 1e-7, at most k.
-static int spec_rank(int k, double pr)
-{
-    std::vector<double> pmf(k + 1);
-    double tail = 0.0;
-    // pmf by the recurrence from j = 0 (pr < 1/16 here, so (1 - pr)^k > 0)
-    pmf[0] = std::pow(1.0 - pr, k);
-    for (int j = 1; j <= k; ++j)
-        pmf[j] = pmf[j - 1] * (double)(k - j + 1) / (double)j * pr / (1.0 - pr);
-    int r = k;
-    for (int j = k; j >= 1; --j) {
-        tail += pmf[j];
-        if (tail > 1e-7)
-            break;
-        r = j;
-    }
-    return r;
-}
-
 // Speculation for a whole-database plan of kind 2 or 3: about N / 32 sample
 // rows (16 to 256 chunks), fewer if Q of them would not fit kSpecMaxDists.
 static void plan_spec(FusedPlan &p, int64_t N, int64_t Q, int k)
@@ -574,7 +455,7 @@ static void plan_spec(FusedPlan &p, int64_t N, int64_t Q, int k)
         nsc /= 2;
     if (Q * nsc * kSpecSpan > kSpecMaxDists)
         return;
-    const int r = spec_rank(k, (double)(nsc * kSpecSpan) / (double)N);
+    const int r = bolt::spec_rank(k, (double)(nsc * kSpecSpan) / (double)N);
     p.spec = true;
     p.spec_r = r;
     p.spec_nsc = (int)nsc;
@@ -696,6 +577,25 @@ const char *scan_prof_name(int kind)
 }  // namespace
 
 namespace bolt {
+
+// Smallest r with P(binomial(k, p) >= r) <= 1e-7, at most k.
+int spec_rank(int k, double pr)
+{
+    std::vector<double> pmf(k + 1);
+    double tail = 0.0;
+    // pmf by the recurrence from j = 0 (pr < 1/16 here, so (1 - pr)^k > 0)
+    pmf[0] = std::pow(1.0 - pr, k);
+    for (int j = 1; j <= k; ++j)
+        pmf[j] = pmf[j - 1] * (double)(k - j + 1) / (double)j * pr / (1.0 - pr);
+    int r = k;
+    for (int j = k; j >= 1; --j) {
+        tail += pmf[j];
+        if (tail > 1e-7)
+            break;
+        r = j;
+    }
+    return r;
+}
 
 bool fused_supported(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 {

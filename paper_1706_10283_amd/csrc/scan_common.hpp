@@ -47,6 +47,16 @@ extern int g_force_unfused_topk;
 extern int g_force_fused_kind;   // -1 automatic, 2 grouped, 3 matrix cores
 extern int g_spec_mode;           // speculative bounds: -1 automatic, 0 off, 1 on, 2 on and failing
 
+// Speculative starting bounds (fused.hip): sample chunks of kSpecSpan rows,
+// used from kSpecMinRows rows (kSpecMinRowsForced under test mode 1), at
+// most kSpecMaxDists sample distances held at once; spec_rank gives the
+// smallest rank r with P(binomial(k, p) >= r) <= 1e-7 (at most k).
+constexpr int64_t kSpecSpan = 1024;
+constexpr int64_t kSpecMinRows = 1 << 19;
+constexpr int64_t kSpecMinRowsForced = 1 << 17;
+constexpr int64_t kSpecMaxDists = 1 << 26;
+int spec_rank(int k, double pr);
+
 // Top-k of the rows of a uint16 matrix (arguments already validated).
 int topk_u16(const uint16_t *d, int64_t Q, int64_t N, int64_t ldd, int k, int largest,
              uint16_t *vals, int32_t *idx, hipStream_t s);

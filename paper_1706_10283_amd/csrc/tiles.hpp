@@ -972,4 +972,106 @@ __device__ void merge_keys(const uint64_t *__restrict__ src, int64_t lo, int64_t
     merge_emit(L, n, k, largest, smax, vals, idx);
 }
 
+// The first histogram bin at which the running count of candidate keys
+// reaches k; its upper edge bounds the query's k-th smallest d (that many
+// distinct rows have d at or below it).  One wave; returns `bound` lowered to
+// that edge (unchanged if fewer than k keys were counted).
+__device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int shift, uint32_t bound)
+{
+    constexpr int PER = kHistBins / 64;
+    const int lane = threadIdx.x & 63;
+    const uint4 *h = reinterpret_cast<const uint4 *>(hq + lane * PER);
+    uint32_t b[PER];
+#pragma unroll
+    for (int v = 0; v < PER / 4; ++v) {
+        const uint4 t = h[v];
+        b[4 * v + 0] = t.x;
+        b[4 * v + 1] = t.y;
+        b[4 * v + 2] = t.z;
+        b[4 * v + 3] = t.w;
+    }
+    uint32_t own = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        own += b[i];
+    uint32_t inc = own;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o)
+            inc += t;
+    }
+    const uint64_t hit = __ballot(inc >= k);
+    if (hit == 0)
+        return bound;
+    const int first = (int)__builtin_ctzll(hit);
+    int bin = lane * PER + PER - 1;
+    uint32_t run = inc - own;
+    for (int i = 0; i < PER; ++i) {
+        run += b[i];
+        if (run >= k) {
+            bin = lane * PER + i;
+            break;
+        }
+    }
+    const uint32_t edge = (((uint32_t)__shfl(bin, first) + 1u) << shift) - 1u;
+    return edge < bound ? edge : bound;
+}
+
+// Exact top-k of one query whose speculative bound failed (fewer than k
+// rows passed it), by the merging workgroup itself: it scans every row with
+// the query's table in LDS, appends keys (d << 32 | row) below the running
+// bound and prunes by the merge's scheme, then writes the sorted result.
+__device__ void redo_query(MergeLds &L, const uint8_t *__restrict__ codes, int64_t N, int M,
+                           const uint8_t *__restrict__ luts, int64_t q, uint32_t k, int largest,
+                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    __shared__ uint16_t tab[64 * 16];   // d contribution of (subspace, code)
+    const int tid = threadIdx.x;
+    __syncthreads();   // the caller is done with L
+    for (int e = tid; e < M * 16; e += 256) {
+        const uint32_t v = luts[q * M * 16 + e];
+        tab[e] = (uint16_t)(largest ? 255u - v : v);
+    }
+    if (tid == 0) {
+        L.mcnt = 0;
+        L.mbound = ~0ull;
+    }
+    __syncthreads();
+    const int half = M / 2;
+    for (int64_t c0 = 0; c0 < N; c0 += 256 * kMergeE) {
+        const uint64_t bnd = L.mbound;
+        for (int e = 0; e < kMergeE; ++e) {
+            const int64_t row = c0 + tid + 256 * e;
+            if (row < N) {
+                const uint8_t *pr = codes + row * half;
+                uint32_t d = 0;
+                for (int b = 0; b < half; ++b) {
+                    const uint32_t byte = pr[b];
+                    d += tab[(2 * b) * 16 + (byte & 15u)] + tab[(2 * b + 1) * 16 + (byte >> 4)];
+                }
+                const uint64_t key = ((uint64_t)d << 32) | (uint64_t)row;
+                if (key < bnd) {
+                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                    L.mb[pos] = key;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < 64 && L.mcnt > kMergeCap - 256 * kMergeE) {
+            const uint64_t kth = prune_u64<kMergeCap>(L.mb, L.mcnt, k);
+            if (tid == 0) {
+                L.mcnt = k;
+                L.mbound = kth + 1;
+            }
+        }
+        __syncthreads();
+    }
+    const uint32_t n = L.mcnt;
+    if (tid < 64 && n > k)
+        prune_u64<kMergeCap>(L.mb, n, k);
+    __syncthreads();
+    merge_emit(L, n > k ? k : n, k, largest, 255u * (uint32_t)M, vals + q * k, idx + q * k);
+}
+
 }  // namespace bolt

@@ -102,3 +102,37 @@ def test_batched_rejects_bad_input(bolt):
     luts = torch.zeros((2, 32, 16), dtype=torch.uint8, device=DEV)
     with pytest.raises(bolt.BoltError):
         bolt.BatchPlan([{"codes": codes, "luts": luts, "k": 300}])
+
+
+# databases large enough for speculative bounds under test mode 1 (2^17 rows),
+# with matrix-core tiles (M = 16 or 32, 32 or more queries), beside others
+SPEC_DBS = [
+    (32, 140000, 40, 100, "l2", "rand"), (16, 150000, 70, 64, "dot", "coarse"), (32, 131072, 33, 1, "dot", "const"),
+    (64, 140000, 40, 100, "l2", "rand"), (16, 20000, 50, 10, "l2", "rand"), (32, 160000, 5, 100, "dot", "rand"),
+]
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batched_speculation(bolt, mode):
+    """Sampled starting bounds (mode 1), and all of them failing (mode 2: every
+    speculative query recomputed exactly): results equal the oracle's."""
+    print("[case] batched speculation mode", mode, flush=True)
+    host, dev = [], []
+    for i, (M, N, Q, k, metric, kind) in enumerate(SPEC_DBS):
+        codes, luts = _make(700 + 11 * i, M, N, Q, kind)
+        host.append((codes, luts, k, metric))
+        dev.append({"codes": torch.from_numpy(codes).to(DEV), "luts": torch.from_numpy(luts).to(DEV),
+                    "k": k, "metric": metric})
+    bolt.debug_speculation(mode)
+    try:
+        plan = bolt.BatchPlan(dev, tuning=(16384, 4, 2))
+        plan.run()
+        torch.cuda.synchronize()
+        res = [(v.cpu().numpy(), i.cpu().numpy()) for v, i in plan.results()]
+        plan.close()
+    finally:
+        bolt.debug_speculation(-1)
+    for (codes, luts, k, metric), (v, i) in zip(host, res):
+        vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+        assert np.array_equal(v, vr)
+        assert np.array_equal(i, ir)
