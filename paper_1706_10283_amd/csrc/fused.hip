@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
     __syncthreads();
     uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, s_lo, s_hi, k);
     if (threadIdx.x < 64 && n > k)
-        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
+        bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
     __syncthreads();
     if (gridDim.y == 1) {
         if (fail && (n < k || fail[q]))
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
         return;
     }
     if (tid < 64 && n > k)
-        bolt::prune_u64<bolt::kMergeCap>(L.mb, n, k);
+        bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
     __syncthreads();
     bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
 }

@@ -911,7 +911,7 @@ __device__ uint32_t merge_collect(MergeLds &L, const uint64_t *__restrict__ src,
     }
     uint32_t n = L.mcnt;
     if (tid < 64 && n > k)
-        prune_u64<kMergeCap>(L.mb, n, k);
+        prune_u64_fit<kMergeCap>(L.mb, n, k);
     __syncthreads();
     return n > k ? k : n;
 }
@@ -1069,7 +1069,7 @@ __device__ void redo_query(MergeLds &L, const uint8_t *__restrict__ codes, int64
     }
     const uint32_t n = L.mcnt;
     if (tid < 64 && n > k)
-        prune_u64<kMergeCap>(L.mb, n, k);
+        prune_u64_fit<kMergeCap>(L.mb, n, k);
     __syncthreads();
     merge_emit(L, n > k ? k : n, k, largest, 255u * (uint32_t)M, vals + q * k, idx + q * k);
 }

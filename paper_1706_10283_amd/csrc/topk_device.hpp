@@ -207,4 +207,18 @@ __device__ __attribute__((noinline)) uint64_t prune_u64(uint64_t *keys, uint32_t
     return ans;
 }
 
+// prune_u64 over the smallest buffer size that holds n keys (up to CAP): the
+// 48 counting passes cost in proportion to the registers each lane loads.
+template <int CAP>
+__device__ uint64_t prune_u64_fit(uint64_t *keys, uint32_t n, uint32_t k)
+{
+    if (CAP > 256 && n <= 256)
+        return prune_u64<(CAP > 256 ? 256 : CAP)>(keys, n, k);
+    if (CAP > 512 && n <= 512)
+        return prune_u64<(CAP > 512 ? 512 : CAP)>(keys, n, k);
+    if (CAP > 1024 && n <= 1024)
+        return prune_u64<(CAP > 1024 ? 1024 : CAP)>(keys, n, k);
+    return prune_u64<CAP>(keys, n, k);
+}
+
 }  // namespace bolt
