@@ -44,10 +44,10 @@ struct DevDb {
     int32_t k;
     int32_t largest;
     // speculative starting bounds (matrix-core databases from kSpecMinRows rows)
-    uint16_t *sdist;   // sample distances [Q][S], or null: no speculation
-    int64_t S;         // sample rows: S / kSpecSpan chunks at a stride of `stride` rows
+    uint16_t *sdist;   // sample group minima [Q][G], or null: no speculation
+    int64_t G;         // group minima per query: G / kSpecGroups chunks at a stride of `stride` rows
     int64_t stride;
-    int32_t spec_r;    // rank of the sample distance taken as the bound
+    int32_t spec_r;    // rank of the sample group minimum taken as the bound
     int32_t pad;
 };
 
@@ -153,27 +153,28 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict
     }
 }
 
-// Sample distances of the speculative bounds (as in the one-database path):
-// one workgroup per work item.
+// Sample group minima of the speculative bounds (as in the one-database
+// path): one workgroup per work item.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_sample_kernel(
     const DevDb *__restrict__ dbs, const DevSample *__restrict__ items)
 {
     __shared__ uint4 onehot[16];
+    __shared__ __attribute__((aligned(16))) uint16_t gmin[32 * bolt::kSpecGminStride];
     const DevSample it = items[blockIdx.x];
     const DevDb db = dbs[it.db];
     const int nq = (db.Q - it.q0) < 32 ? (db.Q - it.q0) : 32;
-    const int64_t r0 = (int64_t)it.chunk * db.stride, s0 = (int64_t)it.chunk * bolt::kSpecSpan;
+    const int64_t r0 = (int64_t)it.chunk * db.stride, g0 = (int64_t)it.chunk * bolt::kSpecGroups;
     if (db.M == 16)
-        bolt::mfma_sample_tile<16, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, bolt::kSpecSpan, db.sdist,
-                                      db.S, s0, onehot);
+        bolt::mfma_sample_tile<16, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
+                                      gmin);
     else
-        bolt::mfma_sample_tile<32, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, bolt::kSpecSpan, db.sdist,
-                                      db.S, s0, onehot);
+        bolt::mfma_sample_tile<32, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
+                                      gmin);
 }
 
 // Starting bound of each query of a speculative database: the upper edge of
-// the histogram bin holding the r-th smallest sample distance (0 when a test
-// forces the recomputation); other queries keep the open bound.
+// the histogram bin holding the r-th smallest sample group minimum (0 when a
+// test forces the recomputation); other queries keep the open bound.
 __global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restrict__ dbs,
                                                            const DevQuery *__restrict__ queries, int force_fail)
 {
@@ -186,8 +187,8 @@ __global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restri
     for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
         h[i] = 0;
     __syncthreads();
-    const uint4 *d = reinterpret_cast<const uint4 *>(db.sdist + (int64_t)qq.q * db.S);   // 8 distances per load
-    for (int64_t i = threadIdx.x; i < db.S / 8; i += 256) {
+    const uint4 *d = reinterpret_cast<const uint4 *>(db.sdist + (int64_t)qq.q * db.G);   // 8 minima per load
+    for (int64_t i = threadIdx.x; i < db.G / 8; i += 256) {
         const uint4 v = d[i];
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -315,7 +316,7 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
         const int64_t nsc = spec_chunks(d, kind);
         if (nsc) {
             samples += (d.Q + 31) / 32 * nsc;
-            cand += align256((size_t)d.Q * nsc * bolt::kSpecSpan * sizeof(uint16_t));
+            cand += align256((size_t)d.Q * nsc * bolt::kSpecGroups * sizeof(uint16_t));
         }
     }
     L.n_tiles = tiles;
@@ -434,10 +435,10 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
         const int64_t nsc = spec_chunks(d, kind);
         if (nsc) {
             o.sdist = reinterpret_cast<uint16_t *>(p->ws + cand_off);
-            cand_off += align256((size_t)d.Q * nsc * bolt::kSpecSpan * sizeof(uint16_t));
-            o.S = nsc * bolt::kSpecSpan;
+            cand_off += align256((size_t)d.Q * nsc * bolt::kSpecGroups * sizeof(uint16_t));
+            o.G = nsc * bolt::kSpecGroups;
             o.stride = d.N / nsc;
-            o.spec_r = bolt::spec_rank(d.k, (double)o.S / (double)d.N);
+            o.spec_r = bolt::spec_rank(d.k, (double)(nsc * bolt::kSpecSpan) / (double)d.N);
             for (int q0 = 0; q0 < d.Q; q0 += 32)
                 for (int64_t c = 0; c < nsc; ++c)
                     hs.push_back({i, q0, (int32_t)c, 0});

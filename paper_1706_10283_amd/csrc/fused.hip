@@ -324,28 +324,30 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restri
             atomicAdd(&hist[q * bolt::kHistBins + i], h[i]);
 }
 
-// Sample distances (speculative bounds): workgroup (query block, chunk c)
-// writes the d of its queries over rows [c * stride, c * stride + span) to
-// out[q][c * span ...].
+// Sample (speculative bounds): workgroup (query block, chunk c) writes the
+// group minima of its queries over rows [c * stride, c * stride + kSpecSpan)
+// to out[q][c * kSpecGroups ...] (G entries per query).
 template <int MM, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void spec_sample_kernel(
     const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t Q, int largest, int64_t stride,
-    int64_t span, int64_t S, uint16_t *__restrict__ out)
+    int64_t G, uint16_t *__restrict__ out)
 {
     __shared__ uint4 onehot[16];
+    __shared__ __attribute__((aligned(16))) uint16_t gmin[32 * NT * bolt::kSpecGminStride];
     const int64_t q0 = (int64_t)blockIdx.x * 32 * NT;
     const int nq = (int)((Q - q0) < 32 * NT ? (Q - q0) : 32 * NT);
     const int64_t c = blockIdx.y;
-    bolt::mfma_sample_tile<MM, NT>(codes, luts, q0, nq, largest, c * stride, span, out, S, c * span, onehot);
+    bolt::mfma_sample_tile<MM, NT>(codes, luts, q0, nq, largest, c * stride, out, G, c * bolt::kSpecGroups, onehot,
+                                   gmin);
 }
 
-// Speculative bound of one query (one workgroup): histogram of its S sample
-// distances and the upper edge of the bin holding the r-th smallest, written
-// as the query's starting bound (0 when a test forces every query onto the
-// recomputation).  Also clears the query's candidate histogram and overflow
-// flag (this kernel replaces the initialisation when the bounds are
-// speculative).
-__global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ dists, int64_t S,
+// Speculative bound of one query (one workgroup): histogram of its G sample
+// group minima and the upper edge of the bin holding the r-th smallest
+// (r distinct sample rows lie at or below it), written as the query's
+// starting bound (0 when a test forces every query onto the recomputation).
+// Also clears the query's candidate histogram and overflow flag (this kernel
+// replaces the initialisation when the bounds are speculative).
+__global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ gmins, int64_t G,
                                                           uint32_t r, int shift, uint32_t *__restrict__ gthr,
                                                           uint32_t *__restrict__ hist, uint32_t *__restrict__ fail,
                                                           int force_fail)
@@ -357,8 +359,8 @@ __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__rest
         hist[q * bolt::kHistBins + i] = 0;
     }
     __syncthreads();
-    const uint4 *d = reinterpret_cast<const uint4 *>(dists + q * S);   // 8 distances per load
-    for (int64_t i = threadIdx.x; i < S / 8; i += 256) {
+    const uint4 *d = reinterpret_cast<const uint4 *>(gmins + q * G);   // 8 minima per load
+    for (int64_t i = threadIdx.x; i < G / 8; i += 256) {
         const uint4 v = d[i];
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -393,8 +395,12 @@ constexpr int ng_for()
 // smallest rows fall in the sample; for a random row order that number is
 // binomial(k, S / N), and r is the smallest rank whose tail is below 1e-7
 // (r = k: the bound is certain).  The sample's distances come from the
-// matrix cores (whatever kernel scans), the r-th smallest from a histogram,
-// rounded up to its bin's edge.  The bound only selects candidates: the
+// matrix cores (whatever kernel scans) and are kept as one minimum per group
+// of kSpecGroup sample rows: the r-th smallest group minimum still has r
+// distinct sample rows at or below it, so the same tail bounds it, and for
+// small r it rarely differs from the r-th smallest distance.  It is found
+// from a histogram, rounded up to its bin's edge.  The bound only selects
+// candidates: the
 // final merge flags any query with fewer than k candidates and
 // redo_query recomputes it exactly, so results never depend on it.
 using bolt::kSpecSpan;
@@ -412,7 +418,7 @@ struct FusedPlan {
     bool spec = false;   // speculative bound from a sample
     int spec_r = 0, spec_nsc = 0;
     int64_t spec_stride = 0;
-    size_t spec_bytes = 0;   // sample distances [Q][nsc * kSpecSpan] uint16, overflow flags [Q]
+    size_t spec_bytes = 0;   // sample group minima [Q][nsc * kSpecGroups] uint16, overflow flags [Q]
 };
 
 // The kernel for the shape and its rows per tile (N: rows to scan).
@@ -481,7 +487,7 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
                                     : 0;
     if (p.n_chunks > 65535)
         return p;
-    p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * kSpecSpan * sizeof(uint16_t)) +
+    p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * bolt::kSpecGroups * sizeof(uint16_t)) +
                                 align256((size_t)Q * sizeof(uint32_t))
                           : 0;
     p.ok = true;
@@ -544,29 +550,20 @@ void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, c
 }
 
 void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_t Q, int largest, int64_t stride,
-                        int64_t S, int nsc, uint16_t *out, hipStream_t s)
+                        int64_t G, int nsc, uint16_t *out, hipStream_t s)
 {
     const int nt = kMfmaNT;
     const dim3 grid((unsigned)((Q + 32 * nt - 1) / (32 * nt)), (unsigned)nsc);
-    const int64_t span = kSpecSpan;
+#define BOLT_SAMPLE_M(MM)                                                                                           \
+    hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, G, \
+                       out)
     switch (M) {
-    case 8:
-        hipLaunchKernelGGL((spec_sample_kernel<8, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
-                           S, out);
-        break;
-    case 16:
-        hipLaunchKernelGGL((spec_sample_kernel<16, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
-                           S, out);
-        break;
-    case 32:
-        hipLaunchKernelGGL((spec_sample_kernel<32, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
-                           S, out);
-        break;
-    case 64:
-        hipLaunchKernelGGL((spec_sample_kernel<64, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, span,
-                           S, out);
-        break;
+    case 8: BOLT_SAMPLE_M(8); break;
+    case 16: BOLT_SAMPLE_M(16); break;
+    case 32: BOLT_SAMPLE_M(32); break;
+    case 64: BOLT_SAMPLE_M(64); break;
     }
+#undef BOLT_SAMPLE_M
 }
 
 const char *scan_prof_name(int kind)
@@ -631,18 +628,18 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     uint32_t *level2_cnt = reinterpret_cast<uint32_t *>(w + p.gthr_bytes + p.hist_bytes +
                                                         align256((size_t)Q * p.n_chunks * k * sizeof(uint64_t)));
     char *ws_spec = w + p.gthr_bytes + p.hist_bytes + p.level2_bytes;
-    const int64_t S = (int64_t)p.spec_nsc * kSpecSpan;
-    uint16_t *sdist = p.spec ? reinterpret_cast<uint16_t *>(ws_spec) : nullptr;
-    uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * S * sizeof(uint16_t)))
+    const int64_t G = (int64_t)p.spec_nsc * bolt::kSpecGroups;
+    uint16_t *gmins = p.spec ? reinterpret_cast<uint16_t *>(ws_spec) : nullptr;
+    uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * G * sizeof(uint16_t)))
                             : nullptr;
     if (p.spec) {
-        // sample distances, then each query's starting bound (and cleared histogram)
+        // sample group minima, then each query's starting bound (and cleared histogram)
         {
             bolt::ProfScope prof_("spec_sample", s);
-            launch_spec_sample(M, codes, luts, Q, (int)largest, p.spec_stride, S, p.spec_nsc, sdist, s);
+            launch_spec_sample(M, codes, luts, Q, (int)largest, p.spec_stride, G, p.spec_nsc, gmins, s);
         }
         bolt::ProfScope prof_("spec_select", s);
-        hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, sdist, S, (uint32_t)p.spec_r,
+        hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, gmins, G, (uint32_t)p.spec_r,
                            bolt::hist_shift(M), gthr, hist, fail, bolt::g_spec_mode == 2 ? 1 : 0);
     } else {
         const int64_t n_hist = Q * bolt::kHistBins;

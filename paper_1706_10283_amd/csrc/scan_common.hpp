@@ -49,9 +49,12 @@ extern int g_spec_mode;           // speculative bounds: -1 automatic, 0 off, 1 
 
 // Speculative starting bounds (fused.hip): sample chunks of kSpecSpan rows,
 // used from kSpecMinRows rows (kSpecMinRowsForced under test mode 1), at
-// most kSpecMaxDists sample distances held at once; spec_rank gives the
-// smallest rank r with P(binomial(k, p) >= r) <= 1e-7 (at most k).
+// most kSpecMaxDists sample distances computed per call, kept as one
+// minimum per kSpecGroup rows; spec_rank gives the smallest rank r with
+// P(binomial(k, p) >= r) <= 1e-7 (at most k).
 constexpr int64_t kSpecSpan = 1024;
+constexpr int kSpecGroup = 16;
+constexpr int kSpecGroups = (int)kSpecSpan / kSpecGroup;   // group minima per chunk
 constexpr int64_t kSpecMinRows = 1 << 19;
 constexpr int64_t kSpecMinRowsForced = 1 << 17;
 constexpr int64_t kSpecMaxDists = 1 << 26;

@@ -545,14 +545,18 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
     }
 }
 
-// Sample distances for the speculative bounds: the d of every (query, row)
-// of span consecutive rows from r0, written as uint16 to out[q][s0 + row - r0]
-// (out has S entries per query).  Each lane's accumulators hold four runs of
-// four consecutive rows of one query, written as 8-byte words.
+// Sample for the speculative bounds: the d of every (query, row) of the
+// kSpecSpan consecutive rows from r0, reduced to one minimum per group of
+// kSpecGroup rows (the 16 rows one lane's accumulators hold in a pass, from
+// four runs of four), written as uint16 to out[q][g0 .. g0 + kSpecGroups)
+// (out has G entries per query).  The minima are staged in LDS (gmin, at
+// least 32 * NT * kSpecGminStride entries) and stored as 16-byte rows.
+constexpr int kSpecGminStride = kSpecGroups + 8;   // uint16 per query row in LDS (2-way banks)
+
 template <int MM, int NT>
 __device__ void mfma_sample_tile(const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t q0,
-                                 int nq, int largest, int64_t r0, int64_t span, uint16_t *__restrict__ out,
-                                 int64_t S, int64_t s0, uint4 *onehot)
+                                 int nq, int largest, int64_t r0, uint16_t *__restrict__ out, int64_t G,
+                                 int64_t g0, uint4 *onehot, uint16_t *gmin)
 {
     constexpr int NW = MM / 8;
     constexpr int OFF = 128 * MM;
@@ -566,31 +570,32 @@ __device__ void mfma_sample_tile(const uint8_t *__restrict__ codes, const uint8_
     // codes one pass ahead (the last pass re-reads its own rows)
     uint32_t nxt[NW];
     load_row<MM>(codes, r0 + 32 * wave + col, nxt);
-    for (int64_t base = 0; base < span; base += kMfmaPass) {
+    for (int base = 0; base < (int)kSpecSpan; base += kMfmaPass) {
         uint32_t cw[NW];
 #pragma unroll
         for (int v = 0; v < NW; ++v)
             cw[v] = nxt[v];
-        const int64_t ahead = base + kMfmaPass < span ? base + kMfmaPass : base;
+        const int ahead = base + kMfmaPass < (int)kSpecSpan ? base + kMfmaPass : base;
         load_row<MM>(codes, r0 + ahead + 32 * wave + col, nxt);
         __builtin_amdgcn_sched_barrier(0);
         i32x16 acc[NT];
         mfma_pass<MM, NT>(cw, oh, tb, acc);
-        const int64_t rl = base + 32 * wave + 4 * half;   // first row of this lane's runs, from r0
+        const int g = base / kSpecGroup + 2 * wave + half;   // this lane's group in the chunk
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int q = 32 * t + col;
-            if (q < nq) {
-                uint16_t *dst = out + (q0 + q) * S + s0 + rl;
+            int m = acc[t][0];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t lo = (uint32_t)(acc[t][4 * j] + OFF) | ((uint32_t)(acc[t][4 * j + 1] + OFF) << 16);
-                    const uint32_t hi =
-                        (uint32_t)(acc[t][4 * j + 2] + OFF) | ((uint32_t)(acc[t][4 * j + 3] + OFF) << 16);
-                    *reinterpret_cast<uint2 *>(dst + 8 * j) = make_uint2(lo, hi);
-                }
-            }
+            for (int v = 1; v < 16; ++v)
+                m = acc[t][v] < m ? acc[t][v] : m;
+            gmin[(32 * t + col) * kSpecGminStride + g] = (uint16_t)(m + OFF);
         }
+    }
+    __syncthreads();
+    constexpr int V = kSpecGroups / 8;   // 16-byte words per query
+    for (int e = tid; e < nq * V; e += 256) {
+        const int q = e / V, v = e - q * V;
+        reinterpret_cast<uint4 *>(out + (q0 + q) * G + g0)[v] =
+            reinterpret_cast<const uint4 *>(gmin + q * kSpecGminStride)[v];
     }
 }
 
