@@ -389,13 +389,35 @@ __device__ __forceinline__ void mfma_pass(const uint32_t (&cw)[MM / 8], const ch
 #pragma unroll
     for (int t = 0; t < NT; ++t)
         acc[t] = i32x16{};
+    if constexpr (MM >= 64) {
+        // two waves per SIMD at this width: keep four one-hot reads in flight,
+        // in the order written (the scheduler would otherwise sink them)
+        constexpr int D = 4;
+        i32x4 av[D];
 #pragma unroll
-    for (int s = 0; s < MM / 2; ++s) {
-        const uint32_t a = (wa[s >> 2] >> (8 * (s & 3))) & 0xFFu;
-        const i32x4 av = *reinterpret_cast<const i32x4 *>(oh + a);
+        for (int s = 0; s < D - 1; ++s)
+            av[s] = *reinterpret_cast<const i32x4 *>(oh + ((wa[s >> 2] >> (8 * (s & 3))) & 0xFFu));
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-            acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, tb[t][s], acc[t], 0, 0, 0);
+        for (int s = 0; s < MM / 2; ++s) {
+            if (s + D - 1 < MM / 2) {
+                const int u = s + D - 1;
+                av[u % D] = *reinterpret_cast<const i32x4 *>(oh + ((wa[u >> 2] >> (8 * (u & 3))) & 0xFFu));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av[s % D], tb[t][s], acc[t], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < MM / 2; ++s) {
+            const uint32_t a = (wa[s >> 2] >> (8 * (s & 3))) & 0xFFu;
+            const i32x4 av = *reinterpret_cast<const i32x4 *>(oh + a);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, tb[t][s], acc[t], 0, 0, 0);
+        }
     }
 }
 
