@@ -320,13 +320,17 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
 //
 // FREE (with speculative starting bounds only): the bounds are taken as
 // they are and never tightened, so the waves need no barriers between
-// passes: appends take slots with LDS atomics, and a query whose buffer
-// would overflow (never in practice: the bound admits a few rows per tile)
-// is flagged in job.fail, writes no keys, and is recomputed exactly by the
-// final merge.
+// passes, and no atomics either: the query's buffer is cut into kMfmaSegs
+// segments, one per (wave, lane half), each lane appending to its own with
+// a private count; the tile's end packs the segments.  A query whose
+// segment would overflow (never in practice: the bound admits a few rows
+// per tile) is flagged in job.fail, writes no keys, and is recomputed
+// exactly by the final merge.
 
 constexpr int kMfmaCap = 256;    // candidate slots per query: k <= kMfmaCap - kMfmaPass
 constexpr int kMfmaPass = 128;   // rows per pass: 4 waves x 32
+constexpr int kMfmaSegs = 8;     // FREE: one buffer segment per (wave, lane half)
+constexpr int kMfmaSeg = kMfmaCap / kMfmaSegs;
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
@@ -336,6 +340,7 @@ struct MfmaLds {
     uint32_t buf[NT * 32 * kMfmaCap];
     uint32_t cnt[NT * 32];
     uint32_t bnd[NT * 32];
+    uint32_t seg[NT * 32 * kMfmaSegs];   // FREE: keys appended to each segment
     uint4 onehot[16];
 };
 
@@ -459,6 +464,12 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
         thr[t] = (int)L.bnd[32 * t + col] - OFF;
+    // FREE: this lane's segment of each query's buffer and its append count
+    const int sg = 2 * wave + half;
+    uint32_t pc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        pc[t] = 0;
     int pass = 0;
     for (int64_t base = r0; base < r1; base += kMfmaPass, ++pass) {
         // published bounds: read at the start of every pass (unconditional,
@@ -512,9 +523,14 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
                 for (int v = 0; v < 16; ++v) {
                     if (acc[t][v] < thr[t]) {
                         const uint32_t d = (uint32_t)(acc[t][v] + OFF);
-                        const uint32_t pos = atomicAdd(&L.cnt[q], 1u);
-                        if (!FREE || pos < CAP)
-                            L.buf[q * CAP + pos] = local_key(d, lbase + 8 * (v >> 2) + (v & 3));
+                        const uint32_t key = local_key(d, lbase + 8 * (v >> 2) + (v & 3));
+                        if (FREE) {
+                            if (pc[t] < (uint32_t)kMfmaSeg)
+                                L.buf[q * CAP + sg * kMfmaSeg + pc[t]] = key;
+                            ++pc[t];
+                        } else {
+                            L.buf[q * CAP + atomicAdd(&L.cnt[q], 1u)] = key;
+                        }
                     }
                 }
             }
@@ -549,15 +565,54 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
         }
         __syncthreads();
     }
-    if (FREE)
+    if (FREE) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            L.seg[(32 * t + col) * kMfmaSegs + sg] = pc[t];
         __syncthreads();   // every append is done
+    }
     for (int q = wave; q < nq && q < QB; q += 4) {
-        if (FREE && L.cnt[q] > CAP) {   // overflowed: no keys, the merge recomputes the query
-            if (lane == 0) {
-                job.fail[q0 + q] = 1u;
-                job.ccnt[(q0 + q) * job.n_rb + job.rb] = 0u;
+        if (FREE) {
+            // pack the segments in place: a wave reads all of the query's
+            // keys into registers before it writes any
+            const uint32_t c = lane < kMfmaSegs ? L.seg[q * kMfmaSegs + lane] : 0u;
+            if (__ballot(c > (uint32_t)kMfmaSeg)) {   // overflowed: no keys, the merge recomputes the query
+                if (lane == 0) {
+                    job.fail[q0 + q] = 1u;
+                    job.ccnt[(q0 + q) * job.n_rb + job.rb] = 0u;
+                }
+                continue;
             }
-            continue;
+            // key i of the packed list sits at slot i + (g kMfmaSeg - pre_g) of
+            // its segment g: the gaps of the segments before it
+            uint32_t pre[kMfmaSegs], gap[kMfmaSegs];
+            uint32_t n = 0;
+#pragma unroll
+            for (int g = 0; g < kMfmaSegs; ++g) {
+                const uint32_t cg = __shfl(c, g);
+                pre[g] = n;
+                gap[g] = (uint32_t)kMfmaSeg - cg;
+                n += cg;
+            }
+            constexpr int PER = CAP / 64;
+            uint32_t key[PER];
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const uint32_t i = (uint32_t)(lane + 64 * e);
+                uint32_t src = i;
+#pragma unroll
+                for (int g = 1; g < kMfmaSegs; ++g)
+                    src += i >= pre[g] ? gap[g - 1] : 0u;
+                key[e] = i < n ? L.buf[q * CAP + src] : 0u;
+            }
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const uint32_t i = (uint32_t)(lane + 64 * e);
+                if (i < n)
+                    L.buf[q * CAP + i] = key[e];
+            }
+            if (lane == 0)
+                L.cnt[q] = n;
         }
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
