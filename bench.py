@@ -65,9 +65,9 @@ WRITE_FACTOR = 1.0
 TRAFFIC = {
     "scan_topk_mfma": {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 9874.1,
-        "write_kib": 18713.3,
-        "sources_sha256": "9d388ff9ab8bb1032b381a314e72d5aeec217331da9dad02fc6a0f786c31f5f1",
+        "fetch_kib": 9891.3,
+        "write_kib": 18747.8,
+        "sources_sha256": "348cc870f1bb9db6ab8d31cc5c3a84a68ba35fe8070542ac355fc00f1dc98c3e",
     },
 }
 TRAFFIC_SOURCES = {

@@ -172,9 +172,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
                                       gmin);
 }
 
-// Starting bound of each query of a speculative database: the upper edge of
-// the histogram bin holding the r-th smallest sample group minimum (0 when a
-// test forces the recomputation); other queries keep the open bound.
+// Starting bound of each query of a speculative database: the r-th smallest
+// of its sample group minima (0 when a test forces the recomputation); other
+// queries keep the open bound.
 __global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restrict__ dbs,
                                                            const DevQuery *__restrict__ queries, int force_fail)
 {
@@ -183,26 +183,10 @@ __global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restri
     const DevDb db = dbs[qq.db];
     if (!db.sdist)
         return;
-    const int shift = bolt::hist_shift(db.M);
-    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
-        h[i] = 0;
-    __syncthreads();
-    const uint4 *d = reinterpret_cast<const uint4 *>(db.sdist + (int64_t)qq.q * db.G);   // 8 minima per load
-    for (int64_t i = threadIdx.x; i < db.G / 8; i += 256) {
-        const uint4 v = d[i];
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            atomicAdd(&h[(w[j] & 0xFFFFu) >> shift], 1u);
-            atomicAdd(&h[(w[j] >> 16) >> shift], 1u);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const uint32_t b = bolt::hist_bound(h, (uint32_t)db.spec_r, shift, 0xFFFFu);
-        if (threadIdx.x == 0)
-            db.gthr[qq.q] = force_fail ? 0u : b;
-    }
+    const uint32_t b = bolt::select_rank_u16(db.sdist + (int64_t)qq.q * db.G, db.G, (uint32_t)db.spec_r,
+                                             bolt::hist_shift(db.M), h);
+    if (threadIdx.x == 0)
+        db.gthr[qq.q] = force_fail ? 0u : b;
 }
 
 // Top k of one query from its candidate lists; a query of a speculative

@@ -341,12 +341,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
                                    gmin);
 }
 
-// Speculative bound of one query (one workgroup): histogram of its G sample
-// group minima and the upper edge of the bin holding the r-th smallest
-// (r distinct sample rows lie at or below it), written as the query's
-// starting bound (0 when a test forces every query onto the recomputation).
-// Also clears the query's candidate histogram and overflow flag (this kernel
-// replaces the initialisation when the bounds are speculative).
+// Speculative bound of one query (one workgroup): the r-th smallest of its
+// G sample group minima (r distinct sample rows lie at or below it), written
+// as the query's starting bound (0 when a test forces every query onto the
+// recomputation).  Also clears the query's candidate histogram and overflow
+// flag (this kernel replaces the initialisation when the bounds are
+// speculative).
 __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ gmins, int64_t G,
                                                           uint32_t r, int shift, uint32_t *__restrict__ gthr,
                                                           uint32_t *__restrict__ hist, uint32_t *__restrict__ fail,
@@ -354,28 +354,12 @@ __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__rest
 {
     __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
     const int64_t q = blockIdx.x;
-    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256) {
-        h[i] = 0;
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
         hist[q * bolt::kHistBins + i] = 0;
-    }
-    __syncthreads();
-    const uint4 *d = reinterpret_cast<const uint4 *>(gmins + q * G);   // 8 minima per load
-    for (int64_t i = threadIdx.x; i < G / 8; i += 256) {
-        const uint4 v = d[i];
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            atomicAdd(&h[(w[j] & 0xFFFFu) >> shift], 1u);
-            atomicAdd(&h[(w[j] >> 16) >> shift], 1u);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const uint32_t b = hist_bound(h, r, shift, 0xFFFFu);
-        if (threadIdx.x == 0) {
-            gthr[q] = force_fail ? 0u : b;
-            fail[q] = 0u;
-        }
+    const uint32_t b = bolt::select_rank_u16(gmins + q * G, G, r, shift, h);
+    if (threadIdx.x == 0) {
+        gthr[q] = force_fail ? 0u : b;
+        fail[q] = 0u;
     }
 }
 

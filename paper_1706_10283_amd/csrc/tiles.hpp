@@ -1100,6 +1100,82 @@ __device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int 
     return edge < bound ? edge : bound;
 }
 
+// Exact r-th smallest of the G uint16 values v[0, G) (G a multiple of 8, v
+// 16-byte aligned), by one workgroup of 256 threads: a histogram (h, LDS,
+// kHistBins bins of 2^shift values) finds the value's bin and the count
+// below it, a second pass counts that bin's values one by one.  Returns
+// 0xFFFF when G < r.
+__device__ uint32_t select_rank_u16(const uint16_t *__restrict__ v, int64_t G, uint32_t r, int shift, uint32_t *h)
+{
+    __shared__ uint32_t sub[64];   // one counter per value of the bin (2^shift <= 64)
+    __shared__ uint32_t loc[2];    // the bin, the count below it
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kHistBins; i += 256)
+        h[i] = 0;
+    if (tid < 64)
+        sub[tid] = 0;
+    __syncthreads();
+    const uint4 *d = reinterpret_cast<const uint4 *>(v);   // 8 values per load
+    for (int64_t i = tid; i < G / 8; i += 256) {
+        const uint4 t = d[i];
+        const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            atomicAdd(&h[(w[j] & 0xFFFFu) >> shift], 1u);
+            atomicAdd(&h[(w[j] >> 16) >> shift], 1u);
+        }
+    }
+    __syncthreads();
+    if (tid < 64) {
+        constexpr int PER = kHistBins / 64;
+        uint32_t own = 0;
+        for (int i = 0; i < PER; ++i)
+            own += h[tid * PER + i];
+        uint32_t inc = own;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (tid >= o)
+                inc += t;
+        }
+        const uint64_t hit = __ballot(inc >= r);
+        if (tid == (hit ? (int)__builtin_ctzll(hit) : 0)) {
+            uint32_t run = inc - own, bin = 0xFFFFFFFFu;
+            for (int i = 0; hit && i < PER; ++i) {
+                const uint32_t c = h[tid * PER + i];
+                if (run + c >= r) {
+                    bin = (uint32_t)(tid * PER + i);
+                    break;
+                }
+                run += c;
+            }
+            loc[0] = bin;
+            loc[1] = run;
+        }
+    }
+    __syncthreads();
+    const uint32_t bin = loc[0];
+    if (bin == 0xFFFFFFFFu)
+        return 0xFFFFu;
+    for (int64_t i = tid; i < G / 8; i += 256) {
+        const uint4 t = d[i];
+        const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t a = w[j] & 0xFFFFu, b = w[j] >> 16;
+            if ((a >> shift) == bin)
+                atomicAdd(&sub[a & ((1u << shift) - 1u)], 1u);
+            if ((b >> shift) == bin)
+                atomicAdd(&sub[b & ((1u << shift) - 1u)], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t run = loc[1], j = 0;
+    while (run + sub[j] < r)   // the bin holds the r-th value: ends at j < 2^shift
+        run += sub[j++];
+    return (bin << shift) + j;
+}
+
 // Exact top-k of one query whose speculative bound failed (fewer than k
 // rows passed it), by the merging workgroup itself: it scans every row with
 // the query's table in LDS, appends keys (d << 32 | row) below the running
