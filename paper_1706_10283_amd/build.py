@@ -23,9 +23,11 @@ SOURCES = ["errors.cpp", "prof.cpp", "encode.hip", "luts.hip", "scan.hip", "topk
 
 COMMON_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
                 "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
-# Device code: gfx950 only; packed fp32 instructions disabled.
+# Device code: gfx950 only; packed fp32 instructions disabled; matrix-core
+# accumulators in ordinary VGPRs (no copies out of the accumulation registers
+# before the candidate test, and fewer registers per wave).
 HIP_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
-             "-packed-fp32-ops", "-munsafe-fp-atomics"]
+             "-packed-fp32-ops", "-munsafe-fp-atomics", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _headers():
