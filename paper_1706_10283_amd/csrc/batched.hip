@@ -79,8 +79,8 @@ constexpr size_t kBatchLds = 49664;
 __global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < 2)
-        counter[i] = 0;   // matrix-core tiles, other tiles
+    if (i < 3)
+        counter[i] = 0;   // matrix-core tiles (M = 16, 32), other tiles, matrix-core tiles (M = 64)
     if (i < n)
         gthr[i] = 0xFFFFu;
 }
@@ -111,10 +111,11 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     }
 }
 
-// MF: the matrix-core tiles (a launch of their own, so that the other
-// tiles keep their own register budget), else the pair-table and grouped
-// tiles.
-template <bool MF>
+// F = 1: the matrix-core tiles of M = 16 and 32, F = 2: those of M = 64,
+// F = 0: the pair-table and grouped tiles.  Each family is a launch of its
+// own, so that each keeps its own register budget (at M = 64 the tables
+// alone take 128 registers: two waves per SIMD).
+template <int F>
 __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict__ dbs,
                                                          const DevTile *__restrict__ tiles,
                                                          int32_t n_tiles, int64_t rows_per_tile,
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict
     static_assert(sizeof(bolt::GroupedLds<16, 2>) <= kBatchLds, "grouped tile LDS");
     static_assert(sizeof(bolt::GroupedLds<8, 2>) <= kBatchLds, "grouped tile LDS");
     static_assert(sizeof(bolt::MfmaLds<1>) <= kBatchLds, "matrix-core tile LDS");
-    __shared__ __attribute__((aligned(16))) char lds[MF ? sizeof(bolt::MfmaLds<1>) : kBatchLds];
+    __shared__ __attribute__((aligned(16))) char lds[F ? sizeof(bolt::MfmaLds<1>) : kBatchLds];
     __shared__ int32_t sh_tile;
     for (;;) {
         if (threadIdx.x == 0)
@@ -137,7 +138,11 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict
             break;
         const DevTile t = tiles[ti];
         const DevDb db = dbs[t.db];
-        if (MF) {   // M = 16 or 32 only (see tile_kind)
+        if (F == 2) {   // M = 64 only
+            run_tile<64, true>(db, t, rows_per_tile, lds);
+            continue;
+        }
+        if (F == 1) {   // M = 16 or 32 only (see tile_kind)
             if (db.M == 16)
                 run_tile<16, true>(db, t, rows_per_tile, lds);
             else
@@ -167,8 +172,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     if (db.M == 16)
         bolt::mfma_sample_tile<16, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
                                       gmin);
-    else
+    else if (db.M == 32)
         bolt::mfma_sample_tile<32, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
+                                      gmin);
+    else
+        bolt::mfma_sample_tile<64, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
                                       gmin);
 }
 
@@ -247,14 +255,13 @@ int resolve(const bolt_batch_tuning *tuning, int32_t &rows, int32_t &few_max, in
 bool few_fits(int M, int nq) { return bolt::few_tile_lds_bytes(M, nq) <= kBatchLds; }
 
 // Tile kind of a database: 1 pair tables (few queries), 3 matrix cores
-// (M = 16 or 32, 32 or more queries, k within the tile's candidate buffer;
-// at M = 64 the tables alone would take 128 registers of every tile of the
-// persistent kernel), else 2 grouped.
+// (M = 16, 32 or 64, 32 or more queries, k within the tile's candidate
+// buffer), else 2 grouped.
 int tile_kind(const bolt_batch_db &d, int few_max)
 {
     if (d.Q <= few_max && few_fits(d.M, d.Q))
         return 1;
-    if ((d.M == 16 || d.M == 32) && d.Q >= 32 && d.k <= bolt::kMfmaCap - bolt::kMfmaPass)
+    if (d.M >= 16 && d.Q >= 32 && d.k <= bolt::kMfmaCap - bolt::kMfmaPass)
         return 3;
     return 2;
 }
@@ -330,7 +337,8 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
 struct bolt_batch_plan {
     char *ws = nullptr;
     int64_t n_tiles = 0, n_queries = 0;
-    int64_t n_mfma = 0;   // the first n_mfma tiles are matrix-core tiles
+    int64_t n_mfma = 0;     // the first n_mfma tiles are matrix-core tiles of M = 16 and 32,
+    int64_t n_mfma64 = 0;   // the next n_mfma64 those of M = 64
     int64_t n_samples = 0;
     int32_t rows_per_tile = 0, grid = 0;
     std::vector<char> host;   // staged descriptors (kept until the plan is destroyed)
@@ -448,17 +456,22 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
         for (int q = 0; q < d.Q; ++q)
             hq.push_back({i, q});
     }
-    // matrix-core tiles first (their own launch), each group longest first
+    // matrix-core tiles of M = 16 and 32, then of M = 64, then the others
+    // (a launch each), each family longest first
+    auto family = [&](const DevTile &t) { return t.kind != 3 ? 2 : (hd[t.db].M == 64 ? 1 : 0); };
     std::vector<int64_t> order(ht.size());
     for (size_t e = 0; e < order.size(); ++e)
         order[e] = (int64_t)e;
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-        const bool ma = ht[a].kind == 3, mb = ht[b].kind == 3;
-        return ma != mb ? ma : cost[a] > cost[b];
+        const int fa = family(ht[a]), fb = family(ht[b]);
+        return fa != fb ? fa < fb : cost[a] > cost[b];
     });
     p->n_mfma = 0;
-    for (const DevTile &t : ht)
-        p->n_mfma += t.kind == 3;
+    p->n_mfma64 = 0;
+    for (const DevTile &t : ht) {
+        p->n_mfma += family(t) == 0;
+        p->n_mfma64 += family(t) == 1;
+    }
     const size_t nb_db = sizeof(DevDb) * hd.size(), nb_t = sizeof(DevTile) * ht.size(),
                  nb_q = sizeof(DevQuery) * hq.size(), nb_s = sizeof(DevSample) * hs.size();
     p->host.resize(nb_db + nb_t + nb_q + nb_s + 1);
@@ -504,13 +517,18 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
     }
     {
         bolt::ProfScope prof_("batch_scan", s);
+        const int64_t n_mf = p->n_mfma + p->n_mfma64;
         if (p->n_mfma > 0)
-            hipLaunchKernelGGL(batch_scan_kernel<true>, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs, p->tiles,
+            hipLaunchKernelGGL(batch_scan_kernel<1>, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs, p->tiles,
                                (int32_t)p->n_mfma, (int64_t)p->rows_per_tile, p->counter);
-        if (p->n_tiles > p->n_mfma)
-            hipLaunchKernelGGL(batch_scan_kernel<false>, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs,
-                               p->tiles + p->n_mfma, (int32_t)(p->n_tiles - p->n_mfma),
-                               (int64_t)p->rows_per_tile, p->counter + 1);
+        if (p->n_mfma64 > 0)
+            hipLaunchKernelGGL(batch_scan_kernel<2>, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs,
+                               p->tiles + p->n_mfma, (int32_t)p->n_mfma64, (int64_t)p->rows_per_tile,
+                               p->counter + 2);
+        if (p->n_tiles > n_mf)
+            hipLaunchKernelGGL(batch_scan_kernel<0>, dim3((unsigned)p->grid), dim3(256), 0, s, p->dbs,
+                               p->tiles + n_mf, (int32_t)(p->n_tiles - n_mf), (int64_t)p->rows_per_tile,
+                               p->counter + 1);
     }
     {
         bolt::ProfScope prof_("batch_merge", s);

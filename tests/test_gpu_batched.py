@@ -25,6 +25,8 @@ DBS = [
     (8, 100, 5, 100, "dot", "rand"), (32, 1, 8, 1, "l2", "rand"), (64, 33000, 1, 50, "dot", "const"),
     (16, 70000, 9, 100, "l2", "coarse"), (32, 0, 4, 10, "l2", "rand"), (8, 20000, 2, 7, "l2", "rand"),
     (32, 16385, 33, 100, "dot", "rand"), (64, 9000, 6, 100, "l2", "rand"), (16, 123457, 7, 256, "dot", "rand"),
+    # matrix-core tiles at M = 64 (their own launch): ragged rows and query block, ties
+    (64, 50001, 45, 100, "dot", "rand"), (64, 20000, 32, 64, "l2", "coarse"),
 ]
 
 
@@ -105,7 +107,7 @@ def test_batched_rejects_bad_input(bolt):
 
 
 # databases large enough for speculative bounds under test mode 1 (2^17 rows),
-# with matrix-core tiles (M = 16 or 32, 32 or more queries), beside others
+# with matrix-core tiles (M = 16, 32 or 64, 32 or more queries), beside others
 SPEC_DBS = [
     (32, 140000, 40, 100, "l2", "rand"), (16, 150000, 70, 64, "dot", "coarse"), (32, 131072, 33, 1, "dot", "const"),
     (64, 140000, 40, 100, "l2", "rand"), (16, 20000, 50, 10, "l2", "rand"), (32, 160000, 5, 100, "dot", "rand"),
