@@ -49,6 +49,7 @@ struct DevDb {
     int64_t stride;
     int32_t spec_r;    // rank of the sample group minimum taken as the bound
     int32_t pad;
+    uint32_t *fail;    // per query: a barrier-free tile overflowed, recompute exactly
 };
 
 // One sample work item: queries [q0, q0 + 32) of a database over one chunk.
@@ -76,13 +77,15 @@ struct DevQuery {
 // few-query tile of at most this many bytes.
 constexpr size_t kBatchLds = 49664;
 
-__global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, int64_t n)
+__global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, uint32_t *fail, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < 3)
         counter[i] = 0;   // matrix-core tiles (M = 16, 32), other tiles, matrix-core tiles (M = 64)
-    if (i < n)
+    if (i < n) {
         gthr[i] = 0xFFFFu;
+        fail[i] = 0u;
+    }
 }
 
 template <int MM, bool MF>
@@ -101,8 +104,13 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     job.nq = t.nq;
     job.k = (uint32_t)db.k;
     job.largest = db.largest;
+    job.fail = db.fail;
     if (MF) {
-        bolt::mfma_tile<MM, 1, false>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
+        // sampled bounds: barrier-free passes (overflow flags the query)
+        if (db.sdist)
+            bolt::mfma_tile<MM, 1, true>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
+        else
+            bolt::mfma_tile<MM, 1, false>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
     } else if (t.kind == 1) {
         bolt::few_tile<MM, false>(job, lds);
     } else {
@@ -198,7 +206,8 @@ __global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restri
 }
 
 // Top k of one query from its candidate lists; a query of a speculative
-// database with fewer than k candidates is recomputed exactly.
+// database with fewer than k candidates, or flagged by an overflowing
+// barrier-free tile, is recomputed exactly.
 __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restrict__ dbs,
                                                           const DevQuery *__restrict__ queries)
 {
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restric
     const int64_t per_query = db.n_rb * db.k;
     const uint32_t k = (uint32_t)db.k;
     const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k, db.gthr[qq.q]);
-    if (db.sdist && n < k) {
+    if (db.sdist && (n < k || db.fail[qq.q])) {
         bolt::redo_query(L, db.codes, db.N, db.M, db.luts, qq.q, k, db.largest, db.vals, db.idx);
         return;
     }
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restric
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    size_t dbs_off, tiles_off, queries_off, gthr_off, counter_off, samples_off, cand_off, total;
+    size_t dbs_off, tiles_off, queries_off, gthr_off, fail_off, counter_off, samples_off, cand_off, total;
     int64_t n_tiles, n_queries, n_samples;
 };
 
@@ -322,6 +331,8 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
     off += align256(sizeof(DevQuery) * (size_t)(queries > 0 ? queries : 1));
     L.gthr_off = off;
     off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
+    L.fail_off = off;
+    off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
     L.counter_off = off;
     off += 256;
     L.samples_off = off;
@@ -346,6 +357,7 @@ struct bolt_batch_plan {
     DevTile *tiles = nullptr;
     DevQuery *queries = nullptr;
     uint32_t *gthr = nullptr;
+    uint32_t *fail = nullptr;
     uint32_t *counter = nullptr;
     DevSample *samples = nullptr;
 };
@@ -388,6 +400,7 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
     p->tiles = reinterpret_cast<DevTile *>(p->ws + L.tiles_off);
     p->queries = reinterpret_cast<DevQuery *>(p->ws + L.queries_off);
     p->gthr = reinterpret_cast<uint32_t *>(p->ws + L.gthr_off);
+    p->fail = reinterpret_cast<uint32_t *>(p->ws + L.fail_off);
     p->counter = reinterpret_cast<uint32_t *>(p->ws + L.counter_off);
     p->samples = reinterpret_cast<DevSample *>(p->ws + L.samples_off);
     p->n_samples = L.n_samples;
@@ -422,6 +435,7 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
         o.cand = reinterpret_cast<uint64_t *>(p->ws + cand_off);
         cand_off += align256((size_t)d.Q * o.n_rb * d.k * sizeof(uint64_t));
         o.gthr = p->gthr + qbase;
+        o.fail = p->fail + qbase;
         qbase += d.Q;
         const int kind = tile_kind(d, few_max);
         const int64_t nsc = spec_chunks(d, kind);
@@ -508,7 +522,7 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
     hipStream_t s = as_stream(stream);
     const int64_t nz = p->n_queries;
     hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, p->counter,
-                       p->gthr, nz);
+                       p->gthr, p->fail, nz);
     if (p->n_samples > 0) {   // speculative starting bounds
         bolt::ProfScope prof_("batch_spec", s);
         hipLaunchKernelGGL(batch_sample_kernel, dim3((unsigned)p->n_samples), dim3(256), 0, s, p->dbs, p->samples);

@@ -579,7 +579,8 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
             if (__ballot(c > (uint32_t)kMfmaSeg)) {   // overflowed: no keys, the merge recomputes the query
                 if (lane == 0) {
                     job.fail[q0 + q] = 1u;
-                    job.ccnt[(q0 + q) * job.n_rb + job.rb] = 0u;
+                    if (job.ccnt)
+                        job.ccnt[(q0 + q) * job.n_rb + job.rb] = 0u;
                 }
                 continue;
             }
