@@ -65,14 +65,15 @@ WRITE_FACTOR = 1.0
 TRAFFIC = {
     "scan_topk_mfma": {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 9891.3,
-        "write_kib": 18747.8,
-        "sources_sha256": "348cc870f1bb9db6ab8d31cc5c3a84a68ba35fe8070542ac355fc00f1dc98c3e",
+        "fetch_kib": 9889.1,
+        "write_kib": 16351.1,
+        "sources_sha256": "565a8ce7e180dcfc19902b94931e0a7b2c1230ac9315a3dc21e16f3aea88db15",
     },
 }
+# the kernel's sources and the build flags (paper_1706_10283_amd/build.py)
 TRAFFIC_SOURCES = {
-    "scan_topk_mfma": ["fused.hip", "tiles.hpp", "topk_device.hpp", "scan_common.hpp"],
-    "scan_topk_grouped": ["fused.hip", "tiles.hpp", "topk_device.hpp", "scan_common.hpp"],
+    "scan_topk_mfma": ["fused.hip", "tiles.hpp", "topk_device.hpp", "scan_common.hpp", "../build.py"],
+    "scan_topk_grouped": ["fused.hip", "tiles.hpp", "topk_device.hpp", "scan_common.hpp", "../build.py"],
 }
 
 
