@@ -432,12 +432,14 @@ bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
     return true;
 }
 
-// Speculation for a whole-database plan of kind 2 or 3: about N / 32 sample
-// rows (16 to 256 chunks), fewer if Q of them would not fit kSpecMaxDists.
+// Speculation for a whole-database plan (any kind: with one or a few
+// queries the tiles would otherwise start without a bound and append a
+// fraction of every tile's rows): about N / 32 sample rows (16 to 256
+// chunks), fewer if Q of them would not fit kSpecMaxDists.
 static void plan_spec(FusedPlan &p, int64_t N, int64_t Q, int k)
 {
     const int mode = bolt::g_spec_mode;
-    if (p.kind < 2 || mode == 0 || N < (mode > 0 ? kSpecMinRowsForced : kSpecMinRows))
+    if (p.kind < 1 || mode == 0 || N < (mode > 0 ? kSpecMinRowsForced : kSpecMinRows))
         return;
     int64_t nsc = N / 32 / kSpecSpan;
     nsc = nsc < 16 ? 16 : (nsc > 256 ? 256 : nsc);

@@ -426,6 +426,39 @@ def test_scan_topk_speculation_parity(bolt, mode, kernel, metric, M, Q, N, k, ki
     assert np.array_equal(i.cpu().numpy(), ir)
 
 
+SPEC_FEW_CASES = [
+    # (M, Q, N, k, lut kind): the one- and few-query kernels from sampled bounds
+    (32, 1, 200_000, 100, "rand"), (16, 1, 131_072, 1, "const"), (64, 3, 150_001, 256, "rand"),
+    (8, 7, 140_000, 10, "coarse"), (32, 2, 300_000, 64, "coarse"),
+]
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("M,Q,N,k,kind", SPEC_FEW_CASES)
+def test_scan_topk_speculation_few_parity(bolt, mode, metric, M, Q, N, k, kind):
+    """Sampled starting bounds with one to seven queries: the result equals
+    the oracle's whether the bounds hold or all fail."""
+    seed = 13 * M + 7 * Q + N + k
+    _say("speculation few mode", mode, metric, kind, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    elif kind == "const":
+        luts = np.full_like(luts, 3)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    bolt.debug_speculation(mode)
+    try:
+        v, i = bolt.bolt_scan_topk(cd, ld, metric, k)
+        torch.cuda.synchronize()
+    finally:
+        bolt.debug_speculation(-1)
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
+
+
 def test_scan_topk_fused_repeatable(bolt):
     """Cross-workgroup bounds depend on timing; the answer must not."""
     M, Q, N, k = 32, 24, 200_000, 100
