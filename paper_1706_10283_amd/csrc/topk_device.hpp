@@ -184,15 +184,38 @@ __device__ __attribute__((noinline)) uint64_t prune_u64(uint64_t *keys, uint32_t
         const uint32_t slot = (uint32_t)(lane + 64 * j);
         key[j] = slot < n ? keys[slot] : ~0ull;
     }
-    uint64_t ans = 0;   // largest t with #(key < t) < k, i.e. the k-th smallest key
-    for (int b = 47; b >= 0; --b) {
-        const uint64_t t = ans | (1ull << b);
-        uint32_t c = 0;
+    // Bits on which all n keys agree are the k-th smallest key's too: the
+    // descent below runs only over the bits where they differ (the high bits
+    // of d and the row bits above the largest row are common).
+    uint64_t o = 0, a = ~0ull;
 #pragma unroll
-        for (int j = 0; j < PER; ++j)
-            c += ballot_count(key[j] < t);
-        if (c < k)
-            ans = t;
+    for (int j = 0; j < PER; ++j)
+        if ((uint32_t)(lane + 64 * j) < n) {
+            o |= key[j];
+            a &= key[j];
+        }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const uint32_t olo = __shfl_xor((uint32_t)o, m), ohi = __shfl_xor((uint32_t)(o >> 32), m);
+        const uint32_t alo = __shfl_xor((uint32_t)a, m), ahi = __shfl_xor((uint32_t)(a >> 32), m);
+        o |= ((uint64_t)ohi << 32) | olo;
+        a &= ((uint64_t)ahi << 32) | alo;
+    }
+    const uint64_t diff = o ^ a;   // nonzero for distinct keys (n > k >= 1)
+    uint64_t ans = a;              // largest t with #(key < t) < k, i.e. the k-th smallest key
+    if (diff) {
+        const int hi = 63 - __builtin_clzll(diff), lo = __builtin_ctzll(diff);
+        ans = a & ~((2ull << hi) - 1);
+        for (int b = hi; b >= lo; --b) {
+            const uint64_t t = ans | (1ull << b);
+            uint32_t c = 0;
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+                c += ballot_count(key[j] < t);
+            if (c < k)
+                ans = t;
+        }
+        ans |= a & ((1ull << lo) - 1);
     }
     uint32_t base = 0;
 #pragma unroll
