@@ -363,12 +363,16 @@ int bolt_learn_quantizer_host(const float *Qt, int64_t nq, int32_t J, int64_t ld
 /*
  * Kernel timing: with bolt_prof_enable(1), every library kernel launch is
  * bracketed by HIP events recorded on its own stream (not inside graph
- * capture).  bolt_prof_read waits for the recorded events and writes
- * "name=launches:milliseconds;" for every kernel name into names (a HOST
- * buffer of cap bytes, NUL-terminated, truncated if short); it returns the
- * full length and, with reset != 0, clears the totals.
+ * capture).  bolt_prof_only(prefix) restricts that to the launches whose
+ * name starts with prefix (a HOST string, copied; NULL or "" times every
+ * launch), so that a timed loop pays the events' stream time only for the
+ * kernels it measures.  bolt_prof_read waits for the recorded events and
+ * writes "name=launches:milliseconds;" for every kernel name into names (a
+ * HOST buffer of cap bytes, NUL-terminated, truncated if short); it returns
+ * the full length and, with reset != 0, clears the totals.
  */
 int bolt_prof_enable(int32_t on);
+int bolt_prof_only(const char *prefix);
 int bolt_prof_read(char *names, size_t cap, int32_t reset);
 
 /*

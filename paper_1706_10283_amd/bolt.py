@@ -490,12 +490,16 @@ class BatchPlan:
 
 _lib.bolt_prof_enable.argtypes = [_I32]
 _lib.bolt_prof_enable.restype = ctypes.c_int
+_lib.bolt_prof_only.argtypes = [ctypes.c_char_p]
+_lib.bolt_prof_only.restype = ctypes.c_int
 _lib.bolt_prof_read.argtypes = [ctypes.c_char_p, _SZ, _I32]
 _lib.bolt_prof_read.restype = ctypes.c_int
 
 
-def prof_enable(on: bool = True):
-    """Record HIP events around every library kernel launch (on its stream)."""
+def prof_enable(on: bool = True, only: str = ""):
+    """Record HIP events around every library kernel launch (on its stream),
+    or only around those whose name starts with `only`."""
+    _lib.bolt_prof_only(only.encode())
     _lib.bolt_prof_enable(1 if on else 0)
 
 

@@ -1,9 +1,12 @@
 // Kernel timing with HIP events, recorded on each kernel's launch stream.
 //
 // When enabled (bolt_prof_enable), every instrumented launch records a start
-// and a stop event around itself; bolt_prof_read waits for the recorded
-// events and returns, per kernel name, the number of launches and their total
-// duration.  Disabled, the instrumentation is a single branch per launch.
+// and a stop event around itself (only launches whose name starts with the
+// prefix given to bolt_prof_only, when one is given: each pair of events
+// costs a few microseconds of stream time); bolt_prof_read waits for the
+// recorded events and returns, per kernel name, the number of launches and
+// their total duration.  Disabled, the instrumentation is a single branch per
+// launch.
 #include <map>
 #include <mutex>
 #include <string>
@@ -20,6 +23,7 @@ struct Pending {
 
 std::mutex g_mu;
 bool g_on = false;
+std::string g_only;   // name prefix of the timed launches (empty: all)
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, std::pair<int64_t, double>> g_totals;   // name -> (launches, ms)
@@ -62,10 +66,12 @@ ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), s_(s), star
 {
     if (!g_on)
         return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_only.empty() && g_only.compare(0, g_only.size(), name, 0, g_only.size()) != 0)
+        return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return;   // no timing inside graph capture
-    std::lock_guard<std::mutex> lk(g_mu);
     start_ = take_event();
     if (start_ && hipEventRecord(reinterpret_cast<hipEvent_t>(start_), s) != hipSuccess)
         start_ = nullptr;
@@ -92,6 +98,13 @@ extern "C" int bolt_prof_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_on = on != 0;
+    return BOLT_OK;
+}
+
+extern "C" int bolt_prof_only(const char *prefix)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_only = prefix ? prefix : "";
     return BOLT_OK;
 }
 
