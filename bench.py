@@ -67,7 +67,7 @@ TRAFFIC = {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
         "fetch_kib": 9889.0,
         "write_kib": 16348.4,
-        "sources_sha256": "90ef5dbab7c13bba3ed8050cc3ca0f2cd8b9758bdc446510c742aa6f0e7cdbfd",
+        "sources_sha256": "cdfc4f2e588764fc16f6a4ef81d5d8c7058916c885d0997a8a2ac978dafd1cd0",
     },
 }
 # the kernel's sources and the build flags (paper_1706_10283_amd/build.py)
@@ -78,11 +78,21 @@ TRAFFIC_SOURCES = {
 
 
 def sources_sha256(kernel):
+    """Hash of the kernel's code: comments and blank lines stripped, so that
+    documentation edits do not invalidate the counters."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_1706_10283_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1706_10283_amd", "csrc", f)) as fh:
+            text = fh.read()
+        if f.endswith(".py"):
+            text = re.sub(r"#[^\n]*", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+        h.update("\n".join(lines).encode())
     return h.hexdigest()
 
 

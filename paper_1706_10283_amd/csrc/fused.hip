@@ -1,21 +1,33 @@
 // Scan fused with top-k selection (Sec. 3.1 scan; Sec. 1.2 the k closest
 // vectors) for gfx950: the [Q][N] sums are never written to memory.
 //
-// Stage 1, one workgroup per (row block of <= 65536 rows, query block): the
-// scan of the grouped (many queries) or few-query kernel computes the sums;
-// each sum is compared with its query's bound and the rare survivors are
-// appended to that query's LDS buffer (see topk_device.hpp).  Between passes
-// of 256 rows the buffers that could overflow are pruned, one wave per query.
-// A pruned bound is also published to the other workgroups with a global
-// atomicMin (any row whose d exceeds a workgroup's k-th smallest d cannot be
-// in the global top-k), and every workgroup folds the published bounds into
-// its own every few passes.  The bounds only decide which rows are kept as
-// candidates, never the result, so the answer is exact and independent of
-// timing.  Each workgroup finally writes its exact local top-k per query.
+// Stage 0 (a whole database of 2^19 rows or more): sampled starting bounds.
+// A sample launch takes the d of every query over chunks of rows at a
+// regular stride on the matrix cores and keeps one minimum per 16 rows; a
+// selection launch gives each query the exact r-th smallest of its minima
+// as its starting bound.
 //
-// Stage 2, one workgroup per query: the row blocks' candidates are merged by
-// the same append-and-prune scheme on 48-bit keys (d << 32 | row) and the k
-// survivors are sorted.
+// Stage 1, one workgroup per (row block, query block): the scan computes
+// the sums (one or a few queries: pair tables in LDS; 32 or more queries:
+// the one-hot codes times the tables on the int8 matrix cores; otherwise,
+// or for k > 128: query-interleaved tables in LDS); each sum is compared with
+// its query's bound and the survivors are appended to that query's LDS
+// buffer.  Without sampled bounds the buffers that could overflow are pruned
+// between passes and a pruned bound is published to the other workgroups
+// with a global atomicMin (any row whose d exceeds a workgroup's k-th
+// smallest d cannot be in the global top-k); with them the matrix-core
+// passes run with no barriers and no atomics (see tiles.hpp).  The bounds
+// only decide which rows are kept as candidates, never the result.  Each
+// workgroup finally writes its exact local top-k per query as packed 48-bit
+// keys (d << 32 | row) with their count, and counts them into a per-query
+// histogram of d.
+//
+// Stage 2: the merge takes per query the keys at or below the bound the
+// histogram gives (the first bin where the count reaches k), in one or two
+// levels, keeps the exact k smallest and sorts them.  A query whose sampled
+// bound failed (fewer than k candidates, or a tile's buffer overflowed) is
+// recomputed exactly by its merging workgroup, so results never depend on
+// the sample, the schedule or the row order.
 //
 // Workgroups of one row block are placed on one XCD (consecutive workgroup
 // ids are dispatched round-robin to the 8 XCDs), so each XCD's L2 holds only
@@ -383,8 +395,8 @@ constexpr int ng_for()
 // of kSpecGroup sample rows: the r-th smallest group minimum still has r
 // distinct sample rows at or below it, so the same tail bounds it, and for
 // small r it rarely differs from the r-th smallest distance.  It is found
-// from a histogram, rounded up to its bin's edge.  The bound only selects
-// candidates: the
+// exactly: a histogram locates its bin, a second count that bin's values.
+// The bound only selects candidates: the
 // final merge flags any query with fewer than k candidates and
 // redo_query recomputes it exactly, so results never depend on it.
 using bolt::kSpecSpan;
