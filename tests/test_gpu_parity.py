@@ -426,6 +426,40 @@ def test_scan_topk_speculation_parity(bolt, mode, kernel, metric, M, Q, N, k, ki
     assert np.array_equal(i.cpu().numpy(), ir)
 
 
+TIE_CASES = [
+    # (M, Q, N, k, lut kind): one merge level with more than 1024 candidate keys
+    # at or below the boundary bin, most of them tied at the k-th sum
+    (8, 40, 200_000, 100, "coarse"), (16, 33, 150_000, 100, "const"), (8, 64, 300_001, 256, "coarse"),
+    (32, 40, 250_000, 128, "const"),
+]
+
+
+@pytest.mark.parametrize("kernel", [2, 3])
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("M,Q,N,k,kind", TIE_CASES)
+def test_scan_topk_crowded_ties_parity(bolt, kernel, metric, M, Q, N, k, kind):
+    """Thousands of keys tied at the k-th sum: the merge bounds the ties by row
+    before it selects; ties still resolve by the lowest row."""
+    seed = 17 * M + 3 * Q + N + k
+    _say("crowded ties kernel", kernel, metric, kind, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    else:
+        luts = np.full_like(luts, 5)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    bolt.debug_force_fused_kind(kernel)
+    try:
+        v, i = bolt.bolt_scan_topk(cd, ld, metric, k)
+        torch.cuda.synchronize()
+    finally:
+        bolt.debug_force_fused_kind(-1)
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
+
+
 SPEC_FEW_CASES = [
     # (M, Q, N, k, lut kind): the one- and few-query kernels from sampled bounds
     (32, 1, 200_000, 100, "rand"), (16, 1, 131_072, 1, "const"), (64, 3, 150_001, 256, "rand"),
