@@ -12,7 +12,8 @@
 // dimension order, the same order the definition fixes, so the fp32 argmin
 // (ties to the lowest index) is reproducible; the expanded form
 // |x|^2 - 2 x.c + |c|^2 would cancel badly.  Codes are gathered per row in
-// LDS and written back as packed bytes with coalesced dword stores.
+// LDS (M bytes per row, dynamic, so that four workgroups fit per CU at
+// M <= 64) and written back as packed bytes with coalesced dword stores.
 #include "common.hpp"
 
 namespace {
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void encode_lds_kernel(
     constexpr int kChunkM = kChunkDims / SUB;
     static_assert(kChunkM % G == 0, "chunk must hold whole lane steps");
     __shared__ __attribute__((aligned(16))) float xs[kRows * kStride];
-    __shared__ uint8_t cs[kRows * 256];
+    extern __shared__ uint8_t cs[];   // [kRows][M]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -134,13 +135,13 @@ __global__ __launch_bounds__(kThreads) void encode_lds_kernel(
                 const int m = m0 + s * G + g;
                 if (m < M) {
                     const float *cm = C + (int64_t)m * bolt::kCentroids * SUB;
-                    cs[lane * 256 + m] = (uint8_t)nearest<SUB>(x + g * SUB, cm);
+                    cs[lane * M + m] = (uint8_t)nearest<SUB>(x + g * SUB, cm);
                 }
             }
         }
     }
     __syncthreads();
-    store_codes(cs, 256, rows, M, codes + n0 * (M >> 1), byte_store);
+    store_codes(cs, M, rows, M, codes + n0 * (M >> 1), byte_store);
 }
 
 // Any subspace width: one thread per (row, subspace pair), reading X and the
@@ -186,8 +187,8 @@ void launch_lds(const float *X, int64_t N, int64_t ldx, const float *C, int M, u
     dim3 grid((unsigned)((N + kRows - 1) / kRows));
     {
         bolt::ProfScope prof_("encode", s);
-        hipLaunchKernelGGL(encode_lds_kernel<SUB>, grid, dim3(kThreads), 0, s, X, N, ldx, C, M, codes,
-                           vec4, byte_store);
+        hipLaunchKernelGGL(encode_lds_kernel<SUB>, grid, dim3(kThreads), (size_t)kRows * M, s, X, N, ldx, C, M,
+                           codes, vec4, byte_store);
     }
 }
 
