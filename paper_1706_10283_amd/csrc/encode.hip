@@ -12,8 +12,10 @@
 // dimension order, the same order the definition fixes, so the fp32 argmin
 // (ties to the lowest index) is reproducible; the expanded form
 // |x|^2 - 2 x.c + |c|^2 would cancel badly.  Codes are gathered per row in
-// LDS (M bytes per row, dynamic, so that four workgroups fit per CU at
-// M <= 64) and written back as packed bytes with coalesced dword stores.
+// LDS (M bytes per row, dynamic) and written back as packed bytes with
+// coalesced dword stores.  Rows are staged 64 dimensions at a time, so a
+// workgroup holds about 19 KB of LDS and 39 registers per lane: eight
+// workgroups per CU keep the VALU busy.
 #include "common.hpp"
 
 namespace {
@@ -21,7 +23,7 @@ namespace {
 constexpr int kRows = 64;                 // rows per tile = lanes per wave
 constexpr int kWaves = 4;
 constexpr int kThreads = kRows * kWaves;
-constexpr int kChunkDims = 128;           // dimensions staged per pass
+constexpr int kChunkDims = 64;            // dimensions staged per pass (17 KB of rows: eight workgroups per CU)
 constexpr int kStride = kChunkDims + 4;   // LDS row stride in floats (4 mod 64 banks)
 
 template <int SUB>
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void encode_lds_kernel(
 {
     constexpr int G = SUB >= 4 ? 1 : 4 / SUB;
     constexpr int kChunkM = kChunkDims / SUB;
-    static_assert(kChunkM % G == 0, "chunk must hold whole lane steps");
+    static_assert(kChunkM >= 1 && kChunkM % G == 0, "chunk must hold whole lane steps");
     __shared__ __attribute__((aligned(16))) float xs[kRows * kStride];
     extern __shared__ uint8_t cs[];   // [kRows][M]
 
