@@ -392,9 +392,10 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
     p->n_tiles = L.n_tiles;
     p->n_queries = L.n_queries;
     p->rows_per_tile = rows;
-    int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;   // the persistent grid's size only: MI355X has 256 CUs
     p->grid = per_cu * cus;
     p->dbs = reinterpret_cast<DevDb *>(p->ws + L.dbs_off);
     p->tiles = reinterpret_cast<DevTile *>(p->ws + L.tiles_off);
@@ -598,8 +599,8 @@ extern "C" int bolt_batch_graph_create(const bolt_batch_plan *p, void **graph_ex
             st = fail(BOLT_ERR_DEVICE, "hipGraphInstantiate failed");
     }
     if (g)
-        hipGraphDestroy(g);
-    hipStreamDestroy(cs);
+        (void)hipGraphDestroy(g);   // cleanup: nothing to do on failure
+    (void)hipStreamDestroy(cs);
     if (st == BOLT_OK)
         *graph_exec = ge;
     return st;
@@ -617,7 +618,7 @@ extern "C" int bolt_batch_graph_launch(void *graph_exec, void *stream)
 
 extern "C" int bolt_batch_graph_destroy(void *graph_exec)
 {
-    if (graph_exec)
-        hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec));
+    if (graph_exec && hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec)) != hipSuccess)
+        return bolt::fail(BOLT_ERR_DEVICE, "hipGraphExecDestroy failed");
     return BOLT_OK;
 }

@@ -52,7 +52,7 @@ __device__ __forceinline__ void emit(uint32_t s, int64_t q, int64_t n, uint16_t 
 // ---------------------------------------------------------------- many queries
 
 template <int MM, int NG, OutMode OUT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void scan_grouped_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MM >= 256 ? 2 : 4))) void scan_grouped_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     int64_t rows_per_block, uint16_t *__restrict__ out, float *__restrict__ outf, int64_t ldo,
     float bias, float scale)
