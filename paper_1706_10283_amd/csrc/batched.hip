@@ -264,13 +264,14 @@ int resolve(const bolt_batch_tuning *tuning, int32_t &rows, int32_t &few_max, in
 bool few_fits(int M, int nq) { return bolt::few_tile_lds_bytes(M, nq) <= kBatchLds; }
 
 // Tile kind of a database: 1 pair tables (few queries), 3 matrix cores
-// (M = 16, 32 or 64, 32 or more queries, k within the tile's candidate
-// buffer), else 2 grouped.
+// (M = 16, 32 or 64, 8 or more queries: a part-filled 32-query tile beats
+// the grouped kernel from 8; k within the tile's candidate buffer), else 2
+// grouped.
 int tile_kind(const bolt_batch_db &d, int few_max)
 {
     if (d.Q <= few_max && few_fits(d.M, d.Q))
         return 1;
-    if (d.M >= 16 && d.Q >= 32 && d.k <= bolt::kMfmaCap - bolt::kMfmaPass)
+    if (d.M >= 16 && d.Q >= 8 && d.k <= bolt::kMfmaCap - bolt::kMfmaPass)
         return 3;
     return 2;
 }

@@ -47,7 +47,8 @@ using bolt::PruneResult;
 using bolt::hist_bound;
 
 constexpr int kRowsPerBlock = 16384;      // rows per workgroup (<= 65536: 16-bit local rows)
-constexpr int64_t kMfmaMinQ = 32;         // queries from which the matrix-core tiles are used
+constexpr int64_t kMfmaMinQ = 8;          // queries from which the matrix-core tiles are used (a part-filled
+                                           // 32-query tile beats the grouped kernel from 8)
 // 32-query tiles per matrix-core workgroup: with one, the tables take half
 // the registers of two and four waves per SIMD fit (beside 33 KB of LDS),
 // which more than pays for reading the one-hot operand once per instruction
