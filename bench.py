@@ -65,9 +65,9 @@ WRITE_FACTOR = 1.0
 TRAFFIC = {
     "scan_topk_mfma": {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 9888.9,
-        "write_kib": 16342.2,
-        "sources_sha256": "cdfc4f2e588764fc16f6a4ef81d5d8c7058916c885d0997a8a2ac978dafd1cd0",
+        "fetch_kib": 9889.2,
+        "write_kib": 16355.1,
+        "sources_sha256": "251852719a6b1a01b84e94eab65669a2d9e11a4b826479425e4b1a77fcd05755",
     },
 }
 # the kernel's sources and the build flags (paper_1706_10283_amd/build.py)
