@@ -616,8 +616,8 @@ def run_serving(args, torch, B, W):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the scan would shard "
-              "by database rows; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU; the library has no multi-GPU path (the scan would shard "
+              "by database rows, each GPU keeping its local top-k, merged after one all-gather)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1706_10283_amd.bolt as B

@@ -50,7 +50,7 @@ typedef enum bolt_status {
     BOLT_OK = 0,
     BOLT_ERR_INVALID = -1,     /* null pointer with size > 0, bad k, bad ld, misalignment */
     BOLT_ERR_SHAPE = -2,       /* J % M != 0, M odd, M outside [2, 256], N too large */
-    BOLT_ERR_UNSUPPORTED = -3, /* a valid request this build does not handle (e.g. k > 2048) */
+    BOLT_ERR_UNSUPPORTED = -3, /* a valid request the library does not handle (e.g. k > 2048) */
     BOLT_ERR_DEVICE = -4,      /* the HIP runtime reported an error */
     BOLT_ERR_NOMEM = -5        /* workspace too small */
 } bolt_status;
