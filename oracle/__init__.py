@@ -11,9 +11,13 @@ compiles it with gcc and marshals numpy arrays.
 Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``):
   encode, subspace_dists_f64, luts, scan, scan_pairs, topk,
   scan_f32, topk_f32, rescale_f64, rescale_f32  pinned
-  kmeans, learn_quantizer                       parity unpinned (the paper
-                                                prints no trained values; only
-                                                invariants are checked)
+  kmeans                                        pinned to scikit-learn's Lloyd
+                                                iterations from the same initial
+                                                rows (the paper prints no trained
+                                                values)
+  learn_quantizer                               pinned to numpy quantiles of the
+                                                expanded sample and the argmin of
+                                                the recomputed grid losses
 """
 from __future__ import annotations
 

@@ -55,8 +55,8 @@ def test_validation_without_gpu(lib):
 
 def test_train_host_matches_oracle_definition(lib):
     """Host trainer of the library vs the oracle's (same definition, written
-    independently).  Training is parity-unpinned; this only guards against the
-    two drifting apart."""
+    independently; the oracle's k-means is pinned to scikit-learn's Lloyd
+    iterations in test_oracle_pins.py)."""
     J, M = 32, 8
     X = synth.normal(201, (3000, J))
     init = synth.permutation_prefix(202, 3000, 16)

@@ -3,9 +3,10 @@ through the C ABI.  The assignment uses the oracle's fp64 operations in its
 order, so on integer-valued data (the Gaussian-mixture workloads: every fp64
 sum is exact) the centroids must be identical bit for bit; on N(0, 1) data
 the parallel fp64 sums may round differently, within the last bit of the
-fp32 mean.  The oracle's k-means itself is parity unpinned (the paper
-prints no trained codebooks): these tests bind the GPU to it, and the
-invariants (non-increasing objective) to the mathematics."""
+fp32 mean.  The paper prints no trained codebooks; the oracle's k-means is
+pinned to scikit-learn's Lloyd iterations (test_oracle_pins.py), and these
+tests bind the GPU to it and to the invariants (non-increasing
+objective)."""
 import numpy as np
 import pytest
 import torch

@@ -337,7 +337,8 @@ def test_amm_error_bound_lemma3_plus_lemma1():
         assert (lhs <= np.linalg.norm(X - xh, axis=1) + 1e-9).all()
 
 
-# ---------------------------------------------------------------- training (parity unpinned; invariants)
+# ---------------------------------------------------------------- training (no trained values in the paper: an
+# independent Lloyd implementation, invariants and numpy quantiles)
 
 def test_kmeans_invariants():
     J, M = 32, 8
@@ -353,6 +354,28 @@ def test_kmeans_invariants():
     init2 = np.arange(0, 16 * 30, 30)
     C2, _ = oracle.kmeans(np.concatenate([pts, pts], 1), 2, 3, init2)
     np.testing.assert_allclose(np.sort(C2[0, :, 0]), np.sort(centers[:, 0]), atol=0.1)
+
+
+def test_kmeans_matches_scikit_learn_lloyd():
+    """Per subspace, the oracle's k-means equals scikit-learn's Lloyd
+    iterations from the same initial rows (an independent implementation of
+    the same algorithm, in fp64): centroids within the fp32 rounding the
+    oracle applies to every mean, and the objective of the final
+    assignment.  Continuous data, no cluster empties on the way."""
+    cluster = pytest.importorskip("sklearn.cluster")
+    J, M, n, iters = 32, 8, 3000, 6
+    X = synth.normal(171, (n, J))
+    init = synth.permutation_prefix(172, n, 16)
+    C, obj = oracle.kmeans(X, M, iters, init)
+    sub = J // M
+    total = 0.0
+    for m in range(M):
+        Xm = X[:, m * sub:(m + 1) * sub].astype(np.float64)
+        km = cluster.KMeans(n_clusters=16, init=Xm[init], n_init=1, max_iter=iters, tol=0.0,
+                            algorithm="lloyd").fit(Xm)
+        np.testing.assert_allclose(C[m], km.cluster_centers_, rtol=1e-5, atol=1e-6)
+        total += km.inertia_
+    assert obj[iters] == pytest.approx(total, rel=1e-6)
 
 
 def test_quantizer_learning_matches_expanded_quantiles():
