@@ -8,9 +8,9 @@
 // as its starting bound.
 //
 // Stage 1, one workgroup per (row block, query block): the scan computes
-// the sums (one or a few queries: pair tables in LDS; 32 or more queries:
-// the one-hot codes times the tables on the int8 matrix cores; otherwise,
-// or for k > 128: query-interleaved tables in LDS); each sum is compared with
+// the sums (one to seven queries: pair tables in LDS; 8 or more queries:
+// the one-hot codes times the tables on the int8 matrix cores; for
+// k > 128: query-interleaved tables in LDS); each sum is compared with
 // its query's bound and the survivors are appended to that query's LDS
 // buffer.  Without sampled bounds the buffers that could overflow are pruned
 // between passes and a pruned bound is published to the other workgroups
