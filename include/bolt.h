@@ -151,14 +151,18 @@ int bolt_topk(const uint16_t *dists, int64_t Q, int64_t N, int64_t ldd, int32_t 
  * Scan followed by top-k without materialising the [Q][N] sums: the same
  * result as bolt_scan_* then bolt_topk with largest = (metric == DOT).
  *
+ *   codes      device uint8 [N][M/2], 16-byte aligned
+ *   luts_u8    device uint8 [Q][M][16], 16-byte aligned
  *   metric     BOLT_METRIC_L2 or BOLT_METRIC_L1 (k smallest), BOLT_METRIC_DOT
  *              (k largest)
  *   ws         device workspace of bolt_scan_topk_ws_bytes(N, M, Q, k) bytes,
- *              256-byte aligned.  The size assumes codes and luts_u8 are
- *              16-byte aligned (M in {8, 16, 32, 64} and k <= 256 then take the
- *              fused path, whose workspace is about Q * N * k / 2048 bytes);
- *              otherwise the call needs Q * N * 2 bytes for the sum matrix
- *              and fails with BOLT_ERR_NOMEM, naming the size, if given less.
+ *              256-byte aligned.  M in {8, 16, 32, 64} with k <= 256 takes the
+ *              fused path (workspace about Q * N * k / 2048 bytes); other M
+ *              or k scan into a [Q][N] sum matrix in the workspace (Q * N * 2
+ *              bytes) and select from it.
+ * Errors: BOLT_ERR_INVALID for misaligned codes or tables (N > 0), a null
+ * pointer, a bad metric or k; BOLT_ERR_NOMEM, naming the size, for a smaller
+ * workspace.
  */
 size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32_t k);
 int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,

@@ -9,8 +9,17 @@ for the definitions and the paper passages they follow); this module only
 compiles it with gcc and marshals numpy arrays.
 
 Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``):
-  encode, subspace_dists_f64, luts, scan, scan_pairs, topk,
-  scan_f32, topk_f32, rescale_f64, rescale_f32  pinned
+  encode              pinned: the fp32 decision (canonical order, ties to the
+                      lowest index) against an exact-rational emulation of
+                      each rounding, and against the fp64 argmin (near ties
+                      only)
+  subspace_dists_f64  pinned: integer-valued inputs against int64 brute force
+                      (exact), continuous inputs against exact rationals
+  luts                pinned: fp64 closed forms; the canonical fp32 order bit
+                      for bit against an exact-rational emulation; uint8 by
+                      the formula in exact arithmetic
+  scan, scan_pairs, topk, scan_f32, topk_f32,
+  rescale_f64, rescale_f32                      pinned
   kmeans                                        pinned to scikit-learn's Lloyd
                                                 iterations from the same initial
                                                 rows (the paper prints no trained

@@ -272,9 +272,6 @@ def bolt_scan_topk(codes, luts_u8, metric, k, vals=None, idx=None, ws=None, stre
     if idx is None:
         idx = torch.empty((Q, k), dtype=torch.int32, device=codes.device)
     nws = bolt_scan_topk_ws_bytes(N, M, Q, k)
-    if (codes.data_ptr() | luts_u8.data_ptr()) % 16:
-        # unaligned operands take the scan-then-select path: room for the sums
-        nws = max(nws, (Q * N * 2 + 255) // 256 * 256)
     if ws is None:
         ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=codes.device)
     wsb = ws.numel() * ws.element_size()

@@ -3,7 +3,7 @@
 // Sec. 1.2).
 //
 // Plan (host): every database is cut into tiles (query block x row block):
-// query blocks of 32 on the int8 matrix cores (M = 16 or 32, 32 or more
+// query blocks of 32 on the int8 matrix cores (M = 16, 32 or 64, 8 or more
 // queries, k <= 128), of 16 (8 for M = 64) on the grouped path, or all of a
 // database's queries on the pair-table path when they are few; row blocks
 // of `rows_per_tile` rows.  Tiles are sorted by decreasing work so that the

@@ -304,8 +304,9 @@ extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const 
         return BOLT_OK;
     if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
         return fail(BOLT_ERR_INVALID, "bolt_scan_topk: null pointer");
-    const bool vec_ok = aligned(codes, 16) && aligned(luts_u8, 16);
-    const size_t need = scan_topk_need(N, M, Q, k, vec_ok);
+    if (N > 0 && !(aligned(codes, 16) && aligned(luts_u8, 16)))
+        return fail(BOLT_ERR_INVALID, "bolt_scan_topk: codes and luts_u8 must be 16-byte aligned");
+    const size_t need = scan_topk_need(N, M, Q, k, true);
     if (ws_bytes < need || (need && !ws))
         return fail(BOLT_ERR_NOMEM, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
     if (need && !aligned(ws, 256))

@@ -43,6 +43,23 @@ import torch
 from . import bolt as B
 
 
+def scan_ws_reserve(rows: int, M: int, q: int, k: int) -> int:
+    """Fused scan + top-k workspace to reserve for a request of q queries.
+
+    Requests are grouped into one call, so the reservation must cover the
+    request's share of any group it can join.  Calls of 8 or more queries run
+    the matrix-core tiles, whose workspace per query is largest at 8 queries
+    and falls slowly after; calls of 1 to 7 run the pair-table kernels, whose
+    workspace per query falls as the call grows.  The larger of the
+    request's own workspace and q times the per-query workspace of an
+    8-query call therefore bounds its share in every group, up to the
+    alignment padding of the workspace's parts, which 64 KiB per request
+    covers."""
+    alone = B.bolt_scan_topk_ws_bytes(rows, M, q, k)
+    per8 = B.bolt_scan_topk_ws_bytes(rows, M, 8, k)
+    return max(alone, -(-q * per8 // 8)) + 65536
+
+
 @dataclass
 class Request:
     rid: int
@@ -86,10 +103,12 @@ class GpuExecutor:
 
     # -- sizes used for admission
     def query_bytes(self, req: Request, rows: int) -> int:
+        """Tables, staging and outputs of the request's queries, plus its share
+        of the scan workspace (scan_ws_reserve)."""
         db = self.dbs[req.db]
         q = req.Qv.shape[0]
-        per_q = B.bolt_scan_topk_ws_bytes(max(rows, 1), db.M, 8, req.k) / 8.0
-        return int(q * (db.J * 4 + db.M * 16 + req.k * 6 + per_q)) + 4096
+        ws = scan_ws_reserve(max(rows, 1), db.M, q, req.k)
+        return int(q * (db.J * 4 + db.M * 16 + req.k * 6) + ws) + 4096
 
     def insert_bytes(self, req: Request) -> int:
         return int(req.X.shape[0] * self.dbs[req.db].J * 4) + 4096
@@ -190,6 +209,19 @@ class Server:
             return "request larger than the whole HBM budget"
         return None
 
+    def _insert_failed(self, r: Request, insert_queue):
+        """An insert whose encode failed after it was enqueued.  Its rows hold
+        no valid codes, so the watermark must never cover them.  If no later
+        insert has reserved rows, the range is handed back; otherwise the
+        failed entry stays at its place in the commit queue and holds the
+        watermark below it (later inserts of that database stay invisible,
+        which keeps every query's snapshot valid)."""
+        q = insert_queue.get(r.db, deque())
+        if r.rows and self.reserved[r.db] == r.rows[1] and q and q[-1] is r:
+            q.pop()
+            self.reserved[r.db] = r.rows[0]
+            r.rows = ()
+
     # ---------------------------------------------------------------- run
     def run(self, requests, realtime: bool = True):
         """Serve `requests` (sorted by arrival).  With realtime, arrivals are
@@ -223,6 +255,11 @@ class Server:
                 r.status = "done"
             except Exception as e:   # a failed request does not stop the server
                 r.status, r.error = "failed", str(e)
+                if r.kind == "insert" and r.rows:
+                    # its rows were never encoded: hand them back (one request
+                    # at a time, so the range is the newest one)
+                    self.reserved[r.db] = r.rows[0]
+                    r.rows = ()
             r.done = self.clock() - t0
         return self.clock() - t0
 
@@ -240,11 +277,20 @@ class Server:
             still = []
             for item in inflight:
                 kind, handle, reqs, fp = item
-                if not self.ex.ready(handle):
-                    still.append(item)
-                    continue
+                try:
+                    if not self.ex.ready(handle):
+                        still.append(item)
+                        continue
+                    err = None
+                except Exception as e:      # the device reported the work as failed
+                    err = str(e)
                 t_done = self.clock() - t0
-                if kind == "query":
+                if err is not None:
+                    for r in reqs:
+                        r.status, r.error, r.done = "failed", err, t_done
+                    if kind == "insert":
+                        self._insert_failed(reqs[0], insert_queue)
+                elif kind == "query":
                     try:
                         for r, (v, i) in zip(reqs, self.ex.query_results(handle)):
                             r.vals, r.idx, r.status, r.done = v, i, "done", t_done
@@ -293,6 +339,10 @@ class Server:
                     except Exception as e:
                         r.status, r.error, r.done = "failed", str(e), self.clock() - t0
                         self.in_use -= fp
+                        # nothing was enqueued and no later insert has reserved
+                        # rows yet: hand the range back
+                        self.reserved[r.db] = row0
+                        r.rows = ()
                         continue
                     insert_queue.setdefault(r.db, deque()).append(r)
                     inflight.append(("insert", h, [r], fp))

@@ -47,6 +47,13 @@ def test_validation_without_gpu(lib):
     assert L.bolt_topk(None, 1, 10, 10, 4096, 0, None, None, None, 0, None) == lib.BOLT_ERR_UNSUPPORTED
     assert L.bolt_scan_l2(None, 10, 8, None, 1, None, 5, None) == lib.BOLT_ERR_INVALID
     assert "ldo" in lib.last_error()
+    # misaligned codes or tables are rejected before anything is enqueued (the
+    # pointers are never dereferenced on the host)
+    P = ctypes.c_void_p
+    for c, t in ((0x10001, 0x20000), (0x10000, 0x20008)):
+        assert L.bolt_scan_topk(P(c), 1000, 32, P(t), 4, 0, 10, P(0x30000), P(0x40000), P(0x50000),
+                                1 << 30, None) == lib.BOLT_ERR_INVALID
+        assert "aligned" in lib.last_error()
     # M = 12 has no fused kernel: room for the [Q][N] sums
     assert lib.bolt_scan_topk_ws_bytes(1000, 12, 10, 100) >= 1000 * 10 * 2
     # M = 32 takes the fused path: candidate buffers only, far below the sums
@@ -68,3 +75,24 @@ def test_train_host_matches_oracle_definition(lib):
         assert ai == aio
         assert a == pytest.approx(ao, rel=1e-5)
         np.testing.assert_allclose(offs, offso, rtol=1e-4, atol=1e-3)
+
+
+def test_serving_workspace_reservation_covers_any_group(lib):
+    """The serving admission reserves scan_ws_reserve(q) per request of q
+    queries; admitted requests of one database run as one call, so the call's
+    workspace must not exceed the sum of its members' reservations.  Checked
+    over the serving shapes (one to 64 queries per request: the few-query,
+    part-filled matrix-core and many-query paths, with and without sampled
+    bounds)."""
+    from paper_1706_10283_amd.serve import scan_ws_reserve
+    rng = np.random.default_rng(7)
+    for N in (60_000, 1_000_000, 250_000_000):
+        for M in (16, 32, 64):
+            for _ in range(60):
+                sizes = rng.integers(1, 65, size=int(rng.integers(1, 7)))
+                if rng.random() < 0.3:
+                    sizes = rng.integers(1, 8, size=int(rng.integers(2, 7)))
+                k = int(rng.choice([10, 100, 128]))
+                group = lib.bolt_scan_topk_ws_bytes(N, M, int(sizes.sum()), k)
+                reserved = sum(scan_ws_reserve(N, M, int(q), k) for q in sizes)
+                assert group <= reserved, (N, M, sizes.tolist(), k, group, reserved)

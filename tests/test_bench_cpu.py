@@ -52,3 +52,38 @@ def test_traffic_only_for_its_workload_and_code(bench, monkeypatch):
     assert bench.traffic_bytes("scan_topk_mfma", dict(wl, Q=wl["Q"] + 1)) is None
     monkeypatch.setitem(bench.TRAFFIC["scan_topk_mfma"], "sources_sha256", "0" * 64)
     assert bench.traffic_bytes("scan_topk_mfma", wl) is None
+
+
+def test_roofline_counts_the_methods_work(bench):
+    """frac is one lookup and one add per (query, vector, subspace) against the
+    dense int8 peak; the one-hot multiply-adds are reported separately and cap
+    the method's fraction at 1/16 for the dense matrix-core kernel."""
+    Q, N, M, ms = 1000, 1_000_000, 32, 0.4
+    r = bench.scan_roofline("scan_topk_mfma", Q, N, M, ms)
+    method = 2.0 * Q * N * M / (ms * 1e-3)
+    assert r["frac"] == pytest.approx(method / 5.0e15, abs=1e-4)
+    assert r["achieved"] == pytest.approx(method / 1e12, rel=1e-3)
+    assert r["dense_equiv_frac"] == pytest.approx(16 * method / 5.0e15, abs=1e-4)
+    assert r["onehot_ceiling_frac"] == pytest.approx(16 * r["frac"], rel=1e-3)
+    assert r["bound"] == "mfma" and r["peak"] == 5000.0
+    g = bench.scan_roofline("scan_topk_grouped", Q, N, M, ms)
+    assert g["frac"] == r["frac"] and "dense_equiv_frac" not in g
+
+
+def test_cpu_baseline_threads_give_the_oracle_result(bench):
+    """The all-thread run of the oracle splits rows and queries among threads
+    and must compute exactly what the one-thread run computes."""
+    import numpy as np
+    import oracle
+    import synth
+    X = synth.gmm_rows(5, 6, 0, 2000, 32)
+    Qv = synth.gmm_rows(5, 7, 0, 37, 32)
+    C, _ = oracle.kmeans(X, 8, 2, synth.permutation_prefix(8, 2000, 16))
+    quant = {m: oracle.learn_quantizer(Qv[:10], oracle.encode(X, C, 8), C, m)[:2] for m in ("l2", "dot")}
+    c1, r1 = bench._oracle_step(oracle, X, C, 8, quant, Qv, 10, 1)
+    c4, r4 = bench._oracle_step(oracle, X, C, 8, quant, Qv, 10, 4)
+    assert np.array_equal(c1, c4)
+    for m in ("l2", "dot"):
+        assert np.array_equal(r1[m][0], r4[m][0]) and np.array_equal(r1[m][1], r4[m][1])
+    model, threads, ncpu = bench.host_cpu()
+    assert isinstance(model, str) and 1 <= threads <= ncpu

@@ -107,10 +107,13 @@ def test_batched_rejects_bad_input(bolt):
 
 
 # databases large enough for speculative bounds under test mode 1 (2^17 rows),
-# with matrix-core tiles (M = 16, 32 or 64, 32 or more queries), beside others
+# with matrix-core tiles (M = 16, 32 or 64, 8 or more queries), beside others
 SPEC_DBS = [
     (32, 140000, 40, 100, "l2", "rand"), (16, 150000, 70, 64, "dot", "coarse"), (32, 131072, 33, 1, "dot", "const"),
     (64, 140000, 40, 100, "l2", "rand"), (16, 20000, 50, 10, "l2", "rand"), (32, 160000, 5, 100, "dot", "rand"),
+    # 8 to 31 queries: one part-filled 32-query matrix-core tile per database
+    (32, 140000, 8, 100, "l2", "rand"), (16, 150000, 9, 64, "dot", "coarse"), (64, 131100, 17, 100, "dot", "rand"),
+    (32, 135000, 31, 128, "l2", "coarse"),
 ]
 
 

@@ -69,19 +69,27 @@ def test_single_database_full_size(bolt, mixture, M):
     C, _ = oracle.kmeans(Xtrain, M, 10, synth.permutation_prefix(synth.seed_for(2, 4), Xtrain.shape[0], 16))
     Cd = torch.from_numpy(C).to(DEV)
 
-    # a1: every code of the million rows
+    # a1: every code of the million rows, bit-exact against the oracle's fp32
+    # decision (the same operations in the same order)
     ref_codes = oracle.encode(Xh, C, M)
     got_codes = bolt.bolt_encode(X, Cd, M).cpu().numpy()
     bad = np.nonzero((got_codes != ref_codes).any(axis=1))[0]
-    print("rows with a code differing from the fp64 argmin: %d of %d" % (len(bad), N1))
-    assert len(bad) <= N1 // 10_000
-    if len(bad):
-        d64 = oracle.subspace_dists_f64(Xh[bad], C, M)
-        gu, ru = _unpack(got_codes[bad], M), _unpack(ref_codes[bad], M)
-        r, m = np.nonzero(gu != ru)
-        best = d64[r, m, ru[r, m]]
-        gap = (d64[r, m, gu[r, m]] - best) / np.maximum(best, np.finfo(np.float32).tiny)
-        assert (gap <= 1e-6).all()
+    print("rows with a code differing from the oracle: %d of %d" % (len(bad), N1))
+    assert len(bad) == 0
+    # separately, the fp64 argmin: the fp32 decision may differ from it only on
+    # near ties (relative gap <= 1e-6), which are counted and reported
+    n_near = 0
+    for lo in range(0, N1, 100_000):
+        d64 = oracle.subspace_dists_f64(Xh[lo:lo + 100_000], C, M)
+        gu = _unpack(got_codes[lo:lo + 100_000], M)
+        best = d64.argmin(-1)
+        r, m = np.nonzero(gu != best)
+        if len(r):
+            b = d64[r, m, best[r, m]]
+            gap = (d64[r, m, gu[r, m]] - b) / np.maximum(b, np.finfo(np.float32).tiny)
+            assert (gap <= 1e-6).all()
+            n_near += len(r)
+    print("codes differing from the fp64 argmin (near ties, gap <= 1e-6): %d of %d" % (n_near, N1 * M))
 
     codes_d = torch.from_numpy(ref_codes).to(DEV)
     sample = synth.permutation_prefix(synth.seed_for(2, 6) + M, Q1, 12)

@@ -394,6 +394,9 @@ SPEC_CASES = [
     # (M, Q, N, k, lut kind)
     (32, 64, 200_000, 100, "rand"), (16, 40, 150_000, 10, "coarse"), (64, 33, 140_000, 128, "rand"),
     (8, 100, 131_072, 1, "const"), (32, 48, 300_001, 256, "rand"), (32, 70, 180_000, 64, "coarse"),
+    # 8 to 31 queries: one part-filled 32-query matrix-core tile is the only query block
+    (32, 8, 140_000, 100, "rand"), (16, 9, 150_000, 64, "coarse"), (64, 17, 131_100, 100, "rand"),
+    (8, 31, 160_000, 128, "coarse"),
 ]
 
 
@@ -489,6 +492,26 @@ def test_scan_topk_speculation_few_parity(bolt, mode, metric, M, Q, N, k, kind):
         torch.cuda.synchronize()
     finally:
         bolt.debug_speculation(-1)
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
+
+
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("M,Q,N,k,kind", [(32, 12, 600_000, 100, "rand"), (16, 31, 524_288, 128, "coarse"),
+                                          (64, 8, 530_000, 100, "rand")])
+def test_scan_topk_default_large_part_filled_tile(bolt, metric, M, Q, N, k, kind):
+    """The automatic path at 2^19 rows or more with 8 to 31 queries: sampled
+    bounds and one part-filled 32-query matrix-core tile (what groups of a
+    served workload mostly take); equal to the oracle."""
+    seed = 19 * M + 3 * Q + N + k
+    _say("default large part-filled tile", metric, kind, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    v, i = bolt.bolt_scan_topk(torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV), metric, k)
+    torch.cuda.synchronize()
     assert np.array_equal(v.cpu().numpy(), vr)
     assert np.array_equal(i.cpu().numpy(), ir)
 

@@ -42,6 +42,48 @@ def _reconstruct(codes_unpacked, C):
     return np.concatenate([C[m][codes_unpacked[:, m]] for m in range(M)], axis=1).astype(np.float64)
 
 
+def _round_f32(x):
+    """Round a rational to the nearest fp32, ties to even (IEEE 754 default
+    rounding), written from the definition: scale so that one unit in the last
+    place is 1, round the integer part, scale back.  Subnormals keep the
+    quantum 2^-149."""
+    x = Fraction(x)
+    if x == 0:
+        return np.float32(0.0)
+    sign = -1 if x < 0 else 1
+    x = abs(x)
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    if Fraction(2) ** e > x:
+        e -= 1
+    e = max(e, -126)
+    q = 23 - e
+    scaled = x * Fraction(2) ** q
+    m = scaled.numerator // scaled.denominator
+    rem = scaled - m
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and m % 2 == 1):
+        m += 1
+    return np.float32(sign * m * 2.0 ** (-q))
+
+
+def _fr(v):
+    return Fraction(float(v))
+
+
+def _canonical_f32_entry(qv, c, metric):
+    """One fp32 table entry by exact rational arithmetic, one correct rounding
+    per step in the canonical order: acc = 0, then for j ascending
+    L2: t = round(q_j - c_j), acc = round(t * t + acc) (one fused rounding);
+    dot: acc = round(q_j * c_j + acc)."""
+    acc = np.float32(0.0)
+    for j in range(len(qv)):
+        if metric == "l2":
+            t = _round_f32(_fr(qv[j]) - _fr(c[j]))
+            acc = _round_f32(_fr(t) * _fr(t) + _fr(acc))
+        else:
+            acc = _round_f32(_fr(qv[j]) * _fr(c[j]) + _fr(acc))
+    return acc
+
+
 # ---------------------------------------------------------------- golden
 
 def test_golden_hand_example():
@@ -148,6 +190,74 @@ def test_encode_m1_is_vector_quantisation():
     assert (got[:, 0] == got[:, 1]).all()
 
 
+def test_round_f32_helper_matches_ieee():
+    """The rational rounding helper used by the pins below agrees with the
+    hardware's round-to-nearest-even conversion from fp64 (numpy), including
+    exact halfway cases and subnormals."""
+    rng = np.random.default_rng(5)
+    vals = list(rng.standard_normal(2000) * 10.0 ** rng.integers(-40, 38, 2000))
+    one = 1.0
+    vals += [one + 2.0 ** -24, one + 3 * 2.0 ** -24, -(one + 2.0 ** -24), 2.0 ** -149, 3 * 2.0 ** -150,
+             2.0 ** -150, 1e-45, 0.0, 16777217.0, 16777219.0]
+    for v in vals:
+        assert _round_f32(Fraction(v)).view(np.uint32) == np.float32(v).view(np.uint32), v
+    # a fused step differs from two roundings: (1 + 2^-12)^2 - 1 - 2^-11 = 2^-24 exactly
+    t = np.float32(1 + 2.0 ** -12)
+    fused = _round_f32(_fr(t) * _fr(t) + _fr(np.float32(-(1 + 2.0 ** -11))))
+    assert fused == np.float32(2.0 ** -24)
+    assert np.float32(t * t) + np.float32(-(1 + 2.0 ** -11)) == np.float32(0.0)
+
+
+def test_encode_fp32_decision_exact():
+    """The encoding decision is taken on fp32 distances in the canonical order
+    (t = x_j - c_j rounded, acc = fma(t, t, acc), j ascending), ties to the
+    lowest index: each distance equals the exact-rational emulation of those
+    roundings bit for bit, and each code is the first index of their minimum.
+    Inputs include exact ties (duplicated centroids) and a subvector equal to a
+    centroid."""
+    N, J, M = 24, 12, 4
+    sub = J // M
+    X = synth.normal(181, (N, J)) * 3
+    C = synth.normal(182, (M, 16, sub)) * 3
+    C[:, 11] = C[:, 6]                                  # exact tie: index 6 must win
+    X[0, :sub] = C[0, 6]
+    codes, d32 = oracle.encode(X, C, M, want_dists=True)
+    got = _unpack(codes, M)
+    for n in range(N):
+        for m in range(M):
+            ref = np.array([_canonical_f32_entry(X[n, m * sub:(m + 1) * sub], C[m, i], "l2")
+                            for i in range(16)], dtype=np.float32)
+            assert np.array_equal(d32[n, m].view(np.uint32), ref.view(np.uint32)), (n, m)
+            assert got[n, m] == int(np.argmin(ref)), (n, m)
+    assert got[0, 0] == 6
+
+
+def test_subspace_dists_f64_pins():
+    """The fp64 subspace distances (the checker of near-tie encodings):
+    on integer-valued inputs every step is exact in fp64, so they equal the
+    int64 brute force exactly; on continuous inputs they are within
+    sub * 2^-52 relative of the exact rational sum; a subvector equal to a
+    centroid has distance 0 there.  A dropped or transposed index, a wrong
+    subspace offset or a missing square fails one of these."""
+    N, J, M = 50, 24, 6
+    sub = J // M
+    Xi = synth.integers(191, -60, 60, (N, J))
+    Ci = synth.integers(192, -60, 60, (M, 16, sub))
+    got = oracle.subspace_dists_f64(Xi.astype(np.float32), Ci.astype(np.float32), M)
+    diff = Xi.astype(np.int64).reshape(N, M, 1, sub) - Ci.astype(np.int64)[None]
+    assert np.array_equal(got, (diff * diff).sum(-1).astype(np.float64))
+    X = synth.normal(193, (8, J))
+    C = synth.normal(194, (M, 16, sub))
+    X[3, 2 * sub:3 * sub] = C[2, 9]
+    got = oracle.subspace_dists_f64(X, C, M)
+    assert got[3, 2, 9] == 0.0
+    for n in range(8):
+        for m in range(M):
+            for i in range(16):
+                exact = sum((_fr(X[n, m * sub + j]) - _fr(C[m, i, j])) ** 2 for j in range(sub))
+                assert abs(Fraction(float(got[n, m, i])) - exact) <= exact * Fraction(sub, 2 ** 52)
+
+
 # ---------------------------------------------------------------- LUTs
 
 @pytest.mark.parametrize("J,M", [(32, 8), (64, 16), (128, 32), (16, 2)])
@@ -186,6 +296,25 @@ def test_lut_l2_dot_identity_and_fp32():
     assert (np.abs(l32 - l64) <= 1e-5 * l64 + 1e-30).all()
     scale = (np.abs(Qv.astype(np.float64).reshape(10, M, 1, sub)) * np.abs(C[None])).sum(-1)
     assert (np.abs(d32 - d64) <= 1e-5 * scale).all()
+
+
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+def test_lut_fp32_canonical_order_exact(metric):
+    """The fp32 tables equal, bit for bit, the exact-rational emulation of the
+    canonical order (acc = 0; j ascending; one rounding for the difference and
+    one per fused multiply-add), the order the GPU tables must reproduce.  A
+    different summation order, separately rounded products or fp64
+    accumulation each change some entries of this input."""
+    J, M, Q = 24, 4, 3
+    sub = J // M
+    Qv = synth.normal(201, (Q, J)) * 7
+    C = synth.normal(202, (M, 16, sub)) * 7
+    _, l32, _ = oracle.luts(Qv, C, M, metric)
+    for q in range(Q):
+        for m in range(M):
+            for i in range(16):
+                ref = _canonical_f32_entry(Qv[q, m * sub:(m + 1) * sub], C[m, i], metric)
+                assert l32[q, m, i].view(np.uint32) == ref.view(np.uint32), (q, m, i)
 
 
 def test_lut_u8_formula_exact():

@@ -27,8 +27,9 @@ class FakeDB:
 class FakeExecutor:
     """Runs the work at launch time; a handle becomes ready after `delay` polls."""
 
-    def __init__(self, dbs, delay=2, fail_on=()):
+    def __init__(self, dbs, delay=2, fail_on=(), fail_ready_on=()):
         self.dbs, self.delay, self.fail_on = dbs, delay, set(fail_on)
+        self.fail_ready_on = set(fail_ready_on)   # launches whose completion reports a device error
         self.launches = []
 
     def query_bytes(self, r, rows):
@@ -53,12 +54,20 @@ class FakeExecutor:
 
     def launch_insert(self, r, row0):
         self.launches.append(("insert", r.db, 1))
+        if len(self.launches) in self.fail_on:
+            raise RuntimeError("injected insert failure")
         db = self.dbs[r.db]
+        if len(self.launches) in self.fail_ready_on:
+            # the encode "fails on the device": its rows keep stale contents
+            db.codes[row0:row0 + r.X.shape[0]] = 0xEE
+            return {"left": self.delay, "fail": True}
         db.codes[row0:row0 + r.X.shape[0]] = oracle.encode(r.X, db.C, db.M)
         return {"left": self.delay}
 
     def ready(self, h):
         h["left"] -= 1
+        if h["left"] < 0 and h.get("fail"):
+            raise RuntimeError("injected device error")
         return h["left"] < 0
 
     def query_results(self, h):
@@ -144,3 +153,59 @@ def test_failure_is_isolated():
     st = [r.status for r in reqs]
     assert st.count("failed") == 1 and st.count("done") == 3
     assert "injected" in [r for r in reqs if r.status == "failed"][0].error
+
+
+def _insert_then_query(dbs, seed):
+    pool = synth.normal(seed, (40, 16))
+    return [Request(0, "insert", 0, 0.0, X=synth.normal(seed + 1, (30, 16))),   # fails
+            Request(1, "insert", 0, 0.0, X=synth.normal(seed + 2, (20, 16))),   # succeeds
+            Request(2, "query", 0, 0.0, k=5, Qv=pool[:3])]
+
+
+@pytest.mark.parametrize("mode", ["continuous", "fifo"])
+def test_failed_insert_rows_never_become_visible(mode):
+    """An insert that fails at launch hands its rows back: the next insert
+    takes them, and no query's snapshot ever covers unencoded rows."""
+    N = 200
+    dbs = [FakeDB(50, N, 1000)]
+    ex = FakeExecutor(dbs, fail_on={1})
+    reqs = _insert_then_query(dbs, 51)
+    srv = Server(ex, dbs, budget_bytes=10 ** 9, mode=mode, max_groups=1)
+    srv.run(reqs, realtime=False)
+    assert [r.status for r in reqs] == ["failed", "done", "done"]
+    assert reqs[0].rows == ()
+    assert reqs[1].rows == (N, N + 20)
+    assert srv.committed[0] == srv.reserved[0] == N + 20
+    q = reqs[2]
+    assert q.watermark in (N, N + 20)
+    db = dbs[0]
+    assert np.array_equal(db.codes[N:N + 20], oracle.encode(reqs[1].X, db.C, db.M))
+    v, i = ex._alone(db, q.Qv, q.metric, q.k, q.watermark)
+    assert np.array_equal(v, q.vals) and np.array_equal(i, q.idx)
+
+
+def test_insert_failing_on_the_device_blocks_the_watermark():
+    """An insert reported failed at completion while a later insert holds the
+    rows after it: the failed rows stay below no watermark, so neither they
+    nor the later rows become visible; a failed newest insert is handed back."""
+    N = 200
+    dbs = [FakeDB(60, N, 1000)]
+    pool = synth.normal(61, (40, 16))
+    ex = FakeExecutor(dbs, delay=3, fail_ready_on={1})
+    reqs = [Request(0, "insert", 0, 0.0, X=synth.normal(62, (30, 16))),     # fails on the device
+            Request(1, "insert", 0, 0.0, X=synth.normal(63, (20, 16))),     # encoded after it
+            Request(2, "query", 0, 0.0, k=5, Qv=pool[:3])]
+    srv = Server(ex, dbs, budget_bytes=10 ** 9, max_groups=1)
+    srv.run(reqs, realtime=False)
+    assert [r.status for r in reqs] == ["failed", "done", "done"]
+    assert srv.committed[0] == N                       # blocked below the failed rows
+    assert reqs[2].watermark == N
+    # the newest range failing is handed back instead
+    dbs = [FakeDB(64, N, 1000)]
+    ex = FakeExecutor(dbs, delay=3, fail_ready_on={2})
+    reqs = [Request(0, "insert", 0, 0.0, X=synth.normal(65, (30, 16))),
+            Request(1, "insert", 0, 0.0, X=synth.normal(66, (20, 16)))]   # fails, newest
+    srv = Server(ex, dbs, budget_bytes=10 ** 9, max_groups=1)
+    srv.run(reqs, realtime=False)
+    assert [r.status for r in reqs] == ["done", "failed"]
+    assert srv.committed[0] == srv.reserved[0] == N + 30
