@@ -168,6 +168,10 @@ def parse():
     p.add_argument("--fifo-requests", type=int, default=100)
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a 1 GiB device-to-device copy (counter calibration for profiles)")
+    p.add_argument("--profile-kernels", default="",
+                   help="instead of the benchmark, run a lean workload for profiler counters: 'headline' "
+                        "(encode, tables, scan + top-k for both metrics, 3 steps) and/or 'single' (one query "
+                        "over 2.5e8 rows at M = 16 and 32, 2 calls per metric), comma-separated")
     return p.parse_args()
 
 
@@ -707,6 +711,72 @@ def run_serving(args, torch, B, W):
     return out
 
 
+def profile_kernels(args, torch, B, W):
+    """A lean workload for profiler counter runs (rocprofv3 --pmc serialises
+    and instruments every dispatch): the kernels of the headline step and of
+    the single-query scan, a few launches each, then a 1 GiB device copy that
+    calibrates the memory counters.  Prints the HIP-event averages."""
+    import synth
+    import synth.device as sdev
+    parts = set(args.profile_kernels.split(","))
+    out = {}
+    if "headline" in parts:
+        N, J, M, Q, k = args.N, args.J, args.M, args.Q, args.k
+        mix = synth.seed_for(2, 0)
+        X = sdev.gmm_rows(mix, synth.seed_for(2, 1), 0, N, J)
+        Qd = sdev.gmm_rows(mix, synth.seed_for(2, 2), 0, Q, J)
+        C, quant = W.train(mix, synth.seed_for(2, 3), synth.seed_for(2, 4), synth.seed_for(2, 5), J, M,
+                           20_000, iters=10)
+        Cd = torch.from_numpy(C).to("cuda")
+        codes = B.bolt_encode(X, Cd, M)
+        luts = {m: _tables(B, torch, Qd, Cd, M, m, quant) for m in ("l2", "dot")}
+        torch.cuda.synchronize()
+        B.prof_read(reset=True)
+        B.prof_enable(True)
+        for _ in range(3):
+            B.bolt_encode(X, Cd, M, codes=codes)
+            for m in ("l2", "dot"):
+                _tables(B, torch, Qd, Cd, M, m, quant)
+                B.bolt_scan_topk(codes, luts[m], m, k)
+        torch.cuda.synchronize()
+        B.prof_enable(False)
+        out["headline"] = {n: {"launches": c, "avg_ms": round(t / c, 5)}
+                           for n, (c, t) in B.prof_read(reset=True).items()}
+        log("profile: headline kernels done")
+        del X, codes
+    if "single" in parts:
+        N, J, k = args.serving_rows, 128, args.k
+        for M in (16, 32):
+            mix = synth.seed_for(5, 0) + 7 * M
+            C, quant = W.train(mix, mix + 3, mix + 4, mix + 5, J, M, n_train=20_000, iters=10)
+            db = W.build_db(mix, mix + 1, N, J, M, C, quant)
+            qv = sdev.gmm_rows(mix, mix + 2, 0, 1, J)
+            torch.cuda.synchronize()
+            log("profile: single-query database M=%d built" % M)
+            B.prof_read(reset=True)
+            B.prof_enable(True)
+            for metric in ("l2", "dot"):
+                luts = db.luts(qv, metric)
+                for _ in range(2):
+                    B.bolt_scan_topk(db.codes[:N], luts, metric, k)
+            torch.cuda.synchronize()
+            B.prof_enable(False)
+            out["single_M%d" % M] = {n: {"launches": c, "avg_ms": round(t / c, 5)}
+                                     for n, (c, t) in B.prof_read(reset=True).items()}
+            del db
+            torch.cuda.empty_cache()
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_kernels": out}), flush=True)
+
+
+def _tables(B, torch, Qd, Cd, M, metric, quant):
+    a, off = quant[metric]
+    return B.bolt_build_luts(Qd, Cd, M, metric, a, torch.from_numpy(off).to("cuda"))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -717,6 +787,9 @@ def main():
     import paper_1706_10283_amd.bolt as B
     from paper_1706_10283_amd import workloads as W
     torch.cuda.set_device(0)
+    if args.profile_kernels:
+        profile_kernels(args, torch, B, W)
+        return
     parts = set(args.parts.split(","))
     res = headline(args, torch, B, W)
     log("headline: %.1f G distances/s, %.3f ms/step" % (res["value"], res["ms_per_step"]))

@@ -17,7 +17,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle_pins.py``
                       (exact), continuous inputs against exact rationals
   luts                pinned: fp64 closed forms; the canonical fp32 order bit
                       for bit against an exact-rational emulation; uint8 by
-                      the formula in exact arithmetic
+                      the formula in exact arithmetic; L_p against L1/L2 at
+                      p = 1, 2, the L_p closed form and an exact-rational
+                      emulation at p = 3; cosine against dot tables of the
+                      unit query and the closed form q.x_hat / |q|
+  normalize_rows      pinned: numpy's IEEE fp32 sqrt and division after the
+                      exact-rational fused sum of squares; unit norm
   scan, scan_pairs, topk, scan_f32, topk_f32,
   rescale_f64, rescale_f32                      pinned
   kmeans                                        pinned to scikit-learn's Lloyd
@@ -42,7 +47,17 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 ALPHAS = np.array([0.0, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1], dtype=np.float64)
-METRICS = {"l2": 0, "dot": 1, "l1": 2}
+METRICS = {"l2": 0, "dot": 1, "l1": 2, "cosine": 4}
+
+
+def _metric(metric):
+    """(code, p) of a metric name: "l2", "dot", "l1", "cosine" or "lp<p>"
+    (the L_p distance to the p, integer p >= 1)."""
+    if metric in METRICS:
+        return METRICS[metric], 0
+    if metric.startswith("lp") and metric[2:].isdigit() and int(metric[2:]) >= 1:
+        return 3, int(metric[2:])
+    raise ValueError("unknown metric %r" % (metric,))
 
 
 def build(force: bool = False) -> str:
@@ -106,9 +121,19 @@ def luts(Qv, C, M, metric="l2", a=1.0, offsets=None):
     l64 = np.zeros((Q, M, 16), dtype=np.float64)
     l32 = np.zeros((Q, M, 16), dtype=np.float32)
     l8 = np.zeros((Q, M, 16), dtype=np.uint8)
-    _load().orc_luts(_p(Qv), I64(Q), I32(J), I64(J), _p(C), I32(M), I32(METRICS[metric]),
+    code, p = _metric(metric)
+    _load().orc_luts(_p(Qv), I64(Q), I32(J), I64(J), _p(C), I32(M), I32(code), I32(p),
                      ctypes.c_float(a), _p(offsets), _p(l64), _p(l32), _p(l8))
     return l64, l32, l8
+
+
+def normalize_rows(X):
+    """Unit-norm rows fp32 [N, J] (cosine similarity); zero rows stay zero."""
+    X = _f32(X)
+    N, J = X.shape
+    Y = np.zeros((N, J), dtype=np.float32)
+    _load().orc_normalize_rows(_p(X), I64(N), I32(J), I64(J), _p(Y), I64(J))
+    return Y
 
 
 def scan(codes, lut8):
@@ -207,8 +232,9 @@ def learn_quantizer(Qt, codes, C, metric="l2", alphas=ALPHAS):
     losses = np.zeros(len(alphas), dtype=np.float64)
     lib = _load()
     lib.orc_learn_quantizer.restype = ctypes.c_int
+    code, p = _metric(metric)
     best = lib.orc_learn_quantizer(_p(Qt), I64(nq), I32(J), I64(J), _p(codes), I64(codes.shape[0]),
-                                   _p(C), I32(M), I32(METRICS[metric]), _p(alphas),
+                                   _p(C), I32(M), I32(code), I32(p), _p(alphas),
                                    I32(len(alphas)), _p(a), _p(offs), _p(losses))
     return float(a[0]), offs, int(best), losses
 

@@ -97,32 +97,68 @@ void orc_subspace_dists_f64(const float *X, int64_t N, int32_t J, int64_t ldx,
 }
 
 /*
+ * Unit-norm rows, for cosine similarity (Sec. 1.1 names it among the
+ * similarities the method serves; with unit vectors it is the dot product):
+ *   s = 0; for j ascending: s = fmaf(x_j, x_j, s);  n = sqrtf(s);
+ *   y_j = x_j / n          (each operation correctly rounded in fp32)
+ * A zero row stays zero.
+ */
+void orc_normalize_rows(const float *X, int64_t N, int32_t J, int64_t ldx, float *Y, int64_t ldy)
+{
+    for (int64_t r = 0; r < N; r++) {
+        const float *x = X + r * ldx;
+        float s = 0.0f;
+        for (int j = 0; j < J; j++)
+            s = fmaf(x[j], x[j], s);
+        float n = sqrtf(s);
+        for (int j = 0; j < J; j++)
+            Y[r * ldy + j] = n > 0.0f ? x[j] / n : 0.0f;
+    }
+}
+
+/*
  * Query encoding g(q) (Sec. 3.1, definition of the matrix D) followed by
  * the learned quantisation beta_m (Sec. 3.2).
  *
- *   D[m][i] = sum over j in p_m of delta(q_j, c_ij)
- *       delta = (q - c)^2 for squared Euclidean (metric 0)
- *       delta = q * c     for the dot product   (metric 1)
- *       delta = |q - c|   for L1, the L_p distance with p = 1 (metric 2;
- *                         eq. distFuncForm with f the identity)
+ *   D[m][i] = sum over j in p_m of delta(q_j, c_ij)   (eq. distFuncForm)
+ *       metric 0, squared Euclidean:  delta = (q - c)^2
+ *       metric 1, dot product:        delta = q * c
+ *       metric 2, L1:                 delta = |q - c|
+ *       metric 3, L_p (integer p):    delta = |q - c|^p, the L_p distance
+ *                                     raised to the p (f the p-th root)
+ *       metric 4, cosine similarity:  delta = (q / |q|) * c, the dot
+ *                                     product with the unit query (the
+ *                                     database side encodes unit rows)
  *
  *   lut64: the entries in fp64 (the "true" table).
  *   lut32: the entries in fp32, canonical order, acc = 0 then j ascending,
  *          L2: t = q_j - c_j; acc = fmaf(t, t, acc)
  *          dot: acc = fmaf(q_j, c_j, acc)
  *          L1:  acc = acc + |q_j - c_j|
+ *          L_p: t = |q_j - c_j|; p = 1: acc = acc + t; p >= 2:
+ *               w = t, then w = w * t (p - 2 times), acc = fmaf(w, t, acc)
+ *               (so L_1 and L_2 give exactly the L1 and L2 tables)
+ *          cosine: u = the unit query (orc_normalize_rows), then as dot
  *   lut8:  beta = max(0, min(255, floor(a*y - b'_m))), with a*y - b'_m
  *          evaluated as one fmaf(a, lut32, -offsets[m]).  offsets[m] is
  *          b'_m = a * F^-1(alpha) for table m, i.e. the offset in
  *          quantised units, so the alpha-quantile maps to 0.
- * Any of the three outputs may be NULL.
+ * Any of the three outputs may be NULL.  p is used by metric 3 only.
  */
 void orc_luts(const float *Qv, int64_t Q, int32_t J, int64_t ldq,
-              const float *C, int32_t M, int32_t metric, float a,
+              const float *C, int32_t M, int32_t metric, int32_t p, float a,
               const float *offsets, double *lut64, float *lut32, uint8_t *lut8)
 {
     int sub = J / M;
-    for (int64_t q = 0; q < Q; q++)
+    float *unit = (float *)malloc(sizeof(float) * (size_t)(J > 0 ? J : 1));
+    for (int64_t q = 0; q < Q; q++) {
+        double qn64 = 0.0;
+        if (metric == 4) {
+            orc_normalize_rows(Qv + q * ldq, 1, J, ldq, unit, J);
+            for (int j = 0; j < J; j++)
+                qn64 += (double)Qv[q * ldq + j] * (double)Qv[q * ldq + j];
+            qn64 = sqrt(qn64);
+        }
         for (int m = 0; m < M; m++)
             for (int i = 0; i < K; i++) {
                 const float *qv = Qv + q * ldq + m * sub;
@@ -138,6 +174,20 @@ void orc_luts(const float *Qv, int64_t Q, int32_t J, int64_t ldq,
                     } else if (metric == 2) {
                         s64 += fabs((double)qv[jj] - (double)c[jj]);
                         s32 = s32 + fabsf(qv[jj] - c[jj]);
+                    } else if (metric == 3) {
+                        s64 += pow(fabs((double)qv[jj] - (double)c[jj]), (double)p);
+                        float t = fabsf(qv[jj] - c[jj]);
+                        if (p == 1) {
+                            s32 = s32 + t;
+                        } else {
+                            float w = t;
+                            for (int e = 2; e < p; e++)
+                                w = w * t;
+                            s32 = fmaf(w, t, s32);
+                        }
+                    } else if (metric == 4) {
+                        s64 += (qn64 > 0.0 ? (double)qv[jj] / qn64 : 0.0) * (double)c[jj];
+                        s32 = fmaf(unit[m * sub + jj], c[jj], s32);
                     } else {
                         s64 += (double)qv[jj] * (double)c[jj];
                         s32 = fmaf(qv[jj], c[jj], s32);
@@ -158,6 +208,8 @@ void orc_luts(const float *Qv, int64_t Q, int32_t J, int64_t ldq,
                     lut8[e] = (uint8_t)f;
                 }
             }
+    }
+    free(unit);
 }
 
 /*
@@ -462,10 +514,9 @@ static double ws_quantile(const wsample *s, int64_t ns, int64_t total, double p)
  */
 int orc_learn_quantizer(const float *Qt, int64_t nq, int32_t J, int64_t ldq,
                         const uint8_t *codes, int64_t n, const float *C, int32_t M,
-                        int32_t metric, const double *alphas, int32_t nalpha,
+                        int32_t metric, int32_t p, const double *alphas, int32_t nalpha,
                         float *a_out, float *offsets_out, double *losses)
 {
-    int sub = J / M;
     int64_t per_table = nq * K;
     int64_t *count = (int64_t *)calloc((size_t)M * K, sizeof(int64_t));
     wsample *y = (wsample *)malloc(sizeof(wsample) * (size_t)(M * per_table));
@@ -475,19 +526,18 @@ int orc_learn_quantizer(const float *Qt, int64_t nq, int32_t J, int64_t ldq,
     for (int64_t r = 0; r < n; r++)
         for (int m = 0; m < M; m++)
             count[m * K + code_of(codes, r, M, m)]++;
-    for (int m = 0; m < M; m++)
-        for (int64_t q = 0; q < nq; q++)
+    double *tab = (double *)malloc(sizeof(double) * (size_t)M * K);
+    for (int64_t q = 0; q < nq; q++) {
+        /* the fp64 table of training query q, as orc_luts defines it */
+        orc_luts(Qt + q * ldq, 1, J, ldq, C, M, metric, p, 1.0f, NULL, tab, NULL, NULL);
+        for (int m = 0; m < M; m++)
             for (int i = 0; i < K; i++) {
-                double s = 0.0;
-                for (int jj = 0; jj < sub; jj++) {
-                    double qv = (double)Qt[q * ldq + m * sub + jj];
-                    double cv = (double)C[((int64_t)m * K + i) * sub + jj];
-                    s += (metric == 0) ? (qv - cv) * (qv - cv) : (metric == 2 ? fabs(qv - cv) : qv * cv);
-                }
                 wsample *e = &y[m * per_table + q * K + i];
-                e->v = s;
+                e->v = tab[m * K + i];
                 e->w = count[m * K + i];
             }
+    }
+    free(tab);
     int64_t total_m = nq * n; /* multiset size of one table */
     for (int m = 0; m < M; m++)
         qsort(y + m * per_table, (size_t)per_table, sizeof(wsample), cmp_ws);

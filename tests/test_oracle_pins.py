@@ -619,3 +619,94 @@ def test_lut_l1_closed_form_and_fp32():
     for j in range(sub):
         ref = ref + np.abs(Qv.reshape(8, M, 1, sub)[..., j] - C[None, :, :, j]).astype(np.float32)
     assert np.array_equal(l32.view(np.uint32), ref.view(np.uint32))
+
+
+# ------------------------------------------------------------------ L_p and cosine tables (eq. distFuncForm)
+
+def test_lut_lp_reduces_to_l1_and_l2_and_closed_form():
+    """L_p tables (|q - c|^p per dimension): p = 1 and p = 2 are the L1 and
+    squared-L2 tables bit for bit (fp32) and equal in fp64; for p = 3 and 4
+    the fp64 entries selected by h(x) sum to ||q - x_hat||_p^p."""
+    J, M = 32, 8
+    X = synth.normal(211, (60, J))
+    Qv = synth.normal(212, (6, J)) * 2
+    C = synth.normal(213, (M, 16, J // M))
+    for p, base in ((1, "l1"), (2, "l2")):
+        a64, a32, _ = oracle.luts(Qv, C, M, "lp%d" % p)
+        b64, b32, _ = oracle.luts(Qv, C, M, base)
+        assert np.array_equal(a32.view(np.uint32), b32.view(np.uint32))
+        np.testing.assert_allclose(a64, b64, rtol=1e-13)
+    cu = _unpack(oracle.encode(X, C, M), M)
+    xh = _reconstruct(cu, C)
+    for p in (3, 4):
+        l64, l32, _ = oracle.luts(Qv, C, M, "lp%d" % p)
+        for q in range(len(Qv)):
+            s = l64[q][np.arange(M)[None, :], cu].sum(1)
+            ref = (np.abs(Qv[q].astype(np.float64)[None] - xh) ** p).sum(1)
+            np.testing.assert_allclose(s, ref, rtol=1e-12)
+        assert (np.abs(l32 - l64) <= 1e-5 * l64 + 1e-30).all()
+
+
+def test_lut_lp3_fp32_order_exact():
+    """The canonical fp32 order of the L_p entries at p = 3, by exact rational
+    arithmetic: t = |round(q - c)|, w = round(t * t), acc = round(w * t + acc)
+    (one fused rounding), j ascending."""
+    J, M, Q = 16, 4, 2
+    sub = J // M
+    Qv = synth.normal(221, (Q, J)) * 3
+    C = synth.normal(222, (M, 16, sub)) * 3
+    _, l32, _ = oracle.luts(Qv, C, M, "lp3")
+    for q in range(Q):
+        for m in range(M):
+            for i in range(16):
+                acc = np.float32(0.0)
+                for j in range(sub):
+                    t = abs(_round_f32(_fr(Qv[q, m * sub + j]) - _fr(C[m, i, j])))
+                    w = _round_f32(_fr(t) * _fr(t))
+                    acc = _round_f32(_fr(w) * _fr(t) + _fr(acc))
+                assert l32[q, m, i].view(np.uint32) == acc.view(np.uint32), (q, m, i)
+
+
+def test_normalize_rows_pins():
+    """Unit rows: the fused sum of squares emulated exactly, then numpy's IEEE
+    fp32 square root and division (correctly rounded, like the oracle's);
+    the result has unit norm to fp32 accuracy and the direction of x; a zero
+    row stays zero."""
+    X = synth.normal(231, (20, 12)) * 5
+    X[7] = 0.0
+    Y = oracle.normalize_rows(X)
+    for r in range(X.shape[0]):
+        s = np.float32(0.0)
+        for j in range(X.shape[1]):
+            s = _round_f32(_fr(X[r, j]) * _fr(X[r, j]) + _fr(s))
+        n = np.sqrt(np.float32(s))
+        ref = (X[r] / n).astype(np.float32) if n > 0 else np.zeros(X.shape[1], np.float32)
+        assert np.array_equal(Y[r].view(np.uint32), ref.view(np.uint32)), r
+    norms = np.linalg.norm(Y.astype(np.float64), axis=1)
+    assert abs(norms[7]) == 0.0
+    np.testing.assert_allclose(np.delete(norms, 7), 1.0, atol=4e-7)
+    cosang = (Y.astype(np.float64) * X).sum(1) / np.maximum(np.linalg.norm(X.astype(np.float64), axis=1), 1e-30)
+    np.testing.assert_allclose(np.delete(cosang, 7), 1.0, atol=1e-6)
+
+
+def test_lut_cosine_is_dot_of_the_unit_query():
+    """Cosine tables are the dot tables of the unit query (bit for bit in
+    fp32), and over h(x) of unit database rows the fp64 entries sum to
+    q . x_hat / |q|, the cosine of q with the reconstruction times |x_hat|."""
+    J, M = 32, 8
+    Qv = synth.normal(241, (7, J)) * 4
+    X = oracle.normalize_rows(synth.normal(242, (80, J)))
+    init = synth.permutation_prefix(243, 80, 16)
+    C, _ = oracle.kmeans(X, M, 3, init)
+    c64, c32, _ = oracle.luts(Qv, C, M, "cosine")
+    _, d32, _ = oracle.luts(oracle.normalize_rows(Qv), C, M, "dot")
+    assert np.array_equal(c32.view(np.uint32), d32.view(np.uint32))
+    cu = _unpack(oracle.encode(X, C, M), M)
+    xh = _reconstruct(cu, C)
+    q64 = Qv.astype(np.float64)
+    for q in range(len(Qv)):
+        s = c64[q][np.arange(M)[None, :], cu].sum(1)
+        ref = xh @ q64[q] / np.linalg.norm(q64[q])
+        np.testing.assert_allclose(s, ref, rtol=1e-12, atol=1e-12)
+        cos = ref / np.linalg.norm(xh, axis=1)
+        assert (np.abs(cos) <= 1 + 1e-12).all()
