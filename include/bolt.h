@@ -56,10 +56,19 @@ typedef enum bolt_status {
 } bolt_status;
 
 /* Table metrics (Sec. 1.1, eq. distFuncForm: a sum over dimensions of a
- * per-dimension term): squared L2 (q - c)^2, dot product q * c, and L1
- * |q - c| (the L_p distance with p = 1).  L2 and L1 retrieve the smallest
- * sums, dot the largest.  Encoding uses squared L2 for all of them. */
-enum { BOLT_METRIC_L2 = 0, BOLT_METRIC_DOT = 1, BOLT_METRIC_L1 = 2 };
+ * per-dimension term; Sec. 1.1 also names cosine similarity):
+ *   BOLT_METRIC_L2      squared L2, (q - c)^2
+ *   BOLT_METRIC_DOT     dot product, q * c
+ *   BOLT_METRIC_L1      L1, |q - c| (the same tables as BOLT_METRIC_LP(1))
+ *   BOLT_METRIC_LP(p)   the L_p distance to the p, |q - c|^p, integer
+ *                       1 <= p <= 16 (BOLT_METRIC_LP(2) gives the L2 tables)
+ *   BOLT_METRIC_COSINE  cosine similarity: the dot product of the unit query
+ *                       q / |q| with codebooks learned on unit database rows
+ *                       (bolt_normalize_rows before bolt_encode)
+ * Distances (L2, L1, L_p) retrieve the smallest sums, similarities (dot,
+ * cosine) the largest.  Encoding uses squared L2 for all of them. */
+enum { BOLT_METRIC_L2 = 0, BOLT_METRIC_DOT = 1, BOLT_METRIC_L1 = 2, BOLT_METRIC_COSINE = 4 };
+#define BOLT_METRIC_LP(p) (3 + 256 * (p))
 
 enum { BOLT_TOPK_MAX_K = 2048 };
 
@@ -89,17 +98,35 @@ int bolt_encode(const float *X, int64_t N, int32_t J, int64_t ldx,
                 const float *centroids, int32_t M, uint8_t *codes, void *stream);
 
 /*
+ * Unit rows for cosine similarity (Sec. 1.1): Y[r] = X[r] / |X[r]| in fp32,
+ *     s = 0; for j ascending: s = fma(x_j, x_j, s);  n = sqrt(s);  y_j = x_j / n
+ * with a correctly rounded square root and division; a zero row stays zero.
+ * The database side of cosine search encodes these rows (bolt_encode) with
+ * codebooks learned on unit rows.
+ *
+ *   X   device fp32 [N][ldx], ldx >= J;   Y  device fp32 [N][ldy], ldy >= J
+ *   (Y may equal X with ldy == ldx: in place)
+ */
+int bolt_normalize_rows(const float *X, int64_t N, int32_t J, int64_t ldx, float *Y, int64_t ldy,
+                        void *stream);
+
+/*
  * Query encoding g with the learned uint8 quantisation (Sec. 3.1,
  * definition of D; Sec. 3.2, beta_m).  For query q, table m, entry i:
  *     D = sum over j in subspace m of delta(q_j, c_ij), in fp32, j ascending,
  *         squared L2: t = q_j - c_ij; acc = fma(t, t, acc)
  *         dot:        acc = fma(q_j, c_ij, acc)
+ *         L1:         acc = acc + |q_j - c_ij|
+ *         L_p:        t = |q_j - c_ij|; p = 1: acc = acc + t; else
+ *                     w = t, p - 2 times w = w * t, then acc = fma(w, t, acc)
+ *         cosine:     u = q / |q| as bolt_normalize_rows computes it, then
+ *                     acc = fma(u_j, c_ij, acc)
  *     beta = clamp(floor(fma(a, D, -offsets[m])), 0, 255)
  * offsets[m] is the table offset in quantised units, b'_m = a * F_m^-1(alpha),
  * so that the learned lower quantile maps to 0 (Sec. 3.2).
  *
  *   Qv         device fp32 [Q][ldq]
- *   metric     BOLT_METRIC_L2, BOLT_METRIC_DOT or BOLT_METRIC_L1
+ *   metric     any of the metric codes above
  *   a          shared scale (> 0), host scalar
  *   offsets    device fp32 [M]
  *   luts_f32   device fp32 [Q][M][16] or NULL (the unquantised D)
@@ -153,8 +180,8 @@ int bolt_topk(const uint16_t *dists, int64_t Q, int64_t N, int64_t ldd, int32_t 
  *
  *   codes      device uint8 [N][M/2], 16-byte aligned
  *   luts_u8    device uint8 [Q][M][16], 16-byte aligned
- *   metric     BOLT_METRIC_L2 or BOLT_METRIC_L1 (k smallest), BOLT_METRIC_DOT
- *              (k largest)
+ *   metric     a distance metric (k smallest) or a similarity (dot, cosine:
+ *              k largest); only the direction depends on it
  *   ws         device workspace of bolt_scan_topk_ws_bytes(N, M, Q, k) bytes,
  *              256-byte aligned.  M in {8, 16, 32, 64} with k <= 256 takes the
  *              fused path (workspace about Q * N * k / 2048 bytes); other M

@@ -25,6 +25,7 @@ BOLT_ERR_NOMEM = -5
 METRIC_L2 = 0
 METRIC_DOT = 1
 METRIC_L1 = 2
+METRIC_COSINE = 4
 TOPK_MAX_K = 2048
 ALPHAS = (0.0, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1)
 
@@ -53,6 +54,7 @@ _SIGS = {
     "bolt_last_error": ([], ctypes.c_char_p),
     "bolt_version": ([], ctypes.c_char_p),
     "bolt_encode": ([_P, _I64, _I32, _I64, _P, _I32, _P, _P], ctypes.c_int),
+    "bolt_normalize_rows": ([_P, _I64, _I32, _I64, _P, _I64, _P], ctypes.c_int),
     "bolt_build_luts": ([_P, _I64, _I32, _I64, _P, _I32, _I32, _F32, _P, _P, _P, _P], ctypes.c_int),
     "bolt_scan_l2": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
     "bolt_scan_dot": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
@@ -132,9 +134,26 @@ def _rows(t, name):
 
 
 def metric_id(metric):
-    if metric in (METRIC_L2, METRIC_DOT, METRIC_L1):
+    """The library's metric code of a name ("l2", "dot", "l1", "cosine" or
+    "lp<p>", the L_p distance to the p) or of a code."""
+    if isinstance(metric, (int, np.integer)):
         return int(metric)
-    return {"l2": METRIC_L2, "dot": METRIC_DOT, "l1": METRIC_L1}[metric]
+    names = {"l2": METRIC_L2, "dot": METRIC_DOT, "l1": METRIC_L1, "cosine": METRIC_COSINE}
+    if metric in names:
+        return names[metric]
+    if metric.startswith("lp") and metric[2:].isdigit():
+        return metric_lp(int(metric[2:]))
+    raise ValueError("unknown metric %r" % (metric,))
+
+
+def metric_lp(p):
+    """Metric code of the L_p distance to the p (bolt.h BOLT_METRIC_LP)."""
+    return 3 + 256 * int(p)
+
+
+def metric_largest(metric):
+    """True for the similarities (dot, cosine), whose top-k takes the largest sums."""
+    return metric_id(metric) in (METRIC_DOT, METRIC_COSINE)
 
 
 # ------------------------------------------------------------------ hot path
@@ -151,6 +170,21 @@ def bolt_encode(X, centroids, M, codes=None, stream=None):
     _dev(codes, torch.uint8, "codes")
     _check(_lib.bolt_encode(_ptr(X), N, J, ldx, _ptr(centroids), M, _ptr(codes), _stream(stream)))
     return codes
+
+
+def bolt_normalize_rows(X, out=None, stream=None):
+    """Unit rows fp32 [N, J] of X [N, J] (cosine similarity); zero rows stay
+    zero.  out may be X itself (in place)."""
+    _dev(X, torch.float32, "X")
+    N, J, ldx = _rows(X, "X")
+    if out is None:
+        out = torch.empty((N, J), dtype=torch.float32, device=X.device)
+    _dev(out, torch.float32, "out")
+    M_, J_, ldy = _rows(out, "out")
+    if (M_, J_) != (N, J):
+        raise ValueError("out must be [N, J]")
+    _check(_lib.bolt_normalize_rows(_ptr(X), N, J, ldx, _ptr(out), ldy, _stream(stream)))
+    return out
 
 
 def bolt_build_luts(Qv, centroids, M, metric, a, offsets, luts_u8=None, luts_f32=None,

@@ -288,8 +288,9 @@ int validate(const bolt_batch_db *dbs, int32_t n_db)
             return bolt::fail(BOLT_ERR_SHAPE, "database %d: bad N or Q", i);
         if (d.k < 1 || d.k > 256)
             return bolt::fail(BOLT_ERR_UNSUPPORTED, "database %d: k must be in [1, 256]", i);
-        if (d.metric != BOLT_METRIC_L2 && d.metric != BOLT_METRIC_DOT && d.metric != BOLT_METRIC_L1)
-            return bolt::fail(BOLT_ERR_INVALID, "database %d: bad metric", i);
+        bolt::Metric mt;
+        if (bolt::decode_metric(d.metric, &mt) != BOLT_OK)
+            return bolt::fail(BOLT_ERR_INVALID, "database %d: bad metric %d", i, d.metric);
         if (d.Q > 0 && (!d.luts || !d.vals || !d.idx || (d.N > 0 && !d.codes)))
             return bolt::fail(BOLT_ERR_INVALID, "database %d: null pointer", i);
         if (!bolt::aligned(d.codes, 16) || !bolt::aligned(d.luts, 16))
@@ -430,7 +431,9 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
         o.M = d.M;
         o.Q = d.Q;
         o.k = d.k;
-        o.largest = d.metric == BOLT_METRIC_DOT;
+        bolt::Metric mt;
+        bolt::decode_metric(d.metric, &mt);   // validated when the plan was made
+        o.largest = mt.largest;
         if (d.Q == 0)
             continue;
         o.n_rb = (d.N + rows - 1) / rows;

@@ -48,6 +48,30 @@ inline int check_N(int64_t N, const char *name)
 
 constexpr int kCentroids = 16;  // K = 16 centroids per codebook (4-bit codes)
 
+// A decoded metric code (bolt.h): kind BOLT_METRIC_L2, _DOT, _L1, 3 (L_p with
+// exponent p) or _COSINE; similarities (dot, cosine) retrieve the largest sums.
+struct Metric {
+    int kind = 0;
+    int p = 0;
+    bool largest = false;
+};
+
+inline int decode_metric(int32_t code, Metric *m)
+{
+    if (code == BOLT_METRIC_L2 || code == BOLT_METRIC_DOT || code == BOLT_METRIC_L1 || code == BOLT_METRIC_COSINE) {
+        m->kind = code;
+        m->p = code == BOLT_METRIC_L1 ? 1 : (code == BOLT_METRIC_L2 ? 2 : 0);
+    } else if (code >= 3 + 256 && (code - 3) % 256 == 0 && (code - 3) / 256 <= 16) {
+        m->kind = 3;
+        m->p = (code - 3) / 256;
+    } else {
+        return fail(BOLT_ERR_INVALID, "unknown metric code %d (0 L2, 1 dot, 2 L1, 4 cosine, 3 + 256 p for L_p "
+                                      "with 1 <= p <= 16)", code);
+    }
+    m->largest = code == BOLT_METRIC_DOT || code == BOLT_METRIC_COSINE;
+    return BOLT_OK;
+}
+
 // Times the launches enqueued during its lifetime on stream s under `name`
 // when timing is enabled (bolt_prof_enable); otherwise does nothing.
 class ProfScope {

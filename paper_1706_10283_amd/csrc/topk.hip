@@ -298,8 +298,8 @@ extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const 
     using namespace bolt;
     BOLT_TRY(check_M(M));
     BOLT_TRY(validate_topk(Q, N, k));
-    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT && metric != BOLT_METRIC_L1)
-        return fail(BOLT_ERR_INVALID, "metric must be 0, 1 or 2 (got %d)", metric);
+    Metric mt;
+    BOLT_TRY(decode_metric(metric, &mt));
     if (Q == 0)
         return BOLT_OK;
     if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
@@ -312,7 +312,7 @@ extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const 
     if (need && !aligned(ws, 256))
         return fail(BOLT_ERR_INVALID, "workspace must be 256-byte aligned");
     hipStream_t s = as_stream(stream);
-    const bool largest = metric == BOLT_METRIC_DOT;
+    const bool largest = mt.largest;
     if (N > 0 && !g_force_unfused_topk) {
         const int st = scan_topk_fused(codes, N, M, luts_u8, Q, k, largest, vals, idx, ws, ws_bytes, s);
         if (st != BOLT_ERR_UNSUPPORTED)
@@ -358,14 +358,14 @@ extern "C" int bolt_scan_topk_ranges(const uint8_t *codes, int64_t N, int32_t M,
     using namespace bolt;
     BOLT_TRY(check_M(M));
     BOLT_TRY(validate_topk(Q, N, k));
-    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT && metric != BOLT_METRIC_L1)
-        return fail(BOLT_ERR_INVALID, "metric must be 0, 1 or 2 (got %d)", metric);
+    Metric mt;
+    BOLT_TRY(decode_metric(metric, &mt));
     BOLT_TRY(validate_ranges(ranges, n_ranges, N));
     if (Q == 0)
         return BOLT_OK;
     if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
         return fail(BOLT_ERR_INVALID, "bolt_scan_topk_ranges: null pointer");
-    return scan_topk_ranges(codes, N, M, luts_u8, Q, k, metric == BOLT_METRIC_DOT, ranges, n_ranges, vals, idx,
+    return scan_topk_ranges(codes, N, M, luts_u8, Q, k, mt.largest, ranges, n_ranges, vals, idx,
                             ws, ws_bytes, as_stream(stream));
 }
 

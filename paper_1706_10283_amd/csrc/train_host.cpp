@@ -138,10 +138,19 @@ struct WeightedSample {
 };
 
 int learn_quantizer(const float *Qt, int64_t nq, int J, int64_t ldq, const uint8_t *codes, int64_t n,
-                    const float *C, int M, int metric, const double *alphas, int nalpha, float *a_out,
+                    const float *C, int M, const bolt::Metric &mt, const double *alphas, int nalpha, float *a_out,
                     float *offsets, int32_t *alpha_idx)
 {
     const int sub = J / M;
+    // per query the fp64 scale of the cosine tables: its norm
+    std::vector<double> qnorm((size_t)nq, 1.0);
+    if (mt.kind == BOLT_METRIC_COSINE)
+        for (int64_t q = 0; q < nq; ++q) {
+            double s = 0.0;
+            for (int j = 0; j < J; ++j)
+                s += (double)Qt[q * ldq + j] * (double)Qt[q * ldq + j];
+            qnorm[q] = std::sqrt(s);
+        }
     // how many training vectors carry each code in each subspace
     std::vector<int64_t> count((size_t)M * K, 0);
     for (int64_t r = 0; r < n; ++r)
@@ -161,8 +170,13 @@ int learn_quantizer(const float *Qt, int64_t nq, int J, int64_t ldq, const uint8
                 for (int j = 0; j < sub; ++j) {
                     const double qv = Qt[q * ldq + (int64_t)m * sub + j];
                     const double cv = C[((int64_t)m * K + i) * sub + j];
-                    d += metric == BOLT_METRIC_L2 ? (qv - cv) * (qv - cv)
-                                                  : (metric == BOLT_METRIC_L1 ? std::fabs(qv - cv) : qv * cv);
+                    switch (mt.kind) {
+                    case BOLT_METRIC_L2: d += (qv - cv) * (qv - cv); break;
+                    case BOLT_METRIC_L1: d += std::fabs(qv - cv); break;
+                    case 3: d += std::pow(std::fabs(qv - cv), (double)mt.p); break;
+                    case BOLT_METRIC_COSINE: d += (qnorm[q] > 0.0 ? qv / qnorm[q] : 0.0) * cv; break;
+                    default: d += qv * cv;
+                    }
                 }
                 ws.s.push_back({d, count[(size_t)m * K + i]});
             }
@@ -251,8 +265,8 @@ extern "C" int bolt_learn_quantizer_host(const float *Qt, int64_t nq, int32_t J,
 {
     using namespace bolt;
     BOLT_TRY(check_JM(J, M));
-    if (metric != BOLT_METRIC_L2 && metric != BOLT_METRIC_DOT && metric != BOLT_METRIC_L1)
-        return fail(BOLT_ERR_INVALID, "metric must be 0 (L2), 1 (dot) or 2 (L1)");
+    Metric mt;
+    BOLT_TRY(decode_metric(metric, &mt));
     if (nq < 1 || n < 1 || nalpha < 1 || ldq < J)
         return fail(BOLT_ERR_INVALID, "need nq >= 1, n >= 1, nalpha >= 1 and ldq >= J");
     if (!Qt || !codes || !centroids || !alphas || !a || !offsets)
@@ -260,7 +274,7 @@ extern "C" int bolt_learn_quantizer_host(const float *Qt, int64_t nq, int32_t J,
     for (int i = 0; i < nalpha; ++i)
         if (!(alphas[i] >= 0.0 && alphas[i] < 0.5))
             return fail(BOLT_ERR_INVALID, "alpha must be in [0, 0.5)");
-    return learn_quantizer(Qt, nq, J, ldq, codes, n, centroids, M, metric, alphas, nalpha, a, offsets,
+    return learn_quantizer(Qt, nq, J, ldq, codes, n, centroids, M, mt, alphas, nalpha, a, offsets,
                            alpha_idx);
 }
 

@@ -47,6 +47,13 @@ def test_validation_without_gpu(lib):
     assert L.bolt_topk(None, 1, 10, 10, 4096, 0, None, None, None, 0, None) == lib.BOLT_ERR_UNSUPPORTED
     assert L.bolt_scan_l2(None, 10, 8, None, 1, None, 5, None) == lib.BOLT_ERR_INVALID
     assert "ldo" in lib.last_error()
+    # metric codes: L_p for 1 <= p <= 16 (3 + 256 p), cosine 4; others rejected
+    for bad in (3, 5, 3 + 256 * 17, -1, 3 + 128):
+        assert L.bolt_build_luts(None, 0, 32, 32, None, 8, bad, 1.0, None, None, None, None) \
+            == lib.BOLT_ERR_INVALID
+    for good in (0, 1, 2, 4, lib.metric_lp(1), lib.metric_lp(16)):
+        assert L.bolt_build_luts(None, 0, 32, 32, None, 8, good, 1.0, None, None, None, None) == lib.BOLT_OK
+    assert lib.metric_id("lp3") == 3 + 256 * 3 and lib.metric_largest("cosine") and not lib.metric_largest("lp2")
     # misaligned codes or tables are rejected before anything is enqueued (the
     # pointers are never dereferenced on the host)
     P = ctypes.c_void_p
@@ -68,7 +75,7 @@ def test_train_host_matches_oracle_definition(lib):
     X = synth.normal(201, (3000, J))
     init = synth.permutation_prefix(202, 3000, 16)
     Qt = X[synth.permutation_prefix(203, 3000, 300)]
-    for metric in ("l2", "dot"):
+    for metric in ("l2", "dot", "lp3", "cosine"):
         C, a, offs, ai = lib.bolt_train_host(X, M, 6, init, Qt, metric)
         Co, ao, offso, aio = oracle.train(X, M, 6, init, Qt, metric)
         np.testing.assert_allclose(C, Co, rtol=1e-5, atol=1e-6)

@@ -103,7 +103,7 @@ def test_encode_gap_report(bolt):
 
 # ------------------------------------------------------------------ tables
 
-@pytest.mark.parametrize("metric", ["l2", "dot", "l1"])
+@pytest.mark.parametrize("metric", ["l2", "dot", "l1", "lp1", "lp2", "lp3", "lp5", "cosine"])
 @pytest.mark.parametrize("Q,J,M", [(1, 32, 8), (17, 128, 32), (100, 64, 16), (5, 256, 16),
                                    (9, 6, 2), (3, 256, 256)])
 def test_luts_parity(bolt, metric, Q, J, M):
@@ -120,12 +120,34 @@ def test_luts_parity(bolt, metric, Q, J, M):
     f32 = f32.cpu().numpy()
     assert np.array_equal(u8.cpu().numpy(), l8)
     assert np.array_equal(f32.view(np.uint32), l32.view(np.uint32))
-    if metric in ("l2", "l1"):
+    if metric not in ("dot", "cosine"):
         assert (np.abs(f32 - l64) <= 1e-5 * l64 + 1e-30).all()
     else:
         sub = J // M
-        scale = (np.abs(Qv.astype(np.float64).reshape(Q, M, 1, sub)) * np.abs(C[None])).sum(-1)
+        Qs = Qv.astype(np.float64)
+        if metric == "cosine":
+            Qs = Qs / np.linalg.norm(Qs, axis=1, keepdims=True)
+        scale = (np.abs(Qs.reshape(Q, M, 1, sub)) * np.abs(C[None])).sum(-1)
         assert (np.abs(f32 - l64) <= 1e-5 * scale).all()
+
+
+@pytest.mark.parametrize("N,J", [(0, 8), (1, 32), (300, 128), (1000, 7), (257, 256)])
+def test_normalize_rows_parity(bolt, N, J):
+    """Unit rows (cosine similarity) bit for bit against the oracle, a zero
+    row included; strided input, separate and in-place output."""
+    _say("normalize rows", "N", N, "J", J)
+    X = synth.normal(N + J, (N, J)) * 7
+    if N > 3:
+        X[3] = 0.0
+    ref = oracle.normalize_rows(X)
+    Xp = torch.zeros((N, J + 5), dtype=torch.float32, device=DEV)
+    Xp[:, :J] = torch.from_numpy(X).to(DEV)
+    got = bolt.bolt_normalize_rows(Xp[:, :J])
+    inplace = torch.from_numpy(X).to(DEV)
+    bolt.bolt_normalize_rows(inplace, out=inplace)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(inplace.cpu().numpy().view(np.uint32), ref.view(np.uint32))
 
 
 # ------------------------------------------------------------------ scan
@@ -213,7 +235,7 @@ def test_topk_constant_rows_and_stride(bolt):
     assert np.array_equal(v.cpu().numpy(), vr) and np.array_equal(i.cpu().numpy(), ir)
 
 
-@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("metric", ["l2", "dot", "lp4", "cosine"])
 @pytest.mark.parametrize("M,Q,k", [(8, 16, 10), (32, 1, 100), (32, 40, 100), (64, 9, 33), (6, 5, 7)])
 def test_scan_topk_parity(bolt, metric, M, Q, k):
     N = 20011
@@ -221,7 +243,7 @@ def test_scan_topk_parity(bolt, metric, M, Q, k):
     _say("scan_topk", metric, "seed", seed, "N", N, "M", M, "Q", Q, "k", k)
     codes = synth.random_codes(seed, N, M)
     luts = (synth.random_luts(seed + 1, Q, M) // 16).astype(np.uint8)   # many ties
-    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric in ("dot", "cosine"))
     v, i = bolt.bolt_scan_topk(torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV),
                                metric, k)
     torch.cuda.synchronize()
@@ -257,12 +279,19 @@ def test_amm_parity(bolt, kernel, transpose, K):
 
 # ------------------------------------------------------------------ end to end
 
-@pytest.mark.parametrize("metric", ["l2", "dot", "l1"])
+@pytest.mark.parametrize("metric", ["l2", "dot", "l1", "lp3", "cosine"])
 def test_end_to_end_tiny_workload(bolt, metric):
     """The tiny workload: 10k x 32 N(0,1), M = 8, 16 queries, top-10, every
-    intermediate equal to the oracle."""
+    intermediate equal to the oracle.  Cosine encodes unit rows (normalised
+    on the GPU and compared with the oracle's) with codebooks learned on
+    them."""
     cfg = synth.configs.TINY
     X = synth.normal(synth.seed_for(1, 1), (cfg.N, cfg.J))
+    Xd = torch.from_numpy(X).to(DEV)
+    if metric == "cosine":
+        X = oracle.normalize_rows(X)
+        Xd = bolt.bolt_normalize_rows(Xd)
+        assert np.array_equal(Xd.cpu().numpy().view(np.uint32), X.view(np.uint32))
     Qv = synth.normal(synth.seed_for(1, 2), (cfg.Q, cfg.J))
     init = synth.permutation_prefix(synth.seed_for(1, 4), cfg.N, 16)
     Qt = X[synth.permutation_prefix(synth.seed_for(1, 5), cfg.N, 1000)]
@@ -270,9 +299,9 @@ def test_end_to_end_tiny_workload(bolt, metric):
     codes_ref = oracle.encode(X, C, cfg.M)
     _, _, l8 = oracle.luts(Qv, C, cfg.M, metric, a, offs)
     S_ref = oracle.scan(codes_ref, l8)
-    vr, ir = oracle.topk(S_ref, cfg.k, metric == "dot")
+    vr, ir = oracle.topk(S_ref, cfg.k, metric in ("dot", "cosine"))
     Cd = torch.from_numpy(C).to(DEV)
-    codes = bolt.bolt_encode(torch.from_numpy(X).to(DEV), Cd, cfg.M)
+    codes = bolt.bolt_encode(Xd, Cd, cfg.M)
     luts = bolt.bolt_build_luts(torch.from_numpy(Qv).to(DEV), Cd, cfg.M, metric, a,
                                 torch.from_numpy(offs).to(DEV))
     v, i = bolt.bolt_scan_topk(codes, luts, metric, cfg.k)
