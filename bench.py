@@ -67,7 +67,7 @@ TRAFFIC = {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
         "fetch_kib": 9889.2,
         "write_kib": 16355.1,
-        "sources_sha256": "251852719a6b1a01b84e94eab65669a2d9e11a4b826479425e4b1a77fcd05755",
+        "sources_sha256": "d5818f1d08013063e93dff76829f15a97f5c0f31c0a01e25c8d6cb46c958e080",
     },
 }
 # the kernel's sources and the build flags (paper_1706_10283_amd/build.py)
@@ -87,7 +87,10 @@ def sources_sha256(kernel):
         with open(os.path.join(ROOT, "paper_1706_10283_amd", "csrc", f)) as fh:
             text = fh.read()
         if f.endswith(".py"):
+            # only the compiler flags of the build script
             text = re.sub(r"#[^\n]*", "", text)
+            text = text[text.index("COMMON_FLAGS = "):]
+            text = text[:text.index("]", text.index("HIP_FLAGS = ")) + 1]
         else:
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
             text = re.sub(r"//[^\n]*", "", text)

@@ -197,6 +197,24 @@ int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *lu
                    void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * bolt_scan_topk for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and result, with the workspace taken from a static
+ * device array of BOLT_NOALLOC_SCRATCH_BYTES bytes that the library holds on
+ * every GPU it runs on until the process ends.  The call allocates nothing.
+ * Inputs and outputs are as for bolt_scan_topk and are still the caller's.
+ * Errors: as bolt_scan_topk, and BOLT_ERR_UNSUPPORTED (naming the size) when
+ * bolt_scan_topk_ws_bytes(N, M, Q, k) exceeds BOLT_NOALLOC_SCRATCH_BYTES.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (several streams or threads) race and must be serialised by the
+ * caller.
+ */
+#define BOLT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int bolt_scan_topk_noalloc(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                           int64_t Q, int32_t metric, int32_t k, uint16_t *vals, int32_t *idx,
+                           void *stream);
+
+/*
  * Scan + top-k over a subset of the rows, as an index produces it (Sec. 1.2:
  * the k closest among the vectors a search visits): the union of n_ranges
  * row ranges [ranges[2r], ranges[2r+1]).  The result is that of
@@ -375,6 +393,39 @@ size_t bolt_kmeans_ws_bytes(int32_t J, int32_t M, int32_t iters);
 int bolt_kmeans(const float *X, int64_t n, int32_t J, int64_t ldx, int32_t M, int32_t iters,
                 const int64_t *init_rows, float *centroids, double *objective, void *ws,
                 size_t ws_bytes, void *stream);
+
+/*
+ * Learning the quantiser on the GPU (Sec. 3.2): the search of
+ * bolt_learn_quantizer_host with the training queries, training codes and
+ * centroids in device memory.  For each alpha of the grid, b_m is the
+ * alpha-quantile of table m's distribution (D_m[i](q) over the training
+ * queries q, weighted by the number of training vectors with code i in
+ * subspace m; fp64 tables), a = 255 / the (1 - alpha)-quantile of y - b_m
+ * pooled over all tables (a = 1 if not positive), b'_m = fp32(fp32(a) b_m),
+ * and the loss is the weighted mean squared reconstruction error; the
+ * smallest loss wins, ties to the smaller alpha.  Quantiles interpolate
+ * linearly between order statistics.  For the chosen alpha, a and b' are the
+ * fp64 operations of the definition in its order (bit-identical to a
+ * sequential evaluation); the losses are summed in parallel order.  L_p
+ * tables take |q - c|^p as repeated fp64 products.
+ *
+ *   Qt         device fp32 [nq][ldq] training queries, 1 <= nq <= 1024
+ *   codes      device uint8 [n][M/2] codes of the n training vectors
+ *   centroids  device fp32 [M][16][J/M]
+ *   alphas     HOST fp64 [nalpha], each in [0, 0.5), 1 <= nalpha <= 64
+ *   a          HOST fp32 (output): the shared scale
+ *   offsets    device fp32 [M] (output): b'_m
+ *   alpha_idx  HOST int32 (output, may be NULL): the chosen grid index
+ *   losses     HOST fp64 [nalpha] (output, may be NULL)
+ *   ws         device workspace of bolt_learn_quantizer_ws_bytes(nq, M, nalpha)
+ *              bytes, 256-byte aligned (0 for unsupported sizes)
+ * The call synchronises the stream before it returns.
+ */
+size_t bolt_learn_quantizer_ws_bytes(int64_t nq, int32_t M, int32_t nalpha);
+int bolt_learn_quantizer(const float *Qt, int64_t nq, int32_t J, int64_t ldq, const uint8_t *codes,
+                         int64_t n, const float *centroids, int32_t M, int32_t metric,
+                         const double *alphas, int32_t nalpha, float *a, float *offsets,
+                         int32_t *alpha_idx, double *losses, void *ws, size_t ws_bytes, void *stream);
 
 int bolt_train_host(const float *X, int64_t n, int32_t J, int64_t ldx, int32_t M,
                     int32_t iters, const int64_t *init_rows, const float *Qt, int64_t nq,

@@ -74,6 +74,9 @@ _SIGS = {
                          _P, _P, _P, _P], ctypes.c_int),
     "bolt_learn_quantizer_host": ([_P, _I64, _I32, _I64, _P, _I64, _P, _I32, _I32, _P, _I32,
                                    _P, _P, _P], ctypes.c_int),
+    "bolt_learn_quantizer_ws_bytes": ([_I64, _I32, _I32], _SZ),
+    "bolt_learn_quantizer": ([_P, _I64, _I32, _I64, _P, _I64, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P,
+                              _SZ, _P], ctypes.c_int),
     "bolt_debug_force_scan_kernel": ([_I32], ctypes.c_int),
     "bolt_debug_force_unfused_topk": ([_I32], ctypes.c_int),
     "bolt_debug_force_fused_kind": ([_I32], ctypes.c_int),
@@ -389,6 +392,30 @@ def bolt_learn_quantizer_host(Qt, codes, centroids, metric, alphas=ALPHAS):
                                           _np_ptr(alphas), len(alphas), _np_ptr(a), _np_ptr(offs),
                                           _np_ptr(ai)))
     return float(a[0]), offs, int(ai[0])
+
+
+def bolt_learn_quantizer(Qt, codes, centroids, metric, alphas=ALPHAS, stream=None):
+    """The quantiser search on the GPU: Qt fp32 [nq, J], codes uint8 [n, M/2]
+    and centroids fp32 [M, 16, J/M] on the device.  Returns (a, offsets fp32
+    [M] on the device, alpha index, losses fp64 [len(alphas)])."""
+    _dev(Qt, torch.float32, "Qt")
+    _dev(codes, torch.uint8, "codes")
+    _dev(centroids, torch.float32, "centroids")
+    nq, J, ldq = _rows(Qt, "Qt")
+    M = centroids.shape[0]
+    alphas = np.ascontiguousarray(alphas, dtype=np.float64)
+    nws = int(_lib.bolt_learn_quantizer_ws_bytes(nq, M, len(alphas)))
+    if nws == 0:
+        raise BoltError(BOLT_ERR_UNSUPPORTED, "unsupported quantiser search size (nq = %d)" % nq)
+    ws = torch.empty(nws, dtype=torch.uint8, device=Qt.device)
+    offs = torch.empty(M, dtype=torch.float32, device=Qt.device)
+    a = np.zeros(1, dtype=np.float32)
+    ai = np.zeros(1, dtype=np.int32)
+    losses = np.zeros(len(alphas), dtype=np.float64)
+    _check(_lib.bolt_learn_quantizer(_ptr(Qt), nq, J, ldq, _ptr(codes), codes.shape[0], _ptr(centroids), M,
+                                     metric_id(metric), _np_ptr(alphas), len(alphas), _np_ptr(a), _ptr(offs),
+                                     _np_ptr(ai), _np_ptr(losses), _ptr(ws), nws, _stream(stream)))
+    return float(a[0]), offs, int(ai[0]), losses
 
 
 def debug_force_unfused_topk(on: bool):

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["errors.cpp", "prof.cpp", "encode.hip", "luts.hip", "scan.hip", "topk.hip", "fused.hip", "few.hip",
-           "nq.hip", "kmeans.hip", "batched.hip", "train_host.cpp"]
+           "nq.hip", "kmeans.hip", "quant.hip", "batched.hip", "train_host.cpp"]
 
 COMMON_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
                 "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]

@@ -11,6 +11,8 @@
 // block-wide prefix sum over contiguous per-thread runs.  The k survivors are
 // sorted by key with a bitonic network in LDS.  One workgroup per row.
 // For the largest-k direction every value v is replaced by 65535 - v.
+#include <mutex>
+
 #include "common.hpp"
 #include "scan_common.hpp"
 
@@ -291,9 +293,75 @@ extern "C" size_t bolt_scan_topk_ws_bytes(int64_t N, int32_t M, int64_t Q, int32
     return scan_topk_need(N, M, Q, k, true);
 }
 
+static int scan_topk_impl(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8, int64_t Q,
+                          int32_t metric, int32_t k, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
+                          void *stream);
+
 extern "C" int bolt_scan_topk(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
                               int64_t Q, int32_t metric, int32_t k, uint16_t *vals, int32_t *idx,
                               void *ws, size_t ws_bytes, void *stream)
+{
+    return scan_topk_impl(codes, N, M, luts_u8, Q, metric, k, vals, idx, ws, ws_bytes, stream);
+}
+
+// The workspace of bolt_scan_topk_noalloc: a file-scope device array, one
+// copy per GPU the library runs on, held until the process ends.  Host code
+// never uses the array's name as an address: the device address of each
+// GPU's copy comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[BOLT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch (set up on its first use).
+int scratch_address(void **out)
+{
+    using namespace bolt;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return fail(BOLT_ERR_DEVICE, "bolt_scan_topk_noalloc: no current device");
+    if (dev >= kMaxDevices)
+        return fail(BOLT_ERR_UNSUPPORTED, "bolt_scan_topk_noalloc: device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(BOLT_ERR_DEVICE, "bolt_scan_topk_noalloc: hipGetSymbolAddress of the scratch failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BOLT_OK;
+}
+}  // namespace
+
+extern "C" int bolt_scan_topk_noalloc(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                                      int64_t Q, int32_t metric, int32_t k, uint16_t *vals, int32_t *idx,
+                                      void *stream)
+{
+    using namespace bolt;
+    BOLT_TRY(check_M(M));
+    BOLT_TRY(validate_topk(Q, N, k));
+    const size_t need = scan_topk_need(N, M, Q, k, true);
+    if (need > (size_t)BOLT_NOALLOC_SCRATCH_BYTES)
+        return fail(BOLT_ERR_UNSUPPORTED,
+                    "bolt_scan_topk_noalloc: this call needs %zu workspace bytes, above the %llu bytes of its "
+                    "static scratch (use bolt_scan_topk with a workspace)",
+                    need, (unsigned long long)BOLT_NOALLOC_SCRATCH_BYTES);
+    if (Q == 0)
+        return scan_topk_impl(codes, N, M, luts_u8, Q, metric, k, vals, idx, nullptr, 0, stream);
+    void *ws = nullptr;
+    BOLT_TRY(scratch_address(&ws));
+    return scan_topk_impl(codes, N, M, luts_u8, Q, metric, k, vals, idx, ws, (size_t)BOLT_NOALLOC_SCRATCH_BYTES,
+                          stream);
+}
+
+static int scan_topk_impl(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8, int64_t Q,
+                          int32_t metric, int32_t k, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
+                          void *stream)
 {
     using namespace bolt;
     BOLT_TRY(check_M(M));

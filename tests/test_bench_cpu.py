@@ -41,10 +41,15 @@ def test_code_hash_ignores_comments_not_code(bench, tmp_path, monkeypatch):
     fused.write_text(text)
     build.write_text(build.read_text().replace('"-munsafe-fp-atomics"', '"-munsafe-fp-atomics", "-g"'))
     assert bench.sources_sha256("scan_topk_mfma") != h0
+    # another source file in the build list is not a change of this kernel's code
+    build.write_text(build.read_text().replace('"-munsafe-fp-atomics", "-g"', '"-munsafe-fp-atomics"')
+                     .replace('"encode.hip",', '"encode.hip", "other.hip",'))
+    assert bench.sources_sha256("scan_topk_mfma") == h0
 
 
 def test_traffic_only_for_its_workload_and_code(bench, monkeypatch):
     t = bench.TRAFFIC["scan_topk_mfma"]
+    monkeypatch.setitem(t, "sources_sha256", bench.sources_sha256("scan_topk_mfma"))
     wl = dict(t["workload"])
     nbytes = bench.traffic_bytes("scan_topk_mfma", wl)
     assert nbytes == pytest.approx(1024.0 * (bench.FETCH_FACTOR * t["fetch_kib"]

@@ -77,3 +77,51 @@ def test_kmeans_errors(bolt):
         bolt.bolt_kmeans(X, 4, 2, np.arange(16) + 90)     # seed row out of range
     with pytest.raises(bolt.BoltError):
         bolt.bolt_kmeans(X, 3, 2, np.arange(16))          # odd M
+
+
+@pytest.mark.parametrize("metric", ["l2", "dot", "l1", "cosine", "lp3"])
+@pytest.mark.parametrize("nq,n,J,M", [(200, 3000, 64, 16), (1000, 20_000, 128, 32), (7, 60, 16, 4),
+                                      (1024, 5000, 32, 8)])
+def test_quantizer_search_matches_oracle(bolt, metric, nq, n, J, M):
+    """The alpha grid search on the GPU (Sec. 3.2) against the oracle's: the
+    same chosen alpha, a and offsets bit for bit (the fp64 operations that
+    decide them are the definition's in its order), losses within the
+    rounding of their parallel sums.  L_p tables use repeated products on
+    the GPU and pow in the oracle: a and offsets within a few fp32 ulp."""
+    _say("quantizer search", metric, "nq", nq, "n", n, "J", J, "M", M)
+    seed = nq + n + J + M
+    X = synth.gmm_rows(synth.seed_for(4, 0), seed, 0, n, J)
+    if metric == "cosine":
+        X = oracle.normalize_rows(X)
+    C, _ = oracle.kmeans(X, M, 3, synth.permutation_prefix(seed + 1, n, 16))
+    codes = oracle.encode(X, C, M)
+    Qt = synth.gmm_rows(synth.seed_for(4, 0), seed + 2, 0, nq, J)
+    a_ref, off_ref, best_ref, loss_ref = oracle.learn_quantizer(Qt, codes, C, metric)
+    a, offs, best, losses = bolt.bolt_learn_quantizer(torch.from_numpy(Qt).to(DEV), torch.from_numpy(codes).to(DEV),
+                                                      torch.from_numpy(C).to(DEV), metric)
+    offs = offs.cpu().numpy()
+    assert best == best_ref
+    np.testing.assert_allclose(losses, loss_ref, rtol=1e-10)
+    if metric == "lp3":
+        np.testing.assert_array_max_ulp(np.float32(a), np.float32(a_ref), maxulp=4)
+        np.testing.assert_allclose(offs, off_ref, rtol=1e-6, atol=1e-3)
+    else:
+        assert np.float32(a).view(np.uint32) == np.float32(a_ref).view(np.uint32)
+        assert np.array_equal(offs.view(np.uint32), off_ref.view(np.uint32))
+
+
+def test_quantizer_search_ties_and_limits(bolt):
+    """Constant tables (every alpha gives the same loss: the smallest alpha
+    wins) and the size limit of 1024 training queries."""
+    J, M, n = 16, 4, 100
+    C = np.ones((M, 16, J // M), dtype=np.float32)
+    codes = np.zeros((n, M // 2), dtype=np.uint8)
+    Qt = np.ones((30, J), dtype=np.float32)
+    a_ref, off_ref, best_ref, _ = oracle.learn_quantizer(Qt, codes, C, "l2")
+    a, offs, best, _ = bolt.bolt_learn_quantizer(torch.from_numpy(Qt).to(DEV), torch.from_numpy(codes).to(DEV),
+                                                 torch.from_numpy(C).to(DEV), "l2")
+    assert best == best_ref == 0
+    assert np.float32(a) == np.float32(a_ref) and np.array_equal(offs.cpu().numpy(), off_ref)
+    with pytest.raises(bolt.BoltError):
+        bolt.bolt_learn_quantizer(torch.zeros((1025, J), device=DEV), torch.from_numpy(codes).to(DEV),
+                                  torch.from_numpy(C).to(DEV), "l2")
