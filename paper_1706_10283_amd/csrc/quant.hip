@@ -46,10 +46,11 @@ struct Alphas {
 
 inline size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Entries per table, padded to a power of two for the bitonic sort.
+// Entries per table, padded to a power of two for the bitonic sort, at
+// least one per sorting thread.
 int64_t sort_size(int64_t nq)
 {
-    int64_t s = 256;
+    int64_t s = kSortThreads;
     while (s < nq * kK)
         s *= 2;
     return s;
