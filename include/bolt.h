@@ -476,6 +476,13 @@ int bolt_debug_force_fused_kind(int32_t kind);
  * exact recomputation).  Results are the same in every mode.
  */
 int bolt_debug_speculation(int32_t mode);
+/*
+ * Test hook: the int8 matrix-core tiles contract the one-hot codes with the
+ * sparse instruction (on != 0, the default: four subspaces per instruction
+ * from a 4:2-structured operand) or the dense one (two subspaces per
+ * instruction).  Results are the same either way.
+ */
+int bolt_debug_sparse_mfma(int32_t on);
 
 #ifdef __cplusplus
 }

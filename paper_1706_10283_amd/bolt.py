@@ -81,6 +81,7 @@ _SIGS = {
     "bolt_debug_force_unfused_topk": ([_I32], ctypes.c_int),
     "bolt_debug_force_fused_kind": ([_I32], ctypes.c_int),
     "bolt_debug_speculation": ([_I32], ctypes.c_int),
+    "bolt_debug_sparse_mfma": ([_I32], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -431,6 +432,11 @@ def debug_force_fused_kind(kind: int):
 def debug_speculation(mode: int):
     """Test hook: speculative bounds, -1 automatic, 0 off, 1 on, 2 on and failing."""
     _check(_lib.bolt_debug_speculation(mode))
+
+
+def debug_sparse_mfma(on: bool):
+    """Test hook: matrix-core tiles with the sparse (True, default) or the dense instruction."""
+    _check(_lib.bolt_debug_sparse_mfma(1 if on else 0))
 
 
 def debug_force_scan_kernel(kind: int):

@@ -15,7 +15,9 @@
 // persistent kernel (a few workgroups per CU) pulls the matrix-core tiles
 // from one counter and a second one the other tiles from another, each
 // until it passes its tile count, so every wave exits; a merge kernel then
-// turns each query's candidate lists into its sorted top k.  The launches
+// turns each query's candidate lists into its sorted top k, and a
+// persistent recomputation kernel redoes, on the whole GPU, any query whose
+// sampled bound failed (its workgroups exit at once when none did).  The launches
 // depend only on the plan, so they can be captured once in a HIP graph and
 // replayed with new query tables in place.  Results are
 // bit-identical to bolt_scan_topk on each database alone: the sums are exact
@@ -77,11 +79,15 @@ struct DevQuery {
 // few-query tile of at most this many bytes.
 constexpr size_t kBatchLds = 49664;
 
+// Workgroups of the persistent recomputation launch (the number of listed
+// queries is known only on the device).
+constexpr int64_t kRedoGrid = 1024;
+
 __global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, uint32_t *fail, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < 3)
-        counter[i] = 0;   // matrix-core tiles (M = 16, 32), other tiles, matrix-core tiles (M = 64)
+    if (i < 4)   // matrix-core tiles (M = 16, 32), other tiles, matrix-core tiles (M = 64), recomputation list
+        counter[i] = 0;
     if (i < n) {
         gthr[i] = 0xFFFFu;
         fail[i] = 0u;
@@ -108,9 +114,9 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     if (MF) {
         // sampled bounds: barrier-free passes (overflow flags the query)
         if (db.sdist)
-            bolt::mfma_tile<MM, 1, true>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
+            bolt::mfma_tile<MM, 1, true, true>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
         else
-            bolt::mfma_tile<MM, 1, false>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
+            bolt::mfma_tile<MM, 1, false, true>(job, *reinterpret_cast<bolt::MfmaLds<1> *>(lds));
     } else if (t.kind == 1) {
         bolt::few_tile<MM, false>(job, lds);
     } else {
@@ -171,20 +177,20 @@ __global__ __launch_bounds__(256) void batch_scan_kernel(const DevDb *__restrict
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_sample_kernel(
     const DevDb *__restrict__ dbs, const DevSample *__restrict__ items)
 {
-    __shared__ uint4 onehot[16];
+    __shared__ bolt::OneHot onehot;
     __shared__ __attribute__((aligned(16))) uint16_t gmin[32 * bolt::kSpecGminStride];
     const DevSample it = items[blockIdx.x];
     const DevDb db = dbs[it.db];
     const int nq = (db.Q - it.q0) < 32 ? (db.Q - it.q0) : 32;
     const int64_t r0 = (int64_t)it.chunk * db.stride, g0 = (int64_t)it.chunk * bolt::kSpecGroups;
     if (db.M == 16)
-        bolt::mfma_sample_tile<16, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
+        bolt::mfma_sample_tile<16, 1, true>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
                                       gmin);
     else if (db.M == 32)
-        bolt::mfma_sample_tile<32, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
+        bolt::mfma_sample_tile<32, 1, true>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
                                       gmin);
     else
-        bolt::mfma_sample_tile<64, 1>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
+        bolt::mfma_sample_tile<64, 1, true>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
                                       gmin);
 }
 
@@ -205,11 +211,15 @@ __global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restri
         db.gthr[qq.q] = force_fail ? 0u : b;
 }
 
-// Top k of one query from its candidate lists; a query of a speculative
+// Top k of one query from its candidate lists.  A query of a speculative
 // database with fewer than k candidates, or flagged by an overflowing
-// barrier-free tile, is recomputed exactly.
+// barrier-free tile, is listed for the exact recomputation instead: its
+// bound is opened, its flag becomes the count of its recomputed tiles, and
+// its index into `queries` is appended to redo (count in *redo_cnt).
 __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restrict__ dbs,
-                                                          const DevQuery *__restrict__ queries)
+                                                          const DevQuery *__restrict__ queries,
+                                                          uint32_t *__restrict__ redo_cnt,
+                                                          uint32_t *__restrict__ redo)
 {
     __shared__ bolt::MergeLds L;
     const DevQuery qq = queries[blockIdx.x];
@@ -218,18 +228,84 @@ __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restric
     const uint32_t k = (uint32_t)db.k;
     const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k, db.gthr[qq.q]);
     if (db.sdist && (n < k || db.fail[qq.q])) {
-        bolt::redo_query(L, db.codes, db.N, db.M, db.luts, qq.q, k, db.largest, db.vals, db.idx);
+        if (threadIdx.x == 0) {
+            db.gthr[qq.q] = 0xFFFFu;
+            db.fail[qq.q] = 0u;
+            redo[atomicAdd(redo_cnt, 1u)] = blockIdx.x;
+        }
         return;
     }
     bolt::merge_emit(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
                      db.idx + (int64_t)qq.q * db.k);
 }
 
+// Exact recomputation of the listed queries on the whole GPU: item i of the
+// persistent loop is (listed query i / max_rb, row block i % max_rb), a
+// one-query tile from the open bound over that row block of the query's
+// database (items past the database's row blocks are skipped), writing its
+// local top k to the query's own candidate slot (free since the merge).  The
+// workgroup that completes a query's last row block (the count in its flag)
+// merges the query's slots below the published bound and writes the result.
+__global__ __launch_bounds__(256) void batch_redo_kernel(const DevDb *__restrict__ dbs,
+                                                         const DevQuery *__restrict__ queries,
+                                                         const uint32_t *__restrict__ redo_cnt,
+                                                         const uint32_t *__restrict__ redo, int64_t max_rb,
+                                                         int64_t rows_per_tile)
+{
+    __shared__ __attribute__((aligned(16))) char lds[bolt::few_tile_lds_bytes(64, 1)];
+    __shared__ bolt::MergeLds L;
+    __shared__ uint32_t s_last;
+    const int tid = threadIdx.x;
+    const int64_t items = (int64_t)*redo_cnt * max_rb;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const DevQuery qq = queries[redo[it / max_rb]];
+        const DevDb db = dbs[qq.db];
+        const int64_t rb = it % max_rb;
+        if (rb >= db.n_rb)
+            continue;   // uniform across the workgroup
+        bolt::TileJob job;
+        job.codes = db.codes;
+        job.luts = db.luts;
+        job.cand = db.cand;
+        job.gthr = db.gthr;
+        job.rb = rb;
+        job.r0 = rb * rows_per_tile;
+        job.r1 = (job.r0 + rows_per_tile) < db.N ? (job.r0 + rows_per_tile) : db.N;
+        job.n_rb = db.n_rb;
+        job.q0 = qq.q;
+        job.nq = 1;
+        job.k = (uint32_t)db.k;
+        job.largest = db.largest;
+        switch (db.M) {
+        case 8: bolt::few_tile<8, true>(job, lds); break;
+        case 16: bolt::few_tile<16, true>(job, lds); break;
+        case 32: bolt::few_tile<32, true>(job, lds); break;
+        default: bolt::few_tile<64, true>(job, lds); break;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();   // this tile's keys before its completion
+            s_last = atomicAdd(&db.fail[qq.q], 1u) == (uint32_t)(db.n_rb - 1) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();   // every tile's keys of the query after their completions
+            const int64_t per_query = db.n_rb * db.k;
+            const uint32_t k = (uint32_t)db.k;
+            const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k,
+                                                   bolt::read_bound(&db.gthr[qq.q]));
+            bolt::merge_emit(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
+                             db.idx + (int64_t)qq.q * db.k);
+        }
+        __syncthreads();
+    }
+}
+
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    size_t dbs_off, tiles_off, queries_off, gthr_off, fail_off, counter_off, samples_off, cand_off, total;
-    int64_t n_tiles, n_queries, n_samples;
+    size_t dbs_off, tiles_off, queries_off, gthr_off, fail_off, redo_off, counter_off, samples_off, cand_off, total;
+    int64_t n_tiles, n_queries, n_samples, max_rb;
 };
 
 // Speculative bounds of a matrix-core database (as the one-database path
@@ -302,7 +378,7 @@ int validate(const bolt_batch_db *dbs, int32_t n_db)
 Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t few_max)
 {
     Layout L{};
-    int64_t tiles = 0, queries = 0, samples = 0;
+    int64_t tiles = 0, queries = 0, samples = 0, max_rb = 0;
     size_t cand = 0;
     for (int i = 0; i < n_db; ++i) {
         const bolt_batch_db &d = dbs[i];
@@ -317,6 +393,7 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
         cand += align256((size_t)d.Q * n_rb * d.k * sizeof(uint64_t));
         const int64_t nsc = spec_chunks(d, kind);
         if (nsc) {
+            max_rb = n_rb > max_rb ? n_rb : max_rb;
             samples += (d.Q + 31) / 32 * nsc;
             cand += align256((size_t)d.Q * nsc * bolt::kSpecGroups * sizeof(uint16_t));
         }
@@ -324,6 +401,7 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
     L.n_tiles = tiles;
     L.n_queries = queries;
     L.n_samples = samples;
+    L.max_rb = max_rb;
     size_t off = 0;
     L.dbs_off = off;
     off += align256(sizeof(DevDb) * (size_t)(n_db > 0 ? n_db : 1));
@@ -334,6 +412,8 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
     L.gthr_off = off;
     off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
     L.fail_off = off;
+    off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
+    L.redo_off = off;
     off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
     L.counter_off = off;
     off += 256;
@@ -353,6 +433,7 @@ struct bolt_batch_plan {
     int64_t n_mfma = 0;     // the first n_mfma tiles are matrix-core tiles of M = 16 and 32,
     int64_t n_mfma64 = 0;   // the next n_mfma64 those of M = 64
     int64_t n_samples = 0;
+    int64_t max_rb = 0;     // most row blocks of a speculative database (recomputation items per query)
     int32_t rows_per_tile = 0, grid = 0;
     std::vector<char> host;   // staged descriptors (kept until the plan is destroyed)
     DevDb *dbs = nullptr;
@@ -360,6 +441,7 @@ struct bolt_batch_plan {
     DevQuery *queries = nullptr;
     uint32_t *gthr = nullptr;
     uint32_t *fail = nullptr;
+    uint32_t *redo = nullptr;      // queries listed for the recomputation (count in counter[3])
     uint32_t *counter = nullptr;
     DevSample *samples = nullptr;
 };
@@ -404,6 +486,8 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
     p->queries = reinterpret_cast<DevQuery *>(p->ws + L.queries_off);
     p->gthr = reinterpret_cast<uint32_t *>(p->ws + L.gthr_off);
     p->fail = reinterpret_cast<uint32_t *>(p->ws + L.fail_off);
+    p->redo = reinterpret_cast<uint32_t *>(p->ws + L.redo_off);
+    p->max_rb = L.max_rb;
     p->counter = reinterpret_cast<uint32_t *>(p->ws + L.counter_off);
     p->samples = reinterpret_cast<DevSample *>(p->ws + L.samples_off);
     p->n_samples = L.n_samples;
@@ -552,7 +636,14 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
     {
         bolt::ProfScope prof_("batch_merge", s);
         hipLaunchKernelGGL(batch_merge_kernel, dim3((unsigned)p->n_queries), dim3(256), 0, s, p->dbs,
-                           p->queries);
+                           p->queries, p->counter + 3, p->redo);
+    }
+    if (p->n_samples > 0) {   // recomputation of failed sampled bounds (none: every workgroup exits at once)
+        bolt::ProfScope prof_("batch_redo", s);
+        const int64_t items = p->max_rb * p->n_queries;
+        hipLaunchKernelGGL(batch_redo_kernel, dim3((unsigned)(items < kRedoGrid ? items : kRedoGrid)), dim3(256),
+                           0, s, p->dbs, p->queries, p->counter + 3, p->redo, p->max_rb,
+                           (int64_t)p->rows_per_tile);
     }
     return check_launch("bolt_batch_run");
 }

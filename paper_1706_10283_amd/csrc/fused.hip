@@ -26,8 +26,14 @@
 // histogram gives (the first bin where the count reaches k), in one or two
 // levels, keeps the exact k smallest and sorts them.  A query whose sampled
 // bound failed (fewer than k candidates, or a tile's buffer overflowed) is
-// recomputed exactly by its merging workgroup, so results never depend on
-// the sample, the schedule or the row order.
+// put on a list instead, and stage 3 recomputes it exactly on the whole GPU,
+// so results never depend on the sample, the schedule or the row order.
+//
+// Stage 3 (with sampled bounds; always launched, its workgroups exit at
+// once when the list is empty): every (listed query, tile) pair is scanned
+// again from an open bound by a one-query tile, over the workgroups of one
+// persistent grid, and the workgroup that finishes a query's last tile
+// merges that query's tiles and writes its result.
 //
 // Workgroups of one row block are placed on one XCD (consecutive workgroup
 // ids are dispatched round-robin to the 8 XCDs), so each XCD's L2 holds only
@@ -114,8 +120,9 @@ __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
 }
 
 // Matrix-core tiles: 32 NT queries per workgroup (tables in registers);
-// FREE: barrier-free passes under speculative bounds (see mfma_tile).
-template <int MM, int NT, bool FREE>
+// FREE: barrier-free passes under speculative bounds (see mfma_tile); SP:
+// the sparse matrix instruction.
+template <int MM, int NT, bool FREE, bool SP>
 __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
@@ -126,10 +133,24 @@ __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
     bolt::TileJob job;
     if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
                  bolt::hist_shift(MM), fail, gthr, tiles, stride, span, job))
-        bolt::mfma_tile<MM, NT, FREE>(job, L);
+        bolt::mfma_tile<MM, NT, FREE, SP>(job, L);
 }
 
 // ------------------------------------------------------------------ merge
+
+// Lists query q for the exact recomputation (stage 3): its bound is opened
+// (every d passes), its overflow flag becomes the count of its recomputed
+// tiles, and q is appended to redo[2 ...] (redo[0] counts the list).  Called
+// by the one workgroup that finishes the query's merge.
+__device__ void flag_redo(int64_t q, uint32_t *gthr, uint32_t *fail, uint32_t *redo)
+{
+    if (threadIdx.x == 0) {
+        gthr[q] = 0xFFFFu;
+        fail[q] = 0u;
+        const uint32_t pos = atomicAdd(&redo[0], 1u);
+        redo[2 + pos] = (uint32_t)q;
+    }
+}
 
 
 // Appends to L every key below L.mbound from slots [s_lo, s_hi) (slot s:
@@ -207,8 +228,8 @@ __device__ uint32_t merge_walk(bolt::MergeLds &L, uint32_t *pre, const uint64_t 
 // survivors go to its slot dst[q][chunk][k] and their number to
 // dst_cnt[q][chunk].  No atomics outside LDS: the slots are fixed.  With
 // fail (speculative starting bounds), the workgroup that finds fewer than k
-// keys for its query, or its overflow flag set, recomputes the query exactly
-// (redo_query).
+// keys for its query, or its overflow flag set, lists the query for the
+// exact recomputation (flag_redo) and writes no result.
 __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restrict__ cand,
                                                          const uint32_t *__restrict__ ccnt, int64_t n_rb,
                                                          int64_t slots_per_chunk, uint32_t k,
@@ -217,9 +238,8 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
                                                          int largest, uint32_t smax, uint64_t *__restrict__ dst,
                                                          uint32_t *__restrict__ dst_cnt,
                                                          uint16_t *__restrict__ vals,
-                                                         int32_t *__restrict__ idx, const uint32_t *__restrict__ fail,
-                                                         const uint8_t *__restrict__ codes, int64_t N, int M,
-                                                         const uint8_t *__restrict__ luts)
+                                                         int32_t *__restrict__ idx, uint32_t *__restrict__ fail,
+                                                         uint32_t *__restrict__ redo)
 {
     __shared__ bolt::MergeLds L;
     __shared__ uint32_t pre[257];
@@ -243,7 +263,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
     __syncthreads();
     if (gridDim.y == 1) {
         if (fail && (n < k || fail[q]))
-            bolt::redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
+            flag_redo(q, gthr, fail, redo);
         else
             bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
         return;
@@ -260,12 +280,10 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
 // (only the filled part of each slot) and writes the sorted result.
 __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__restrict__ src,
                                                           const uint32_t *__restrict__ src_cnt, int n_chunks,
-                                                          uint32_t k, const uint32_t *__restrict__ gthr,
+                                                          uint32_t k, uint32_t *__restrict__ gthr,
                                                           int largest, uint32_t smax,
                                                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx,
-                                                          const uint32_t *__restrict__ fail,
-                                                          const uint8_t *__restrict__ codes, int64_t N, int M,
-                                                          const uint8_t *__restrict__ luts)
+                                                          uint32_t *__restrict__ fail, uint32_t *__restrict__ redo)
 {
     __shared__ bolt::MergeLds L;
     __shared__ uint32_t pre[257];
@@ -279,13 +297,84 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     const uint32_t n = merge_walk(L, pre, src + q * (int64_t)n_chunks * k, src_cnt + q * (int64_t)n_chunks, 0,
                                   n_chunks, k);
     if (fail && (n < k || fail[q])) {
-        bolt::redo_query(L, codes, N, M, luts, q, k, largest, vals, idx);
+        flag_redo(q, gthr, fail, redo);
         return;
     }
     if (tid < 64 && n > k)
         bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
     __syncthreads();
     bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
+}
+
+// Stage 3: exact recomputation of the listed queries (redo[0] of them, at
+// redo[2 ...]) on the whole GPU.  Item i of the persistent loop is (listed
+// query i / n_rb, tile i % n_rb): a one-query tile over the tile's rows from
+// the query's open bound, publishing pruned bounds to the query's other
+// tiles and writing its local top-k to the query's own candidate slot
+// (free since the merge).  The workgroup that completes a query's last tile
+// (its count in fail[q]) merges the n_rb slots below the published bound
+// and writes the sorted result.  With an empty list every workgroup exits
+// at once.
+template <int MM>
+__global__ __launch_bounds__(256) void topk_redo_kernel(const uint8_t *__restrict__ codes, int64_t N,
+                                                        const uint8_t *__restrict__ luts, uint32_t k, int largest,
+                                                        int64_t n_rb, int64_t rpb, const int64_t *__restrict__ tiles,
+                                                        uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
+                                                        uint32_t *fail, const uint32_t *__restrict__ redo,
+                                                        uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    extern __shared__ __attribute__((aligned(16))) char redo_lds[];
+    __shared__ bolt::MergeLds L;
+    __shared__ uint32_t pre[257];
+    __shared__ uint32_t s_last;
+    const int tid = threadIdx.x;
+    const int64_t items = (int64_t)redo[0] * n_rb;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t q = redo[2 + it / n_rb];
+        const int64_t rb = it % n_rb;
+        bolt::TileJob job;
+        job.codes = codes;
+        job.luts = luts;
+        job.cand = cand;
+        job.ccnt = ccnt;
+        job.hist = nullptr;
+        job.fail = nullptr;
+        job.gthr = gthr;
+        if (tiles) {
+            job.r0 = tiles[2 * rb];
+            job.r1 = tiles[2 * rb + 1];
+        } else {
+            job.r0 = rb * rpb;
+            job.r1 = (job.r0 + rpb) < N ? (job.r0 + rpb) : N;
+        }
+        job.rb = rb;
+        job.n_rb = n_rb;
+        job.q0 = q;
+        job.nq = 1;
+        job.k = k;
+        job.largest = largest;
+        bolt::few_tile<MM, true>(job, redo_lds);
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();   // this tile's keys and count before its completion
+            s_last = atomicAdd(&fail[q], 1u) == (uint32_t)(n_rb - 1) ? 1u : 0u;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();   // every tile's keys of q after their completions
+            if (tid == 0) {
+                L.mcnt = 0;
+                L.mbound = ((uint64_t)bolt::read_bound(&gthr[q]) + 1u) << 32;   // keys with d <= bound
+            }
+            __syncthreads();
+            const uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, 0, n_rb, k);
+            if (tid < 64 && n > k)
+                bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
+            __syncthreads();
+            bolt::merge_emit(L, n > k ? k : n, k, largest, 255u * MM, vals + q * k, idx + q * k);
+        }
+        __syncthreads();
+    }
 }
 
 // Result padding when no row is scanned: 65535 / 0 and index -1.
@@ -340,17 +429,17 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restri
 // Sample (speculative bounds): workgroup (query block, chunk c) writes the
 // group minima of its queries over rows [c * stride, c * stride + kSpecSpan)
 // to out[q][c * kSpecGroups ...] (G entries per query).
-template <int MM, int NT>
+template <int MM, int NT, bool SP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void spec_sample_kernel(
     const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t Q, int largest, int64_t stride,
     int64_t G, uint16_t *__restrict__ out)
 {
-    __shared__ uint4 onehot[16];
+    __shared__ bolt::OneHot onehot;
     __shared__ __attribute__((aligned(16))) uint16_t gmin[32 * NT * bolt::kSpecGminStride];
     const int64_t q0 = (int64_t)blockIdx.x * 32 * NT;
     const int nq = (int)((Q - q0) < 32 * NT ? (Q - q0) : 32 * NT);
     const int64_t c = blockIdx.y;
-    bolt::mfma_sample_tile<MM, NT>(codes, luts, q0, nq, largest, c * stride, out, G, c * bolt::kSpecGroups, onehot,
+    bolt::mfma_sample_tile<MM, NT, SP>(codes, luts, q0, nq, largest, c * stride, out, G, c * bolt::kSpecGroups, onehot,
                                    gmin);
 }
 
@@ -358,15 +447,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
 // G sample group minima (r distinct sample rows lie at or below it), written
 // as the query's starting bound (0 when a test forces every query onto the
 // recomputation).  Also clears the query's candidate histogram and overflow
-// flag (this kernel replaces the initialisation when the bounds are
-// speculative).
+// flag, and the recomputation list (this kernel replaces the initialisation
+// when the bounds are speculative).
 __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ gmins, int64_t G,
                                                           uint32_t r, int shift, uint32_t *__restrict__ gthr,
                                                           uint32_t *__restrict__ hist, uint32_t *__restrict__ fail,
-                                                          int force_fail)
+                                                          uint32_t *__restrict__ redo, int force_fail)
 {
     __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
     const int64_t q = blockIdx.x;
+    if (q == 0 && threadIdx.x == 0)
+        redo[0] = 0u;   // the recomputation list starts empty
     for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
         hist[q * bolt::kHistBins + i] = 0;
     const uint32_t b = bolt::select_rank_u16(gmins + q * G, G, r, shift, h);
@@ -398,8 +489,8 @@ constexpr int ng_for()
 // small r it rarely differs from the r-th smallest distance.  It is found
 // exactly: a histogram locates its bin, a second count that bin's values.
 // The bound only selects candidates: the
-// final merge flags any query with fewer than k candidates and
-// redo_query recomputes it exactly, so results never depend on it.
+// final merge lists any query with fewer than k candidates and
+// topk_redo_kernel recomputes it exactly, so results never depend on it.
 using bolt::kSpecSpan;
 using bolt::kSpecMinRows;
 using bolt::kSpecMinRowsForced;
@@ -416,6 +507,7 @@ struct FusedPlan {
     int spec_r = 0, spec_nsc = 0;
     int64_t spec_stride = 0;
     size_t spec_bytes = 0;   // sample group minima [Q][nsc * kSpecGroups] uint16, overflow flags [Q]
+    size_t redo_bytes = 0;   // recomputation list: count, spare, queries [Q] (uint32)
 };
 
 // The kernel for the shape and its rows per tile (N: rows to scan).
@@ -489,6 +581,7 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
     p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * bolt::kSpecGroups * sizeof(uint16_t)) +
                                 align256((size_t)Q * sizeof(uint32_t))
                           : 0;
+    p.redo_bytes = p.spec ? align256((size_t)(Q + 2) * sizeof(uint32_t)) : 0;
     p.ok = true;
     return p;
 }
@@ -517,14 +610,20 @@ void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint
     }
     const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
     bolt::ProfScope prof_(prof_name, s);
-    if (p.kind == 3 && p.spec)
-        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, kMfmaNT, true>), dim3(grid), dim3(256), 0, s, codes,
-                           N, luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles,
-                           stride, span);
+#define BOLT_MFMA_SCAN(FREE, SP)                                                                                  \
+    hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, kMfmaNT, FREE, SP>), dim3(grid), dim3(256), 0, s, codes, N,    \
+                       luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles, stride, \
+                       span)
+    const bool sp = bolt::g_sparse_mfma != 0;
+    if (p.kind == 3 && p.spec && sp)
+        BOLT_MFMA_SCAN(true, true);
+    else if (p.kind == 3 && p.spec)
+        BOLT_MFMA_SCAN(true, false);
+    else if (p.kind == 3 && sp)
+        BOLT_MFMA_SCAN(false, true);
     else if (p.kind == 3)
-        hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, kMfmaNT, false>), dim3(grid), dim3(256), 0, s,
-                           codes, N, luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr,
-                           tiles, stride, span);
+        BOLT_MFMA_SCAN(false, false);
+#undef BOLT_MFMA_SCAN
     else
         hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes, N,
                            luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles,
@@ -554,8 +653,12 @@ void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_
     const int nt = kMfmaNT;
     const dim3 grid((unsigned)((Q + 32 * nt - 1) / (32 * nt)), (unsigned)nsc);
 #define BOLT_SAMPLE_M(MM)                                                                                           \
-    hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT>), grid, dim3(256), 0, s, codes, luts, Q, largest, stride, G, \
-                       out)
+    if (bolt::g_sparse_mfma)                                                                                        \
+        hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT, true>), grid, dim3(256), 0, s, codes, luts, Q, largest, \
+                           stride, G, out);                                                                         \
+    else                                                                                                            \
+        hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT, false>), grid, dim3(256), 0, s, codes, luts, Q, largest,\
+                           stride, G, out)
     switch (M) {
     case 8: BOLT_SAMPLE_M(8); break;
     case 16: BOLT_SAMPLE_M(16); break;
@@ -563,6 +666,29 @@ void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_
     case 64: BOLT_SAMPLE_M(64); break;
     }
 #undef BOLT_SAMPLE_M
+}
+
+// Stage 3 launch: a persistent grid of at most kRedoGrid workgroups (the
+// list's length is known only on the device).
+constexpr int64_t kRedoGrid = 1024;
+
+void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k, int largest,
+                 const FusedPlan &p, const int64_t *tiles, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
+                 uint32_t *fail, const uint32_t *redo, uint16_t *vals, int32_t *idx, hipStream_t s)
+{
+    const int64_t items = (int64_t)p.n_rb * Q;
+    const dim3 grid((unsigned)(items < kRedoGrid ? items : kRedoGrid));
+    const size_t lds = bolt::few_tile_lds_bytes(M, 1);
+#define BOLT_REDO_M(MM)                                                                                          \
+    hipLaunchKernelGGL(topk_redo_kernel<MM>, grid, dim3(256), lds, s, codes, N, luts, (uint32_t)k, largest,     \
+                       (int64_t)p.n_rb, p.rpb, tiles, cand, ccnt, gthr, fail, redo, vals, idx)
+    switch (M) {
+    case 8: BOLT_REDO_M(8); break;
+    case 16: BOLT_REDO_M(16); break;
+    case 32: BOLT_REDO_M(32); break;
+    case 64: BOLT_REDO_M(64); break;
+    }
+#undef BOLT_REDO_M
 }
 
 const char *scan_prof_name(int kind)
@@ -600,7 +726,8 @@ bool fused_supported(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 
 static size_t plan_bytes(const FusedPlan &p)
 {
-    return p.cand_bytes + p.ccnt_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes + p.spec_bytes;
+    return p.cand_bytes + p.ccnt_bytes + p.gthr_bytes + p.hist_bytes + p.level2_bytes + p.spec_bytes +
+           p.redo_bytes;
 }
 
 size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
@@ -631,6 +758,7 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     uint16_t *gmins = p.spec ? reinterpret_cast<uint16_t *>(ws_spec) : nullptr;
     uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * G * sizeof(uint16_t)))
                             : nullptr;
+    uint32_t *redo = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + p.spec_bytes) : nullptr;
     if (p.spec) {
         // sample group minima, then each query's starting bound (and cleared histogram)
         {
@@ -639,7 +767,7 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         }
         bolt::ProfScope prof_("spec_select", s);
         hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, gmins, G, (uint32_t)p.spec_r,
-                           bolt::hist_shift(M), gthr, hist, fail, bolt::g_spec_mode == 2 ? 1 : 0);
+                           bolt::hist_shift(M), gthr, hist, fail, redo, bolt::g_spec_mode == 2 ? 1 : 0);
     } else {
         const int64_t n_hist = Q * bolt::kHistBins;
         hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
@@ -660,12 +788,14 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand, ccnt,
                            (int64_t)p.n_rb, p.n_chunks > 1 ? p.chunk : (int64_t)p.n_rb, (uint32_t)k, gthr, hist,
-                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, fail, codes, N,
-                           M, luts);
+                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, fail, redo);
         if (p.n_chunks > 1)
             hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
-                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, fail, codes, N, M,
-                               luts);
+                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, fail, redo);
+    }
+    if (p.spec) {
+        bolt::ProfScope prof_("topk_redo", s);
+        launch_redo(M, codes, N, luts, Q, k, (int)largest, p, tiles, cand, ccnt, gthr, fail, redo, vals, idx, s);
     }
     return check_launch("bolt_scan_topk (fused)");
 }

@@ -205,18 +205,17 @@ __global__ __launch_bounds__(256) void scan_mfma_kernel(const uint8_t *__restric
 {
     constexpr int NW = MM / 8;
     constexpr int OFF = 128 * MM;
-    __shared__ uint4 onehot[16];
+    __shared__ bolt::OneHot onehot;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int half = lane >> 5, col = lane & 31;
     const int64_t q0 = (int64_t)blockIdx.y * 32 * NT;
     const int nq = (int)((Q - q0) < 32 * NT ? (Q - q0) : 32 * NT);
     const int64_t r0 = (int64_t)blockIdx.x * rpb;
     const int64_t r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
-    bolt::mfma_onehot_init(onehot);
+    bolt::onehot_init(onehot);
     bolt::i32x4 tb[NT][MM / 2];
     bolt::mfma_load_tables<MM, NT>(luts, q0, nq, 0, tb);
     __syncthreads();
-    const char *oh = reinterpret_cast<const char *>(onehot);
     uint32_t nxt[NW];
     {
         const int64_t n = r0 + 32 * wave + col;
@@ -233,7 +232,7 @@ __global__ __launch_bounds__(256) void scan_mfma_kernel(const uint8_t *__restric
         }
         __builtin_amdgcn_sched_barrier(0);
         bolt::i32x16 acc[NT];
-        bolt::mfma_pass<MM, NT>(cw, oh, tb, acc);
+        bolt::mfma_pass<MM, NT, true>(cw, onehot, tb, acc);
         const int64_t rl = base + 32 * wave + 4 * half;   // first row of this lane's runs
         const bool full = base + bolt::kMfmaPass <= r1;
 #pragma unroll

@@ -318,6 +318,25 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
 // each) in registers for the whole tile and takes 32 rows per pass; the
 // one-hot operand comes from a 16-entry LDS table, conflict free.
 //
+// Sparse form (SP): a one-hot row has one nonzero in every group of four
+// entries at most, which is the 4:2 structure of the sparse matrix
+// instruction v_smfmac_i32_32x32x64_i8: it contracts 64 entries (four
+// subspaces) in the time the dense one takes for 32, from a compressed
+// operand of two (value, 2-bit position) slots per group.  Its lanes pair
+// up as follows: compressed element j (0..15) of lane l (row l % 32, half
+// h = l / 32) multiplies byte 16 h + 4 ((j / 2) % 4) + pos_j of the table
+// operand of lane 32 (j / 8) + l % 32, whose 32 bytes are two 16-byte
+// blocks.  So with the table operand of step i (lane half g) made of the
+// tables of subspaces 4 i + g and 4 i + 2 + g -- the dense form's steps
+// 2 i and 2 i + 1, unchanged in registers -- lane half h covers subspaces
+// 4 i + 2 h (elements 0..7) and 4 i + 2 h + 1 (elements 8..15), the two
+// nibbles of code byte 2 i + h.  Code c of the low nibble is element
+// 2 (c / 4) with value 1 and position c % 4, that of the high nibble
+// element 8 + 2 (c / 4); every other element is 0.  The values depend only
+// on the two group numbers (a 16-entry table, conflict free) and the
+// positions on the byte (a 256-entry table of index words).  The result
+// lanes are those of the dense form.
+//
 // FREE (with speculative starting bounds only): the bounds are taken as
 // they are and never tightened, so the waves need no barriers between
 // passes, and no atomics either: the query's buffer is cut into kMfmaSegs
@@ -333,7 +352,15 @@ constexpr int kMfmaSegs = 8;     // FREE: one buffer segment per (wave, lane hal
 constexpr int kMfmaSeg = kMfmaCap / kMfmaSegs;
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+// Operand tables of the one-hot codes in LDS.
+struct OneHot {
+    uint4 dense[16];     // entry c: byte c is 1
+    uint4 sval[16];      // sparse values, entry g0 + 4 g1: bytes 2 g0 and 8 + 2 g1 are 1
+    uint32_t sidx[256];  // sparse positions of code byte b: (b & 3) << 4 (b >> 2 & 3), (b >> 4 & 3) << 16 + 4 (b >> 6)
+};
 
 template <int NT>
 struct MfmaLds {
@@ -341,18 +368,27 @@ struct MfmaLds {
     uint32_t cnt[NT * 32];
     uint32_t bnd[NT * 32];
     uint32_t seg[NT * 32 * kMfmaSegs];   // FREE: keys appended to each segment
-    uint4 onehot[16];
+    OneHot oh;
 };
 
-// Entry c of the one-hot table (16 x 16 bytes): byte c is 1.  Threads 0-63.
-__device__ __forceinline__ void mfma_onehot_init(uint4 *onehot)
+// Fills the one-hot tables (every thread of a 256-thread workgroup takes part).
+__device__ __forceinline__ void onehot_init(OneHot &T)
 {
     const int tid = threadIdx.x;
     if (tid < 64) {
         const int c = tid >> 2, j = tid & 3;
-        reinterpret_cast<uint32_t *>(onehot)[tid] = (c >> 2) == j ? (1u << (8 * (c & 3))) : 0u;
+        reinterpret_cast<uint32_t *>(T.dense)[tid] = (c >> 2) == j ? (1u << (8 * (c & 3))) : 0u;
+        const int g = j < 2 ? (c & 3) : (c >> 2);   // entry c = g0 + 4 g1; words 0, 1 hold g0, words 2, 3 g1
+        reinterpret_cast<uint32_t *>(T.sval)[tid] = (g >> 1) == (j & 1) ? (1u << (16 * (g & 1))) : 0u;
+    }
+    for (int b = tid; b < 256; b += blockDim.x) {
+        const uint32_t c0 = b & 15u, c1 = (uint32_t)b >> 4;
+        T.sidx[b] = ((c0 & 3u) << (4u * (c0 >> 2))) | ((c1 & 3u) << (16u + 4u * (c1 >> 2)));
     }
 }
+
+// Whether the matrix-core tiles use the sparse instruction (test hook).
+extern int g_sparse_mfma;
 
 // This lane's table columns (queries q0 + 32 t + l % 32, subspace 2 s + l / 32)
 // as int8 T - 128 (or (255 - T) - 128 for the largest sums); queries at or
@@ -380,12 +416,48 @@ __device__ __forceinline__ void mfma_load_tables(const uint8_t *__restrict__ lut
 
 // acc[t] = d - 128 M of this lane's 16 rows (its code row cw is row l % 32 of
 // the wave's 32) against the queries of table tile t.
-template <int MM, int NT>
-__device__ __forceinline__ void mfma_pass(const uint32_t (&cw)[MM / 8], const char *oh,
+template <int MM, int NT, bool SP>
+__device__ __forceinline__ void mfma_pass(const uint32_t (&cw)[MM / 8], const OneHot &T,
                                           const i32x4 (&tb)[NT][MM / 2], i32x16 (&acc)[NT])
 {
     constexpr int NW = MM / 8;
     const int half = (threadIdx.x & 63) >> 5;
+    if constexpr (SP) {
+        const char *sv = reinterpret_cast<const char *>(T.sval);
+        const char *oh = reinterpret_cast<const char *>(T.dense);
+        // Subspaces 0-3 take two dense steps: the first one starts the
+        // accumulators from zero, which the sparse instruction (it
+        // accumulates in place) could only do after 16 register moves.
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const i32x4 av = *reinterpret_cast<const i32x4 *>(oh + ((cw[0] >> (8 * s + 4 * half)) & 15u) * 16u);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, tb[t][s], s == 0 ? i32x16{} : acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < NW; ++v) {
+            // bytes 0 and 2 of w: the code bytes of steps 2 v and 2 v + 1
+            const uint32_t w = cw[v] >> (8 * half);
+            // per 16-bit half: 16 (g0 + 4 g1), the offset of the values entry
+            const uint32_t off = ((w & 0x000C000Cu) << 2) | (w & 0x00C000C0u);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (v == 0 && e == 0)
+                    continue;   // subspaces 0-3: the dense steps above
+                const uint32_t pos = T.sidx[(w >> (16 * e)) & 0xFFu];
+                const i32x4 av = *reinterpret_cast<const i32x4 *>(sv + ((off >> (16 * e)) & 0xFFFFu));
+                const int s = 4 * v + 2 * e;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const i32x8 bv = __builtin_shufflevector(tb[t][s], tb[t][s + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+                    acc[t] = __builtin_amdgcn_smfmac_i32_32x32x64_i8(av, bv, acc[t], (int)pos, 0, 0);
+                }
+            }
+        }
+        return;
+    }
+    const char *oh = reinterpret_cast<const char *>(T.dense);
     // byte s of wa: the LDS offset (16 x code) of subspace 2 s + half
     uint32_t wa[NW];
 #pragma unroll
@@ -426,7 +498,7 @@ __device__ __forceinline__ void mfma_pass(const uint32_t (&cw)[MM / 8], const ch
     }
 }
 
-template <int MM, int NT, bool FREE>
+template <int MM, int NT, bool FREE, bool SP>
 __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
 {
     constexpr int KS = MM / 2;       // matrix-core steps per row, two subspaces each
@@ -441,7 +513,7 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
     const uint32_t k = job.k;
     const int64_t q0 = job.q0;
 
-    mfma_onehot_init(L.onehot);
+    onehot_init(L.oh);
     for (int q = tid; q < QB; q += 256) {
         L.cnt[q] = 0;
         L.bnd[q] = q < nq ? read_bound(&job.gthr[q0 + q]) + 1u : 0u;
@@ -452,7 +524,6 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
     __syncthreads();
 
     const int64_t r0 = job.r0, r1 = job.r1;
-    const char *oh = reinterpret_cast<const char *>(L.onehot);
     // codes one pass ahead, clamped to the last row (unconditional loads)
     uint32_t nxt[NW];
     if (r0 < r1) {
@@ -493,7 +564,7 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
         }
 
         i32x16 acc[NT];
-        mfma_pass<MM, NT>(cw, oh, tb, acc);
+        mfma_pass<MM, NT, SP>(cw, L.oh, tb, acc);
 
         // rows of accumulator v: rb + 8 (v / 4) + v % 4
         const int64_t rb = base + 32 * wave + 4 * half;
@@ -631,20 +702,19 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
 // least 32 * NT * kSpecGminStride entries) and stored as 16-byte rows.
 constexpr int kSpecGminStride = kSpecGroups + 8;   // uint16 per query row in LDS (2-way banks)
 
-template <int MM, int NT>
+template <int MM, int NT, bool SP>
 __device__ void mfma_sample_tile(const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t q0,
                                  int nq, int largest, int64_t r0, uint16_t *__restrict__ out, int64_t G,
-                                 int64_t g0, uint4 *onehot, uint16_t *gmin)
+                                 int64_t g0, OneHot &oh, uint16_t *gmin)
 {
     constexpr int NW = MM / 8;
     constexpr int OFF = 128 * MM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int half = lane >> 5, col = lane & 31;
-    mfma_onehot_init(onehot);
+    onehot_init(oh);
     i32x4 tb[NT][MM / 2];
     mfma_load_tables<MM, NT>(luts, q0, nq, largest, tb);
     __syncthreads();
-    const char *oh = reinterpret_cast<const char *>(onehot);
     // codes one pass ahead (the last pass re-reads its own rows)
     uint32_t nxt[NW];
     load_row<MM>(codes, r0 + 32 * wave + col, nxt);
@@ -657,7 +727,7 @@ __device__ void mfma_sample_tile(const uint8_t *__restrict__ codes, const uint8_
         load_row<MM>(codes, r0 + ahead + 32 * wave + col, nxt);
         __builtin_amdgcn_sched_barrier(0);
         i32x16 acc[NT];
-        mfma_pass<MM, NT>(cw, oh, tb, acc);
+        mfma_pass<MM, NT, SP>(cw, oh, tb, acc);
         const int g = base / kSpecGroup + 2 * wave + half;   // this lane's group in the chunk
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -1175,62 +1245,6 @@ __device__ uint32_t select_rank_u16(const uint16_t *__restrict__ v, int64_t G, u
     while (run + sub[j] < r)   // the bin holds the r-th value: ends at j < 2^shift
         run += sub[j++];
     return (bin << shift) + j;
-}
-
-// Exact top-k of one query whose speculative bound failed (fewer than k
-// rows passed it), by the merging workgroup itself: it scans every row with
-// the query's table in LDS, appends keys (d << 32 | row) below the running
-// bound and prunes by the merge's scheme, then writes the sorted result.
-__device__ void redo_query(MergeLds &L, const uint8_t *__restrict__ codes, int64_t N, int M,
-                           const uint8_t *__restrict__ luts, int64_t q, uint32_t k, int largest,
-                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
-{
-    __shared__ uint16_t tab[64 * 16];   // d contribution of (subspace, code)
-    const int tid = threadIdx.x;
-    __syncthreads();   // the caller is done with L
-    for (int e = tid; e < M * 16; e += 256) {
-        const uint32_t v = luts[q * M * 16 + e];
-        tab[e] = (uint16_t)(largest ? 255u - v : v);
-    }
-    if (tid == 0) {
-        L.mcnt = 0;
-        L.mbound = ~0ull;
-    }
-    __syncthreads();
-    const int half = M / 2;
-    for (int64_t c0 = 0; c0 < N; c0 += 256 * kMergeE) {
-        const uint64_t bnd = L.mbound;
-        for (int e = 0; e < kMergeE; ++e) {
-            const int64_t row = c0 + tid + 256 * e;
-            if (row < N) {
-                const uint8_t *pr = codes + row * half;
-                uint32_t d = 0;
-                for (int b = 0; b < half; ++b) {
-                    const uint32_t byte = pr[b];
-                    d += tab[(2 * b) * 16 + (byte & 15u)] + tab[(2 * b + 1) * 16 + (byte >> 4)];
-                }
-                const uint64_t key = ((uint64_t)d << 32) | (uint64_t)row;
-                if (key < bnd) {
-                    const uint32_t pos = atomicAdd(&L.mcnt, 1u);
-                    L.mb[pos] = key;
-                }
-            }
-        }
-        __syncthreads();
-        if (tid < 64 && L.mcnt > kMergeCap - 256 * kMergeE) {
-            const uint64_t kth = prune_u64<kMergeCap>(L.mb, L.mcnt, k);
-            if (tid == 0) {
-                L.mcnt = k;
-                L.mbound = kth + 1;
-            }
-        }
-        __syncthreads();
-    }
-    const uint32_t n = L.mcnt;
-    if (tid < 64 && n > k)
-        prune_u64_fit<kMergeCap>(L.mb, n, k);
-    __syncthreads();
-    merge_emit(L, n > k ? k : n, k, largest, 255u * (uint32_t)M, vals + q * k, idx + q * k);
 }
 
 }  // namespace bolt

@@ -269,6 +269,7 @@ namespace bolt {
 int g_force_unfused_topk = 0;
 int g_force_fused_kind = -1;
 int g_spec_mode = -1;
+int g_sparse_mfma = 1;
 }
 
 static size_t unfused_ws_bytes(int64_t N, int64_t Q)
@@ -452,6 +453,13 @@ extern "C" int bolt_debug_speculation(int32_t mode)
     if (mode < -1 || mode > 2)
         return bolt::fail(BOLT_ERR_INVALID, "speculation mode must be -1, 0, 1 or 2 (got %d)", mode);
     bolt::g_spec_mode = mode;
+    return BOLT_OK;
+}
+
+// Test hook: the matrix-core tiles with the sparse (1) or the dense (0) instruction.
+extern "C" int bolt_debug_sparse_mfma(int32_t on)
+{
+    bolt::g_sparse_mfma = on ? 1 : 0;
     return BOLT_OK;
 }
 

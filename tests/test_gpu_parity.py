@@ -556,3 +556,38 @@ def test_scan_topk_fused_repeatable(bolt):
     vr, ir = oracle.topk(oracle.scan(codes, luts), k, False)
     for v, i in outs:
         assert np.array_equal(v.cpu().numpy(), vr) and np.array_equal(i.cpu().numpy(), ir)
+
+
+# the matrix-core tiles with the dense instruction (the sparse one is the
+# default and runs in every case above): same results, same oracle
+DENSE_CASES = [
+    # (M, Q, N, k, metric, lut kind, speculation mode)
+    (32, 70, 100_003, 100, "l2", "rand", 0), (16, 40, 70_000, 64, "dot", "coarse", 0),
+    (64, 33, 50_001, 128, "l2", "rand", 0), (8, 64, 40_000, 10, "dot", "rand", 0),
+    (32, 48, 140_000, 100, "dot", "rand", 1), (16, 9, 150_000, 100, "l2", "coarse", 2),
+    (64, 40, 131_100, 64, "dot", "rand", 1), (8, 31, 160_000, 128, "l2", "coarse", 2),
+]
+
+
+@pytest.mark.parametrize("M,Q,N,k,metric,kind,mode", DENSE_CASES)
+def test_scan_topk_dense_mfma_parity(bolt, M, Q, N, k, metric, kind, mode):
+    seed = 29 * M + 3 * Q + N + k
+    _say("dense matrix-core", metric, kind, "mode", mode, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    bolt.debug_sparse_mfma(False)
+    bolt.debug_force_fused_kind(3)
+    bolt.debug_speculation(mode)
+    try:
+        v, i = bolt.bolt_scan_topk(cd, ld, metric, k)
+        torch.cuda.synchronize()
+    finally:
+        bolt.debug_speculation(-1)
+        bolt.debug_force_fused_kind(-1)
+        bolt.debug_sparse_mfma(True)
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
