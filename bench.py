@@ -167,8 +167,12 @@ def parse():
     p.add_argument("--cpu-sample-rows", type=int, default=80_000)
     p.add_argument("--batched-dbs", type=int, default=256)
     p.add_argument("--serving-rows", type=int, default=250_000_000)
-    p.add_argument("--serving-requests", type=int, default=300)
-    p.add_argument("--fifo-requests", type=int, default=100)
+    p.add_argument("--serving-requests", type=int, default=2000,
+                   help="requests per load point of the continuous server")
+    p.add_argument("--fifo-requests", type=int, default=300,
+                   help="requests per load point of the FIFO baseline (and of the continuous server at FIFO's rates)")
+    p.add_argument("--served-check-queries", type=int, default=1000,
+                   help="served queries checked against the same queries alone")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run a 1 GiB device-to-device copy (counter calibration for profiles)")
     p.add_argument("--profile-kernels", default="",
@@ -321,11 +325,34 @@ def training_times(args, torch, B, mix):
     t0 = time.perf_counter()
     Ch, _, _, _ = B.bolt_train_host(Xh, M, 10, init, Qt, "l2")
     host_s = time.perf_counter() - t0
-    return {"workload": "k-means, %d x %d mixture rows, M=%d, 10 iterations" % (n, J, M),
+    # the quantiser search (Sec. 3.2: b_m and a from quantiles of the table
+    # entries over training pairs, alpha over its grid) for 1000 training
+    # queries against the training codes, on the GPU and on the host
+    nq = min(1000, n)
+    Qtd = Xtr[torch.from_numpy(synth.permutation_prefix(synth.seed_for(2, 5), n, nq)).to(Xtr.device)].contiguous()
+    tr_codes = B.bolt_encode(Xtr, Cg, M)
+    quant = {}
+    for metric in ("l2", "dot"):
+        B.bolt_learn_quantizer(Qtd, tr_codes, Cg, metric)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ag, og, ig, _ = B.bolt_learn_quantizer(Qtd, tr_codes, Cg, metric)
+        og = og.cpu().numpy()
+        qgpu_s = time.perf_counter() - t0
+        Qth, codes_h = Qtd.cpu().numpy(), tr_codes.cpu().numpy()
+        t0 = time.perf_counter()
+        ah, oh, ih = B.bolt_learn_quantizer_host(Qth, codes_h, Cg.cpu().numpy(), metric)
+        qhost_s = time.perf_counter() - t0
+        quant[metric] = {"gpu_ms": round(qgpu_s * 1e3, 2), "host_ms": round(qhost_s * 1e3, 1),
+                         "identical_to_host": bool(np.float32(ag) == np.float32(ah) and np.array_equal(og, oh)
+                                                   and int(ig) == int(ih))}
+    return {"workload": "k-means, %d x %d mixture rows, M=%d, 10 iterations; quantiser search, %d training "
+                        "queries against the training codes" % (n, J, M, nq),
             "kmeans_gpu_ms": round(gpu_s * 1e3, 2),
             "host_trainer_ms": round(host_s * 1e3, 1),
             "host_trainer_note": "k-means plus the quantiser for 64 queries, host threads",
-            "identical_codebooks": bool(np.array_equal(Cg.cpu().numpy(), Ch))}
+            "identical_codebooks": bool(np.array_equal(Cg.cpu().numpy(), Ch)),
+            "quantiser_search": quant}
 
 
 def exact_nn(torch, X, Qd):
@@ -438,6 +465,26 @@ def run_single_query(args, torch, B, W):
                            "kernels": {n: round(t / c, 4) for n, (c, t) in prof.items()}}
             log("single query M=%d %s: %.3f ms, %.0f GB/s (kernel %.0f GB/s)"
                 % (M, metric, med, nbytes / (med * 1e-3) / 1e9, nbytes / (scan_ms * 1e-3) / 1e9))
+            if metric == "l2":
+                # the same call with its sampled bound forced to fail: the
+                # exact recomputation on the whole GPU, and its result
+                v0, i0 = B.bolt_scan_topk(codes, luts, metric, k)
+                B.debug_speculation(2)
+                try:
+                    B.bolt_scan_topk(codes, luts, metric, k)
+                    flush.fill_(1.0)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    v1, i1 = B.bolt_scan_topk(codes, luts, metric, k)
+                    e1.record()
+                    torch.cuda.synchronize()
+                finally:
+                    B.debug_speculation(-1)
+                row[metric]["failed_bound"] = {
+                    "ms_per_query": round(e0.elapsed_time(e1), 4),
+                    "equals_unforced": bool(torch.equal(v0, v1) and torch.equal(i0, i1))}
+                log("single query M=%d, bound forced to fail: %.3f ms" % (M, e0.elapsed_time(e1)))
         out["M%d" % M] = row
         del db, codes
         torch.cuda.empty_cache()
@@ -654,16 +701,26 @@ def run_batched(args, torch, B, W):
 # ------------------------------------------------------------------ serving
 
 def run_serving(args, torch, B, W):
+    """Serving (8 resident databases): the continuous-batching server at its
+    saturation and at 0.3 / 0.6 / 0.9 of it; the FIFO baseline (one request
+    at a time, one launch sequence per query) at its own saturation and at
+    0.3 / 0.6 / 0.9 of that, with the continuous server at the same offered
+    rates beside it; the peak working memory against the budget and how
+    often admission stopped at the budget; and served results checked against
+    the same queries run alone at their snapshot."""
     import synth
     import synth.device as sdev
     from paper_1706_10283_amd.serve import GpuExecutor, Server, make_requests, summarize
     n_db, N, J, M, k = 8, args.serving_rows, 128, 32, 100
     t0 = time.time()
     dbs = []
+    # capacity: each run starts from the initial rows and appends about 0.1 x
+    # requests x 2.15e5 rows over the 8 databases
+    headroom = max(4_000_000, int(max(args.serving_requests, args.fifo_requests) * 0.1 * 2.15e5 / n_db * 1.5))
     for d in range(n_db):
         mix = synth.seed_for(5, 0) + 100 * d
         C, quant = W.train(mix, mix + 3, mix + 4, mix + 5, J, M, n_train=50_000, iters=10)
-        dbs.append(W.build_db(mix, mix + 1, N, J, M, C, quant, capacity=N + 4_000_000))
+        dbs.append(W.build_db(mix, mix + 1, N, J, M, C, quant, capacity=N + headroom))
         log("serving database %d/%d built (%.1fs)" % (d + 1, n_db, time.time() - t0))
     torch.cuda.synchronize()
     resident = sum(db.codes.numel() for db in dbs)
@@ -677,41 +734,64 @@ def run_serving(args, torch, B, W):
         srv = Server(ex, dbs, budget, mode=mode)
         wall = srv.run(reqs, realtime=rate > 0)
         torch.cuda.synchronize()
-        return reqs, wall, srv
+        out = summarize(reqs, wall)
+        out["offered_req_per_s"] = round(rate, 2) if rate > 0 else None
+        out["peak_in_use_GB"] = round(srv.peak / 1e9, 3)
+        out["budget_stalls"] = srv.budget_stalls
+        out["group_stalls"] = srv.group_stalls
+        log("%s at %s req/s: %s" % (mode, round(rate, 1) if rate else "max", out))
+        return reqs, wall, out
 
     serve("continuous", 0.0, 30, 1)   # warm-up
-    reqs, wall, _ = serve("continuous", 0.0, args.serving_requests, 2)
+    reqs, wall, sat_out = serve("continuous", 0.0, args.serving_requests, 2)
     sat = len(reqs) / wall
-    out = {"workload": "%d databases x %.3g rows, J=%d, M=%d (%.1f GB codes), budget resident + 8 GB"
-                       % (n_db, N, J, M, resident / 1e9),
-           "saturation_req_per_s": round(sat, 2), "continuous": {}, "fifo": {}}
-    out["continuous"]["saturation"] = summarize(reqs, wall)
-    check = None
+    out = {"workload": "%d databases x %.3g rows, J=%d, M=%d (%.1f GB codes), budget resident + %d GB"
+                       % (n_db, N, J, M, resident / 1e9, budget >> 30),
+           "budget_GB": round(budget / 1e9, 3),
+           "saturation_req_per_s": round(sat, 2), "continuous": {"saturation": sat_out}, "fifo": {}}
     for load in (0.3, 0.6, 0.9):
-        reqs, wall, srv = serve("continuous", load * sat, args.serving_requests, 10 + int(load * 10))
-        out["continuous"]["load_%.1f" % load] = summarize(reqs, wall)
-        log("continuous load %.1f: %s" % (load, out["continuous"]["load_%.1f" % load]))
+        reqs, wall, o = serve("continuous", load * sat, args.serving_requests, 10 + int(load * 10))
+        out["continuous"]["load_%.1f" % load] = o
         if load == 0.6:
-            # served == alone on a sample of served queries, checked before the
-            # next run's inserts rewrite the rows past the initial database
-            check = [r for r in reqs if r.kind == "query" and r.status == "done"][:20]
-            same = bool(check)
-            for r in check:
-                db = dbs[r.db]
-                qd = torch.from_numpy(np.ascontiguousarray(r.Qv)).to("cuda")
-                v, i = B.bolt_scan_topk(db.codes[:r.watermark], db.luts(qd, r.metric), r.metric, r.k)
-                same &= bool(np.array_equal(v.cpu().numpy(), r.vals) and np.array_equal(i.cpu().numpy(), r.idx))
-            out["served_equals_alone"] = same
-            out["served_equals_alone_checked"] = len(check)
-    reqs, wall, _ = serve("fifo", 0.0, args.fifo_requests, 3)
+            out["served_equals_alone"] = served_equals_alone(torch, B, dbs, reqs, args.served_check_queries)
+    reqs, wall, o = serve("fifo", 0.0, args.fifo_requests, 3)
     fsat = len(reqs) / wall
     out["fifo"]["saturation_req_per_s"] = round(fsat, 2)
-    out["fifo"]["saturation"] = summarize(reqs, wall)
-    reqs, wall, _ = serve("fifo", 0.3 * sat, args.fifo_requests, 13)
-    out["fifo"]["load_0.3_of_continuous"] = summarize(reqs, wall)
-    log("fifo at 0.3 of continuous saturation: %s" % out["fifo"]["load_0.3_of_continuous"])
+    out["fifo"]["saturation"] = o
+    out["continuous_at_fifo_rates"] = {}
+    for load in (0.3, 0.6, 0.9):
+        _, _, o = serve("fifo", load * fsat, args.fifo_requests, 20 + int(load * 10))
+        out["fifo"]["load_%.1f" % load] = o
+        _, _, o = serve("continuous", load * fsat, args.fifo_requests, 20 + int(load * 10))
+        out["continuous_at_fifo_rates"]["load_%.1f_of_fifo" % load] = o
     del dbs, ex
     return out
+
+
+def served_equals_alone(torch, B, dbs, reqs, n_queries):
+    """Served results of the first query requests (at least n_queries
+    queries) equal the same requests run alone against their database
+    truncated at the request's snapshot; the first 100 of those queries are
+    also run one query per call."""
+    checked, singles, same = 0, 0, True
+    for r in reqs:
+        if checked >= n_queries:
+            break
+        if r.kind != "query" or r.status != "done":
+            continue
+        db = dbs[r.db]
+        qd = torch.from_numpy(np.ascontiguousarray(r.Qv)).to("cuda")
+        v, i = B.bolt_scan_topk(db.codes[:r.watermark], db.luts(qd, r.metric), r.metric, r.k)
+        same &= bool(np.array_equal(v.cpu().numpy(), r.vals) and np.array_equal(i.cpu().numpy(), r.idx))
+        for j in range(r.size):
+            if singles >= 100:
+                break
+            v1, i1 = B.bolt_scan_topk(db.codes[:r.watermark], db.luts(qd[j:j + 1], r.metric), r.metric, r.k)
+            same &= bool(np.array_equal(v1.cpu().numpy(), r.vals[j:j + 1]) and
+                         np.array_equal(i1.cpu().numpy(), r.idx[j:j + 1]))
+            singles += 1
+        checked += r.size
+    return {"equal": same, "queries_checked": checked, "queries_checked_one_per_call": singles}
 
 
 def profile_kernels(args, torch, B, W):

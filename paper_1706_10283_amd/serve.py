@@ -193,6 +193,8 @@ class Server:
         self.clock = clock
         self.in_use = 0
         self.peak = 0
+        self.budget_stalls = 0   # admission rounds stopped by a request that did not fit the budget
+        self.group_stalls = 0    # admission rounds stopped by the limit on query groups in flight
         self.committed = [db.n_rows for db in dbs]   # visible rows per database
         self.reserved = [db.n_rows for db in dbs]    # rows handed out to inserts
 
@@ -318,10 +320,12 @@ class Server:
                     continue
                 fp = self._footprint(r)
                 if self.in_use + fp > self.budget:
+                    self.budget_stalls += 1
                     break
                 if r.kind == "query":
                     key = (r.db, r.metric, self.committed[r.db], r.k)
                     if key not in groups and n_groups + len(groups) >= self.max_groups:
+                        self.group_stalls += 1
                         break
                     waiting.popleft()
                     r.admitted, r.watermark, r.reserved = self.clock() - t0, self.committed[r.db], fp
@@ -396,6 +400,7 @@ def summarize(reqs, wall: float):
         return float(np.percentile(xs, p)) * 1e3 if len(xs) else math.nan
     q = [r.latency for r in reqs if r.kind == "query" and r.status == "done"]
     ins = [r.latency for r in reqs if r.kind == "insert" and r.status == "done"]
+    wait = [r.admitted - r.arrival for r in reqs if r.status == "done"]
     dist = sum(r.size * r.watermark for r in reqs if r.kind == "query" and r.status == "done")
     return {"requests": len(reqs), "done": sum(r.status == "done" for r in reqs),
             "refused": sum(r.status == "refused" for r in reqs),
@@ -404,4 +409,5 @@ def summarize(reqs, wall: float):
             "wall_s": round(wall, 4),
             "query_p50_ms": round(pct(q, 50), 3), "query_p99_ms": round(pct(q, 99), 3),
             "insert_p50_ms": round(pct(ins, 50), 3), "insert_p99_ms": round(pct(ins, 99), 3),
+            "admission_wait_p50_ms": round(pct(wait, 50), 3), "admission_wait_p99_ms": round(pct(wait, 99), 3),
             "G_distances_per_s": round(dist / wall / 1e9, 3) if wall > 0 else math.nan}
