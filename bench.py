@@ -716,7 +716,7 @@ def run_serving(args, torch, B, W):
     dbs = []
     # capacity: each run starts from the initial rows and appends about 0.1 x
     # requests x 2.15e5 rows over the 8 databases
-    headroom = max(4_000_000, int(max(args.serving_requests, args.fifo_requests) * 0.1 * 2.15e5 / n_db * 1.5))
+    headroom = max(4_000_000, int(max(args.serving_requests, args.fifo_requests) * 0.1 * 2.15e5 / n_db * 3))
     for d in range(n_db):
         mix = synth.seed_for(5, 0) + 100 * d
         C, quant = W.train(mix, mix + 3, mix + 4, mix + 5, J, M, n_train=50_000, iters=10)
@@ -729,7 +729,7 @@ def run_serving(args, torch, B, W):
     budget = 8 << 30   # working memory on top of the resident codes
     ex = GpuExecutor(dbs)
 
-    def serve(mode, rate, n_req, seed):
+    def serve(mode, rate, n_req, seed, budget=budget):
         reqs = make_requests(n_req, n_db, J, rate, seed, qpool, ipool, k=k)
         srv = Server(ex, dbs, budget, mode=mode)
         wall = srv.run(reqs, realtime=rate > 0)
@@ -749,6 +749,10 @@ def run_serving(args, torch, B, W):
                        % (n_db, N, J, M, resident / 1e9, budget >> 30),
            "budget_GB": round(budget / 1e9, 3),
            "saturation_req_per_s": round(sat, 2), "continuous": {"saturation": sat_out}, "fifo": {}}
+    # the same saturation run under a working-memory budget of 1 GB, below
+    # what the batching would use: admission now stops at the budget
+    _, _, o = serve("continuous", 0.0, max(args.serving_requests // 4, 100), 2, budget=1 << 30)
+    out["continuous"]["saturation_budget_1GB"] = o
     for load in (0.3, 0.6, 0.9):
         reqs, wall, o = serve("continuous", load * sat, args.serving_requests, 10 + int(load * 10))
         out["continuous"]["load_%.1f" % load] = o

@@ -52,6 +52,7 @@ struct DevDb {
     int32_t spec_r;    // rank of the sample group minimum taken as the bound
     int32_t pad;
     uint32_t *fail;    // per query: a barrier-free tile overflowed, recompute exactly
+    uint32_t *lcnt;    // speculative databases: per-query dense candidate lists (count of cand[q])
 };
 
 // One sample work item: queries [q0, q0 + 32) of a database over one chunk.
@@ -82,8 +83,9 @@ constexpr size_t kBatchLds = 49664;
 // Workgroups of the persistent recomputation launch (the number of listed
 // queries is known only on the device).
 constexpr int64_t kRedoGrid = 1024;
+constexpr int64_t kRedoMergeGrid = 64;
 
-__global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, uint32_t *fail, int64_t n)
+__global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, uint32_t *fail, uint32_t *lcnt, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < 4)   // matrix-core tiles (M = 16, 32), other tiles, matrix-core tiles (M = 64), recomputation list
@@ -91,6 +93,7 @@ __global__ void batch_reset_kernel(uint32_t *counter, uint32_t *gthr, uint32_t *
     if (i < n) {
         gthr[i] = 0xFFFFu;
         fail[i] = 0u;
+        lcnt[i] = 0u;
     }
 }
 
@@ -111,6 +114,7 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     job.k = (uint32_t)db.k;
     job.largest = db.largest;
     job.fail = db.fail;
+    job.lcnt = MF && db.sdist ? db.lcnt : nullptr;
     if (MF) {
         // sampled bounds: barrier-free passes (overflow flags the query)
         if (db.sdist)
@@ -214,23 +218,29 @@ __global__ __launch_bounds__(256) void batch_select_kernel(const DevDb *__restri
 // Top k of one query from its candidate lists.  A query of a speculative
 // database with fewer than k candidates, or flagged by an overflowing
 // barrier-free tile, is listed for the exact recomputation instead: its
-// bound is opened, its flag becomes the count of its recomputed tiles, and
-// its index into `queries` is appended to redo (count in *redo_cnt).
+// bound is opened and its index into `queries` is appended to redo (count
+// in *redo_cnt).
 __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restrict__ dbs,
                                                           const DevQuery *__restrict__ queries,
                                                           uint32_t *__restrict__ redo_cnt,
                                                           uint32_t *__restrict__ redo)
 {
     __shared__ bolt::MergeLds L;
+    __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
     const DevQuery qq = queries[blockIdx.x];
     const DevDb db = dbs[qq.db];
     const int64_t per_query = db.n_rb * db.k;
     const uint32_t k = (uint32_t)db.k;
-    const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k, db.gthr[qq.q]);
+    // speculative databases: the dense list of the barrier-free tiles; others: padded slots
+    const uint64_t *src = db.cand + (int64_t)qq.q * per_query;
+    const uint32_t n =
+        db.sdist ? bolt::merge_collect_list(L, h, src,
+                                            (int64_t)db.lcnt[qq.q] < per_query ? (int64_t)db.lcnt[qq.q] : per_query, k,
+                                            bolt::hist_shift(db.M), db.gthr[qq.q])
+                 : bolt::merge_collect(L, src, 0, per_query, k, db.gthr[qq.q]);
     if (db.sdist && (n < k || db.fail[qq.q])) {
         if (threadIdx.x == 0) {
             db.gthr[qq.q] = 0xFFFFu;
-            db.fail[qq.q] = 0u;
             redo[atomicAdd(redo_cnt, 1u)] = blockIdx.x;
         }
         return;
@@ -243,19 +253,16 @@ __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restric
 // persistent loop is (listed query i / max_rb, row block i % max_rb), a
 // one-query tile from the open bound over that row block of the query's
 // database (items past the database's row blocks are skipped), writing its
-// local top k to the query's own candidate slot (free since the merge).  The
-// workgroup that completes a query's last row block (the count in its flag)
-// merges the query's slots below the published bound and writes the result.
-__global__ __launch_bounds__(256) void batch_redo_kernel(const DevDb *__restrict__ dbs,
-                                                         const DevQuery *__restrict__ queries,
-                                                         const uint32_t *__restrict__ redo_cnt,
-                                                         const uint32_t *__restrict__ redo, int64_t max_rb,
-                                                         int64_t rows_per_tile)
+// local top k to the query's own candidate slot (free since the merge).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_redo_scan_kernel(
+    const DevDb *__restrict__ dbs, const DevQuery *__restrict__ queries, const uint32_t *__restrict__ redo_cnt,
+    const uint32_t *__restrict__ redo, int64_t max_rb, int64_t rows_per_tile)
 {
-    __shared__ __attribute__((aligned(16))) char lds[bolt::few_tile_lds_bytes(64, 1)];
-    __shared__ bolt::MergeLds L;
-    __shared__ uint32_t s_last;
-    const int tid = threadIdx.x;
+    __shared__ __attribute__((aligned(16))) char lds[bolt::one_query_lds_bytes(64)];
+    static_assert(bolt::one_query_lds_bytes(64) >= bolt::one_query_lds_bytes(32) &&
+                      bolt::one_query_lds_bytes(64) >= bolt::one_query_lds_bytes(16) &&
+                      bolt::one_query_lds_bytes(64) >= bolt::one_query_lds_bytes(8),
+                  "one LDS buffer for every code size");
     const int64_t items = (int64_t)*redo_cnt * max_rb;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const DevQuery qq = queries[redo[it / max_rb]];
@@ -263,40 +270,40 @@ __global__ __launch_bounds__(256) void batch_redo_kernel(const DevDb *__restrict
         const int64_t rb = it % max_rb;
         if (rb >= db.n_rb)
             continue;   // uniform across the workgroup
-        bolt::TileJob job;
-        job.codes = db.codes;
-        job.luts = db.luts;
-        job.cand = db.cand;
-        job.gthr = db.gthr;
-        job.rb = rb;
-        job.r0 = rb * rows_per_tile;
-        job.r1 = (job.r0 + rows_per_tile) < db.N ? (job.r0 + rows_per_tile) : db.N;
-        job.n_rb = db.n_rb;
-        job.q0 = qq.q;
-        job.nq = 1;
-        job.k = (uint32_t)db.k;
-        job.largest = db.largest;
+        const int64_t r0 = rb * rows_per_tile;
+        const int64_t r1 = (r0 + rows_per_tile) < db.N ? (r0 + rows_per_tile) : db.N;
+        const uint8_t *lq = db.luts + (int64_t)qq.q * db.M * 16;
+        uint64_t *dst = db.cand + ((int64_t)qq.q * db.n_rb + rb) * db.k;
+        uint32_t *g = db.gthr + qq.q;
         switch (db.M) {
-        case 8: bolt::few_tile<8, true>(job, lds); break;
-        case 16: bolt::few_tile<16, true>(job, lds); break;
-        case 32: bolt::few_tile<32, true>(job, lds); break;
-        default: bolt::few_tile<64, true>(job, lds); break;
+        case 8: bolt::one_query_tile<8>(db.codes, r0, r1, lq, (uint32_t)db.k, db.largest, dst, nullptr, nullptr, g, lds); break;
+        case 16: bolt::one_query_tile<16>(db.codes, r0, r1, lq, (uint32_t)db.k, db.largest, dst, nullptr, nullptr, g, lds); break;
+        case 32: bolt::one_query_tile<32>(db.codes, r0, r1, lq, (uint32_t)db.k, db.largest, dst, nullptr, nullptr, g, lds); break;
+        default: bolt::one_query_tile<64>(db.codes, r0, r1, lq, (uint32_t)db.k, db.largest, dst, nullptr, nullptr, g, lds); break;
         }
-        __syncthreads();
-        if (tid == 0) {
-            __threadfence();   // this tile's keys before its completion
-            s_last = atomicAdd(&db.fail[qq.q], 1u) == (uint32_t)(db.n_rb - 1) ? 1u : 0u;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();   // every tile's keys of the query after their completions
-            const int64_t per_query = db.n_rb * db.k;
-            const uint32_t k = (uint32_t)db.k;
-            const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k,
-                                                   bolt::read_bound(&db.gthr[qq.q]));
-            bolt::merge_emit(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
-                             db.idx + (int64_t)qq.q * db.k);
-        }
+        __syncthreads();   // the tile's writer is done with lds
+    }
+}
+
+// Merge of the recomputed queries: workgroup w takes listed queries w,
+// w + grid, ...: the exact k smallest keys of the query's padded slots at or
+// below its published bound, sorted.
+__global__ __launch_bounds__(256) void batch_redo_merge_kernel(const DevDb *__restrict__ dbs,
+                                                               const DevQuery *__restrict__ queries,
+                                                               const uint32_t *__restrict__ redo_cnt,
+                                                               const uint32_t *__restrict__ redo)
+{
+    __shared__ bolt::MergeLds L;
+    const uint32_t n_redo = *redo_cnt;
+    for (uint32_t j = blockIdx.x; j < n_redo; j += gridDim.x) {
+        const DevQuery qq = queries[redo[j]];
+        const DevDb db = dbs[qq.db];
+        const int64_t per_query = db.n_rb * db.k;
+        const uint32_t k = (uint32_t)db.k;
+        const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k,
+                                               db.gthr[qq.q]);
+        bolt::merge_emit(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
+                         db.idx + (int64_t)qq.q * db.k);
         __syncthreads();
     }
 }
@@ -304,7 +311,8 @@ __global__ __launch_bounds__(256) void batch_redo_kernel(const DevDb *__restrict
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    size_t dbs_off, tiles_off, queries_off, gthr_off, fail_off, redo_off, counter_off, samples_off, cand_off, total;
+    size_t dbs_off, tiles_off, queries_off, gthr_off, fail_off, redo_off, lcnt_off, counter_off, samples_off, cand_off,
+        total;
     int64_t n_tiles, n_queries, n_samples, max_rb;
 };
 
@@ -415,6 +423,8 @@ Layout layout_of(const bolt_batch_db *dbs, int32_t n_db, int32_t rows, int32_t f
     off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
     L.redo_off = off;
     off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
+    L.lcnt_off = off;
+    off += align256(sizeof(uint32_t) * (size_t)(queries > 0 ? queries : 1));
     L.counter_off = off;
     off += 256;
     L.samples_off = off;
@@ -442,6 +452,7 @@ struct bolt_batch_plan {
     uint32_t *gthr = nullptr;
     uint32_t *fail = nullptr;
     uint32_t *redo = nullptr;      // queries listed for the recomputation (count in counter[3])
+    uint32_t *lcnt = nullptr;      // dense candidate list counts per query
     uint32_t *counter = nullptr;
     DevSample *samples = nullptr;
 };
@@ -487,6 +498,7 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
     p->gthr = reinterpret_cast<uint32_t *>(p->ws + L.gthr_off);
     p->fail = reinterpret_cast<uint32_t *>(p->ws + L.fail_off);
     p->redo = reinterpret_cast<uint32_t *>(p->ws + L.redo_off);
+    p->lcnt = reinterpret_cast<uint32_t *>(p->ws + L.lcnt_off);
     p->max_rb = L.max_rb;
     p->counter = reinterpret_cast<uint32_t *>(p->ws + L.counter_off);
     p->samples = reinterpret_cast<DevSample *>(p->ws + L.samples_off);
@@ -525,6 +537,7 @@ extern "C" int bolt_batch_plan_create(const bolt_batch_db *dbs, int32_t n_db,
         cand_off += align256((size_t)d.Q * o.n_rb * d.k * sizeof(uint64_t));
         o.gthr = p->gthr + qbase;
         o.fail = p->fail + qbase;
+        o.lcnt = p->lcnt + qbase;
         qbase += d.Q;
         const int kind = tile_kind(d, few_max);
         const int64_t nsc = spec_chunks(d, kind);
@@ -611,7 +624,7 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
     hipStream_t s = as_stream(stream);
     const int64_t nz = p->n_queries;
     hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, p->counter,
-                       p->gthr, p->fail, nz);
+                       p->gthr, p->fail, p->lcnt, nz);
     if (p->n_samples > 0) {   // speculative starting bounds
         bolt::ProfScope prof_("batch_spec", s);
         hipLaunchKernelGGL(batch_sample_kernel, dim3((unsigned)p->n_samples), dim3(256), 0, s, p->dbs, p->samples);
@@ -641,9 +654,12 @@ extern "C" int bolt_batch_run(const bolt_batch_plan *p, void *stream)
     if (p->n_samples > 0) {   // recomputation of failed sampled bounds (none: every workgroup exits at once)
         bolt::ProfScope prof_("batch_redo", s);
         const int64_t items = p->max_rb * p->n_queries;
-        hipLaunchKernelGGL(batch_redo_kernel, dim3((unsigned)(items < kRedoGrid ? items : kRedoGrid)), dim3(256),
-                           0, s, p->dbs, p->queries, p->counter + 3, p->redo, p->max_rb,
+        hipLaunchKernelGGL(batch_redo_scan_kernel, dim3((unsigned)(items < kRedoGrid ? items : kRedoGrid)),
+                           dim3(256), 0, s, p->dbs, p->queries, p->counter + 3, p->redo, p->max_rb,
                            (int64_t)p->rows_per_tile);
+        hipLaunchKernelGGL(batch_redo_merge_kernel,
+                           dim3((unsigned)(p->n_queries < kRedoMergeGrid ? p->n_queries : kRedoMergeGrid)), dim3(256),
+                           0, s, p->dbs, p->queries, p->counter + 3, p->redo);
     }
     return check_launch("bolt_batch_run");
 }

@@ -87,7 +87,8 @@ template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void few_scan_topk_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int nq, uint32_t k,
     int largest, int64_t rows_per_block, int n_rb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles,
+    uint32_t *__restrict__ lcnt)
 {
     extern __shared__ __attribute__((aligned(16))) char few_lds[];
     bolt::TileJob job;
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     job.cand = cand;
     job.ccnt = ccnt;
     job.hist = hist;
+    job.lcnt = lcnt;
     job.hist_shift = bolt::hist_shift(MM);
     job.gthr = gthr;
     job.rb = blockIdx.x;
@@ -115,81 +117,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
 }
 
 // One query (the HBM-bound case): one workgroup per tile of tile_rows rows;
-// the many small tiles let the dispatcher balance the load.  The tables are
-// static LDS at a fixed address, so their offsets fold into the reads; rows
-// are loaded with a uniform base and 32-bit lane offsets, unconditionally,
-// so the next pass stays in flight while this one is computed.  Each tile
+// the many small tiles let the dispatcher balance the load.  Each tile
 // writes its exact local top-k to cand[tile][k] (packed, count in
-// ccnt[tile] and keys counted in hist, when ccnt is given).
+// ccnt[tile] and keys counted in hist, when ccnt is given), or appends it
+// to the dense list cand (count in *lcnt) when lcnt is given; see
+// bolt::one_query_tile.
 template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void one_scan_topk_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k,
     int largest, int64_t tile_rows, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
-    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles)
+    uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles,
+    uint32_t *__restrict__ lcnt)
 {
-    constexpr int R = bolt::few_r(MM);
-    constexpr int PASS = bolt::few_pass(MM);
-    constexpr int CAP = bolt::few_cap(MM);
-    constexpr uint32_t SMAX = 255u * MM;
-    __shared__ __attribute__((aligned(16))) uint16_t pt[(MM / 2) * 256];
-    __shared__ __attribute__((aligned(16))) uint32_t buf[CAP];
-    __shared__ uint32_t s_cnt, s_bnd;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ __attribute__((aligned(16))) char lds[bolt::one_query_lds_bytes(MM)];
     const int64_t tile = blockIdx.x;
     const int64_t r0 = tiles ? tiles[2 * tile] : tile * tile_rows;
     const int64_t r1 = tiles ? tiles[2 * tile + 1] : ((r0 + tile_rows) < N ? (r0 + tile_rows) : N);
-    uint32_t cw[R][MM / 8], nx[R][MM / 8];
-    load_rows_clamped<MM, R>(codes, r0, r1, nx);
-    build_pair_tables<MM>(luts, 1, pt, reinterpret_cast<uint8_t *>(buf));
-    if (tid == 0) {
-        s_cnt = 0;
-        s_bnd = read_bound(gthr) + 1u;
-    }
-    __syncthreads();
-    int pass = 0;
-    for (int64_t base = r0; base < r1; base += PASS, ++pass) {
-        copy_rows<MM, R>(nx, cw);
-        if (base + PASS < r1)
-            load_rows_clamped<MM, R>(codes, base + PASS, r1, nx);
-        uint32_t s[R];
-        pair_sums<MM, R, true>(reinterpret_cast<const char *>(pt), cw, s);
-        const uint32_t bq = s_bnd;
-        const uint32_t loc = (uint32_t)(base - r0) + (uint32_t)tid;
-        const uint32_t lim = (uint32_t)((r1 - base) < PASS ? (r1 - base) : PASS);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t d = largest ? SMAX - s[r] : s[r];
-            if (d < bq && (uint32_t)tid + 256u * r < lim) {
-                const uint32_t pos = atomicAdd(&s_cnt, 1u);
-                buf[pos] = local_key(d, loc + 256u * r);
-            }
-        }
-        __syncthreads();
-        if (wave == 0) {
-            const uint32_t c = s_cnt;
-            uint32_t nb = 0xFFFFFFFFu;
-            if (c > CAP - PASS) {
-                PruneResult pr = bolt::prune_local_lds<CAP>(buf, c, k, false);
-                if (pr.count > CAP - PASS)
-                    pr = bolt::prune_local_lds<CAP>(buf, pr.count, k, true);
-                if (lane == 0) {
-                    s_cnt = pr.count;
-                    bolt::publish(gthr, pr.T, s_bnd);
-                }
-                nb = pr.T;
-            }
-            if (lane == 0 && (nb != 0xFFFFFFFFu || (pass & 7) == 7)) {
-                uint32_t b = s_bnd;
-                b = nb < b ? nb : b;
-                const uint32_t gb = read_bound(gthr) + 1u;
-                s_bnd = gb < b ? gb : b;
-            }
-        }
-        __syncthreads();
-    }
-    if (wave == 0)
-        bolt::write_local_topk<CAP, true>(buf, s_cnt, k, r0, cand + tile * k, gthr, s_bnd,
-                                          ccnt ? ccnt + tile : nullptr, hist, bolt::hist_shift(MM));
+    if (lcnt)
+        bolt::one_query_tile<MM>(codes, r0, r1, luts, k, largest, cand, nullptr, nullptr, gthr, lds, lcnt);
+    else
+        bolt::one_query_tile<MM>(codes, r0, r1, luts, k, largest, cand + tile * k, ccnt ? ccnt + tile : nullptr,
+                                 hist, gthr, lds);
 }
 
 size_t few_lds_bytes(int M, int nq, bool fused)
@@ -216,15 +164,15 @@ void launch_few_scan(const uint8_t *codes, int64_t N, const uint8_t *luts, int n
 template <int MM>
 void launch_few_scan_topk(const uint8_t *codes, int64_t N, const uint8_t *luts, int nq, int k, bool largest,
                           int64_t rpb, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
-                          const int64_t *tiles, hipStream_t s)
+                          const int64_t *tiles, uint32_t *lcnt, hipStream_t s)
 {
     if (nq == 1)
         hipLaunchKernelGGL(one_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), 0, s, codes, N, luts, (uint32_t)k,
-                           (int)largest, rpb, cand, ccnt, hist, gthr, tiles);
+                           (int)largest, rpb, cand, ccnt, hist, gthr, tiles, lcnt);
     else
         hipLaunchKernelGGL(few_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), few_lds_bytes(MM, nq, true), s,
                            codes, N, luts, nq, (uint32_t)k, (int)largest, rpb, n_rb, cand, ccnt, hist, gthr,
-                           tiles);
+                           tiles, lcnt);
 }
 
 template <int MM>
@@ -331,16 +279,20 @@ int64_t few_rows_per_block(int64_t N, int M, int nq)
 // counts [Q][n_rb] in ccnt and histograms in hist, if given) and bounds.
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
                   bool largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
-                  const int64_t *tiles, hipStream_t s)
+                  const int64_t *tiles, uint32_t *lcnt, hipStream_t s)
 {
     const int nq = (int)Q;
     const int64_t rpb = few_rows_per_block(N, M, nq);
     bolt::ProfScope prof_("scan_topk_few", s);
     switch (M) {
-    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
-    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
-    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
-    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, s); break;
+    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+                                    s); break;
+    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+                                    s); break;
+    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+                                    s); break;
+    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+                                    s); break;
     default: return fail(BOLT_ERR_UNSUPPORTED, "few-query scan takes M in {8, 16, 32, 64}");
     }
     return BOLT_OK;

@@ -75,7 +75,7 @@ __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uin
                                          const uint8_t *luts, int64_t Q, uint32_t k, int largest, int n_rb,
                                          uint64_t *cand, uint32_t *ccnt, uint32_t *hist, int shift,
                                          uint32_t *fail, uint32_t *gthr, const int64_t *tiles, int64_t stride,
-                                         int64_t span, bolt::TileJob &job)
+                                         int64_t span, uint32_t *lcnt, bolt::TileJob &job)
 {
     int qb, rb;
     tile_of(w, n_qb, qb, rb);
@@ -88,6 +88,7 @@ __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uin
     job.hist = hist;
     job.hist_shift = shift;
     job.fail = fail;
+    job.lcnt = lcnt;
     job.gthr = gthr;
     if (tiles) {   // row ranges given by the caller, cut into tiles
         job.r0 = tiles[2 * rb];
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
     __shared__ bolt::GroupedLds<MM, NG> L;
     bolt::TileJob job;
     if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
-                 bolt::hist_shift(MM), fail, gthr, tiles, stride, span, job))
+                 bolt::hist_shift(MM), fail, gthr, tiles, stride, span, nullptr, job))
         bolt::grouped_tile<MM, NG>(job, L);
 }
 
@@ -127,26 +128,24 @@ __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
     uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
     uint32_t *__restrict__ hist, uint32_t *__restrict__ fail, uint32_t *__restrict__ gthr,
-    const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
+    const int64_t *__restrict__ tiles, int64_t stride, int64_t span, uint32_t *__restrict__ lcnt)
 {
     __shared__ bolt::MfmaLds<NT> L;
     bolt::TileJob job;
     if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
-                 bolt::hist_shift(MM), fail, gthr, tiles, stride, span, job))
+                 bolt::hist_shift(MM), fail, gthr, tiles, stride, span, lcnt, job))
         bolt::mfma_tile<MM, NT, FREE, SP>(job, L);
 }
 
 // ------------------------------------------------------------------ merge
 
 // Lists query q for the exact recomputation (stage 3): its bound is opened
-// (every d passes), its overflow flag becomes the count of its recomputed
-// tiles, and q is appended to redo[2 ...] (redo[0] counts the list).  Called
-// by the one workgroup that finishes the query's merge.
-__device__ void flag_redo(int64_t q, uint32_t *gthr, uint32_t *fail, uint32_t *redo)
+// (every d passes) and q is appended to redo[2 ...] (redo[0] counts the
+// list).  Called by the one workgroup that finishes the query's merge.
+__device__ void flag_redo(int64_t q, uint32_t *gthr, uint32_t *redo)
 {
     if (threadIdx.x == 0) {
         gthr[q] = 0xFFFFu;
-        fail[q] = 0u;
         const uint32_t pos = atomicAdd(&redo[0], 1u);
         redo[2 + pos] = (uint32_t)q;
     }
@@ -263,7 +262,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
     __syncthreads();
     if (gridDim.y == 1) {
         if (fail && (n < k || fail[q]))
-            flag_redo(q, gthr, fail, redo);
+            flag_redo(q, gthr, redo);
         else
             bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
         return;
@@ -297,7 +296,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     const uint32_t n = merge_walk(L, pre, src + q * (int64_t)n_chunks * k, src_cnt + q * (int64_t)n_chunks, 0,
                                   n_chunks, k);
     if (fail && (n < k || fail[q])) {
-        flag_redo(q, gthr, fail, redo);
+        flag_redo(q, gthr, redo);
         return;
     }
     if (tid < 64 && n > k)
@@ -306,73 +305,88 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
 }
 
+// Merge of the dense candidate lists (sampled bounds on the pair-table and
+// matrix-core tiles; one launch, one workgroup per query): the exact k
+// smallest of the lcnt[q] keys of cand[q], sorted.  A query with fewer than
+// k keys (its sampled bound failed) or whose barrier-free tile overflowed
+// is listed for the recomputation.
+__global__ __launch_bounds__(256) void topk_list_merge_kernel(const uint64_t *__restrict__ cand,
+                                                              const uint32_t *__restrict__ lcnt, int64_t per_query,
+                                                              uint32_t k, int shift, uint32_t *__restrict__ gthr,
+                                                              int largest,
+                                                              uint32_t smax, uint16_t *__restrict__ vals,
+                                                              int32_t *__restrict__ idx, uint32_t *__restrict__ fail,
+                                                              uint32_t *__restrict__ redo)
+{
+    __shared__ bolt::MergeLds L;
+    __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
+    const int64_t q = blockIdx.x;
+    const uint32_t c = lcnt[q];
+    const int64_t n_keys = (int64_t)c < per_query ? (int64_t)c : per_query;
+    const uint32_t n = bolt::merge_collect_list(L, h, cand + q * per_query, n_keys, k, shift, gthr[q]);
+    if (n < k || fail[q])
+        flag_redo(q, gthr, redo);
+    else
+        bolt::merge_emit(L, n, k, largest, smax, vals + q * k, idx + q * k);
+}
+
 // Stage 3: exact recomputation of the listed queries (redo[0] of them, at
 // redo[2 ...]) on the whole GPU.  Item i of the persistent loop is (listed
 // query i / n_rb, tile i % n_rb): a one-query tile over the tile's rows from
 // the query's open bound, publishing pruned bounds to the query's other
 // tiles and writing its local top-k to the query's own candidate slot
-// (free since the merge).  The workgroup that completes a query's last tile
-// (its count in fail[q]) merges the n_rb slots below the published bound
-// and writes the sorted result.  With an empty list every workgroup exits
-// at once.
+// (free since the merge).  With an empty list every workgroup exits at
+// once.
 template <int MM>
-__global__ __launch_bounds__(256) void topk_redo_kernel(const uint8_t *__restrict__ codes, int64_t N,
-                                                        const uint8_t *__restrict__ luts, uint32_t k, int largest,
-                                                        int64_t n_rb, int64_t rpb, const int64_t *__restrict__ tiles,
-                                                        uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
-                                                        uint32_t *fail, const uint32_t *__restrict__ redo,
-                                                        uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void topk_redo_scan_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k, int largest,
+    int64_t n_rb, int64_t rpb, const int64_t *__restrict__ tiles, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
+    const uint32_t *__restrict__ redo)
 {
-    extern __shared__ __attribute__((aligned(16))) char redo_lds[];
-    __shared__ bolt::MergeLds L;
-    __shared__ uint32_t pre[257];
-    __shared__ uint32_t s_last;
-    const int tid = threadIdx.x;
+    __shared__ __attribute__((aligned(16))) char lds[bolt::one_query_lds_bytes(MM)];
     const int64_t items = (int64_t)redo[0] * n_rb;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const int64_t q = redo[2 + it / n_rb];
         const int64_t rb = it % n_rb;
-        bolt::TileJob job;
-        job.codes = codes;
-        job.luts = luts;
-        job.cand = cand;
-        job.ccnt = ccnt;
-        job.hist = nullptr;
-        job.fail = nullptr;
-        job.gthr = gthr;
+        int64_t r0, r1;
         if (tiles) {
-            job.r0 = tiles[2 * rb];
-            job.r1 = tiles[2 * rb + 1];
+            r0 = tiles[2 * rb];
+            r1 = tiles[2 * rb + 1];
         } else {
-            job.r0 = rb * rpb;
-            job.r1 = (job.r0 + rpb) < N ? (job.r0 + rpb) : N;
+            r0 = rb * rpb;
+            r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
         }
-        job.rb = rb;
-        job.n_rb = n_rb;
-        job.q0 = q;
-        job.nq = 1;
-        job.k = k;
-        job.largest = largest;
-        bolt::few_tile<MM, true>(job, redo_lds);
+        bolt::one_query_tile<MM>(codes, r0, r1, luts + q * MM * 16, k, largest, cand + (q * n_rb + rb) * k,
+                                 ccnt + q * n_rb + rb, nullptr, gthr + q, lds);
+        __syncthreads();   // the tile's writer is done with lds
+    }
+}
+
+// Stage 3, merge: workgroup w takes listed queries w, w + grid, ...: the
+// keys of all n_rb slots of the query at or below its published bound, the
+// exact k smallest, sorted.
+__global__ __launch_bounds__(256) void topk_redo_merge_kernel(const uint64_t *__restrict__ cand,
+                                                              const uint32_t *__restrict__ ccnt, int64_t n_rb,
+                                                              uint32_t k, const uint32_t *__restrict__ gthr,
+                                                              int largest, uint32_t smax,
+                                                              const uint32_t *__restrict__ redo,
+                                                              uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+{
+    __shared__ bolt::MergeLds L;
+    __shared__ uint32_t pre[257];
+    const uint32_t n_redo = redo[0];
+    for (uint32_t j = blockIdx.x; j < n_redo; j += gridDim.x) {
+        const int64_t q = redo[2 + j];
+        if (threadIdx.x == 0) {
+            L.mcnt = 0;
+            L.mbound = ((uint64_t)gthr[q] + 1u) << 32;   // keys with d <= bound
+        }
         __syncthreads();
-        if (tid == 0) {
-            __threadfence();   // this tile's keys and count before its completion
-            s_last = atomicAdd(&fail[q], 1u) == (uint32_t)(n_rb - 1) ? 1u : 0u;
-        }
+        const uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, 0, n_rb, k);
+        if (threadIdx.x < 64 && n > k)
+            bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
         __syncthreads();
-        if (s_last) {
-            __threadfence();   // every tile's keys of q after their completions
-            if (tid == 0) {
-                L.mcnt = 0;
-                L.mbound = ((uint64_t)bolt::read_bound(&gthr[q]) + 1u) << 32;   // keys with d <= bound
-            }
-            __syncthreads();
-            const uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, 0, n_rb, k);
-            if (tid < 64 && n > k)
-                bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
-            __syncthreads();
-            bolt::merge_emit(L, n > k ? k : n, k, largest, 255u * MM, vals + q * k, idx + q * k);
-        }
+        bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
         __syncthreads();
     }
 }
@@ -446,24 +460,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
 // Speculative bound of one query (one workgroup): the r-th smallest of its
 // G sample group minima (r distinct sample rows lie at or below it), written
 // as the query's starting bound (0 when a test forces every query onto the
-// recomputation).  Also clears the query's candidate histogram and overflow
-// flag, and the recomputation list (this kernel replaces the initialisation
-// when the bounds are speculative).
+// recomputation).  Also clears the query's overflow flag and candidate
+// histogram (or, for dense candidate lists, the list's count) and the
+// recomputation list (this kernel replaces the initialisation when the
+// bounds are speculative).
 __global__ __launch_bounds__(256) void spec_select_kernel(const uint16_t *__restrict__ gmins, int64_t G,
                                                           uint32_t r, int shift, uint32_t *__restrict__ gthr,
                                                           uint32_t *__restrict__ hist, uint32_t *__restrict__ fail,
-                                                          uint32_t *__restrict__ redo, int force_fail)
+                                                          uint32_t *__restrict__ redo, uint32_t *__restrict__ lcnt,
+                                                          int force_fail)
 {
     __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
     const int64_t q = blockIdx.x;
     if (q == 0 && threadIdx.x == 0)
         redo[0] = 0u;   // the recomputation list starts empty
-    for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
-        hist[q * bolt::kHistBins + i] = 0;
+    if (!lcnt)   // dense candidate lists need no histogram
+        for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+            hist[q * bolt::kHistBins + i] = 0;
     const uint32_t b = bolt::select_rank_u16(gmins + q * G, G, r, shift, h);
     if (threadIdx.x == 0) {
         gthr[q] = force_fail ? 0u : b;
         fail[q] = 0u;
+        if (lcnt)
+            lcnt[q] = 0u;
     }
 }
 
@@ -578,8 +597,9 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
                                     : 0;
     if (p.n_chunks > 65535)
         return p;
+    // sample minima, overflow flags and (matrix-core tiles) dense list counts
     p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * bolt::kSpecGroups * sizeof(uint16_t)) +
-                                align256((size_t)Q * sizeof(uint32_t))
+                                align256((size_t)Q * sizeof(uint32_t)) * (p.kind != 2 ? 2 : 1)
                           : 0;
     p.redo_bytes = p.spec ? align256((size_t)(Q + 2) * sizeof(uint32_t)) : 0;
     p.ok = true;
@@ -601,11 +621,11 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 template <int MM>
 void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k,
                  int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *fail,
-                 uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name,
-                 hipStream_t s)
+                 uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, uint32_t *lcnt,
+                 const char *prof_name, hipStream_t s)
 {
     if (p.kind == 1) {   // profiled inside under its own name
-        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, ccnt, hist, gthr, tiles, s);
+        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, ccnt, hist, gthr, tiles, lcnt, s);
         return;
     }
     const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
@@ -613,7 +633,7 @@ void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint
 #define BOLT_MFMA_SCAN(FREE, SP)                                                                                  \
     hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, kMfmaNT, FREE, SP>), dim3(grid), dim3(256), 0, s, codes, N,    \
                        luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles, stride, \
-                       span)
+                       span, FREE ? lcnt : nullptr)
     const bool sp = bolt::g_sparse_mfma != 0;
     if (p.kind == 3 && p.spec && sp)
         BOLT_MFMA_SCAN(true, true);
@@ -632,12 +652,12 @@ void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint
 
 void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
                    int k, int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *fail,
-                   uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, const char *prof_name,
-                   hipStream_t s)
+                   uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, uint32_t *lcnt,
+                   const char *prof_name, hipStream_t s)
 {
 #define BOLT_SCAN_M(MMV)                                                                                         \
     launch_scan<MMV>(p, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist, fail, gthr, tiles, stride, span,  \
-                     prof_name, s)
+                     lcnt, prof_name, s)
     switch (M) {
     case 8: BOLT_SCAN_M(8); break;
     case 16: BOLT_SCAN_M(16); break;
@@ -668,20 +688,20 @@ void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_
 #undef BOLT_SAMPLE_M
 }
 
-// Stage 3 launch: a persistent grid of at most kRedoGrid workgroups (the
-// list's length is known only on the device).
+// Stage 3 launches: a persistent scan grid of at most kRedoGrid workgroups
+// (the list's length is known only on the device), then the merge.
 constexpr int64_t kRedoGrid = 1024;
+constexpr int64_t kRedoMergeGrid = 64;
 
 void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k, int largest,
                  const FusedPlan &p, const int64_t *tiles, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
-                 uint32_t *fail, const uint32_t *redo, uint16_t *vals, int32_t *idx, hipStream_t s)
+                 const uint32_t *redo, uint16_t *vals, int32_t *idx, hipStream_t s)
 {
     const int64_t items = (int64_t)p.n_rb * Q;
     const dim3 grid((unsigned)(items < kRedoGrid ? items : kRedoGrid));
-    const size_t lds = bolt::few_tile_lds_bytes(M, 1);
 #define BOLT_REDO_M(MM)                                                                                          \
-    hipLaunchKernelGGL(topk_redo_kernel<MM>, grid, dim3(256), lds, s, codes, N, luts, (uint32_t)k, largest,     \
-                       (int64_t)p.n_rb, p.rpb, tiles, cand, ccnt, gthr, fail, redo, vals, idx)
+    hipLaunchKernelGGL(topk_redo_scan_kernel<MM>, grid, dim3(256), 0, s, codes, N, luts, (uint32_t)k, largest,   \
+                       (int64_t)p.n_rb, p.rpb, tiles, cand, ccnt, gthr, redo)
     switch (M) {
     case 8: BOLT_REDO_M(8); break;
     case 16: BOLT_REDO_M(16); break;
@@ -689,6 +709,9 @@ void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, in
     case 64: BOLT_REDO_M(64); break;
     }
 #undef BOLT_REDO_M
+    hipLaunchKernelGGL(topk_redo_merge_kernel, dim3((unsigned)(Q < kRedoMergeGrid ? Q : kRedoMergeGrid)), dim3(256),
+                       0, s, cand, ccnt, (int64_t)p.n_rb, (uint32_t)k, gthr, largest, 255u * (uint32_t)M, redo, vals,
+                       idx);
 }
 
 const char *scan_prof_name(int kind)
@@ -759,6 +782,10 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     uint32_t *fail = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + align256((size_t)Q * G * sizeof(uint16_t)))
                             : nullptr;
     uint32_t *redo = p.spec ? reinterpret_cast<uint32_t *>(ws_spec + p.spec_bytes) : nullptr;
+    // sampled bounds on the pair-table and matrix-core tiles: dense
+    // per-query candidate lists
+    const bool lists = p.spec && p.kind != 2;
+    uint32_t *lcnt = lists ? fail + align256((size_t)Q * sizeof(uint32_t)) / sizeof(uint32_t) : nullptr;
     if (p.spec) {
         // sample group minima, then each query's starting bound (and cleared histogram)
         {
@@ -767,7 +794,7 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         }
         bolt::ProfScope prof_("spec_select", s);
         hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, gmins, G, (uint32_t)p.spec_r,
-                           bolt::hist_shift(M), gthr, hist, fail, redo, bolt::g_spec_mode == 2 ? 1 : 0);
+                           bolt::hist_shift(M), gthr, hist, fail, redo, lcnt, bolt::g_spec_mode == 2 ? 1 : 0);
     } else {
         const int64_t n_hist = Q * bolt::kHistBins;
         hipLaunchKernelGGL(init_bounds_kernel, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, gthr, Q,
@@ -776,15 +803,20 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     // with speculative bounds (a few keys per tile and query) the tiles count
     // their kept keys into hist as they write them; otherwise a separate
     // kernel aggregates the counts per workgroup first
-    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, p.spec ? hist : nullptr, fail,
-                  gthr, tiles, kRowsPerBlock, kRowsPerBlock, scan_prof_name(p.kind), s);
+    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, p.spec && !lists ? hist : nullptr,
+                  fail, gthr, tiles, kRowsPerBlock, kRowsPerBlock, lcnt, scan_prof_name(p.kind), s);
     if (!p.spec) {
         bolt::ProfScope prof_("cand_hist", s);
         hipLaunchKernelGGL(cand_hist_kernel, dim3((unsigned)Q, (unsigned)((p.n_rb + 255) / 256)), dim3(256), 0, s,
                            cand, ccnt, (int64_t)p.n_rb, (uint32_t)k, bolt::hist_shift(M), hist);
     }
     const uint32_t smax = 255u * (uint32_t)M;
-    {
+    if (lists) {
+        bolt::ProfScope prof_("topk_merge", s);
+        hipLaunchKernelGGL(topk_list_merge_kernel, dim3((unsigned)Q), dim3(256), 0, s, cand, lcnt,
+                           (int64_t)p.n_rb * k, (uint32_t)k, bolt::hist_shift(M), gthr, (int)largest, smax, vals, idx,
+                           fail, redo);
+    } else {
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand, ccnt,
                            (int64_t)p.n_rb, p.n_chunks > 1 ? p.chunk : (int64_t)p.n_rb, (uint32_t)k, gthr, hist,
@@ -795,7 +827,7 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     }
     if (p.spec) {
         bolt::ProfScope prof_("topk_redo", s);
-        launch_redo(M, codes, N, luts, Q, k, (int)largest, p, tiles, cand, ccnt, gthr, fail, redo, vals, idx, s);
+        launch_redo(M, codes, N, luts, Q, k, (int)largest, p, tiles, cand, ccnt, gthr, redo, vals, idx, s);
     }
     return check_launch("bolt_scan_topk (fused)");
 }

@@ -40,7 +40,7 @@ int64_t few_rows_per_block(int64_t N, int M, int nq);
 size_t few_fused_lds_bytes(int M, int nq);
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
                   bool largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
-                  const int64_t *tiles, hipStream_t s);
+                  const int64_t *tiles, uint32_t *lcnt, hipStream_t s);
 
 // Test hook: 1 forces the unfused scan-then-select path of bolt_scan_topk.
 extern int g_force_unfused_topk;

@@ -51,6 +51,8 @@ struct TileJob {
     uint32_t *hist = nullptr;   // with ccnt: per-query histograms [Q][kHistBins] of the kept keys
     int hist_shift = 0;
     uint32_t *fail = nullptr;   // per-query flags [Q]: set when a barrier-free tile overflows
+    uint32_t *lcnt = nullptr;   // with sampled bounds: per-query dense candidate lists, cand[q] holding
+                                // lcnt[q] keys back to back (instead of slots per row block)
     uint32_t *gthr;         // the database's bounds [Q]
     int64_t r0, r1;         // rows of the tile
     int64_t rb;             // row-block index of the tile
@@ -90,11 +92,14 @@ __device__ __forceinline__ void publish(uint32_t *g, uint32_t T, uint32_t known)
 // *cnt_dst (readers walk only that part), and with hist_q each kept key is
 // also counted in the query's histogram (bin d >> shift); without cnt_dst
 // all k slots are written, the dropped keys as padding (~0) that the
-// readers skip.
+// readers skip.  With list_cnt the kept keys are appended to the query's
+// dense list dst instead, at a position reserved with one atomic add on
+// *list_cnt (the list holds every tile's keys back to back).
 template <int CAP, bool LDS_PRUNE>
 __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t r0,
                                  uint64_t *__restrict__ dst, uint32_t *gthr_q, uint32_t known,
-                                 uint32_t *cnt_dst = nullptr, uint32_t *hist_q = nullptr, int shift = 0)
+                                 uint32_t *cnt_dst = nullptr, uint32_t *hist_q = nullptr, int shift = 0,
+                                 uint32_t *list_cnt = nullptr)
 {
     const int lane = threadIdx.x & 63;
     if (n > k) {
@@ -105,6 +110,29 @@ __device__ void write_local_topk(uint32_t *buf, uint32_t n, uint32_t k, int64_t 
             publish(gthr_q, pr.T, known);
     }
     const uint32_t g = __builtin_amdgcn_readfirstlane(read_bound(gthr_q));
+    if (list_cnt) {
+        uint32_t m = 0;
+        for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            m += ballot_count(j < n && (buf[j < n ? j : 0] >> 16) <= g);
+        }
+        if (m == 0)
+            return;
+        uint32_t at = 0;
+        if (lane == 0)
+            at = atomicAdd(list_cnt, m);
+        at = __builtin_amdgcn_readfirstlane(at);
+        for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const uint32_t lk = j < n ? buf[j] : 0xFFFFFFFFu;
+            const bool keep = j < n && (lk >> 16) <= g;
+            const uint32_t r = ballot_rank(keep);
+            if (keep)
+                dst[at + r] = ((uint64_t)(lk >> 16) << 32) | (uint64_t)(r0 + (lk & 0xFFFFu));
+            at += ballot_count(keep);
+        }
+        return;
+    }
     if (cnt_dst) {
         uint32_t m = 0;
         for (uint32_t j0 = 0; j0 < n; j0 += 64) {
@@ -642,6 +670,23 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
             L.seg[(32 * t + col) * kMfmaSegs + sg] = pc[t];
         __syncthreads();   // every append is done
     }
+    // dense lists: reserve each query's place now (its count is known from
+    // the segment counts: min(n, k), 0 on overflow), so that the atomic's
+    // round trip overlaps the packing below; the offset is used after it
+    uint32_t list_at = 0;
+    if (FREE && job.lcnt && tid < nq && tid < QB) {
+        uint32_t n = 0;
+        bool over = false;
+#pragma unroll
+        for (int g = 0; g < kMfmaSegs; ++g) {
+            const uint32_t c = L.seg[tid * kMfmaSegs + g];
+            over = over || c > (uint32_t)kMfmaSeg;
+            n += c;
+        }
+        const uint32_t m = over ? 0u : (n < k ? n : k);
+        if (m)
+            list_at = atomicAdd(job.lcnt + q0 + tid, m);
+    }
     for (int q = wave; q < nq && q < QB; q += 4) {
         if (FREE) {
             // pack the segments in place: a wave reads all of the query's
@@ -650,8 +695,9 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
             if (__ballot(c > (uint32_t)kMfmaSeg)) {   // overflowed: no keys, the merge recomputes the query
                 if (lane == 0) {
                     job.fail[q0 + q] = 1u;
-                    if (job.ccnt)
+                    if (job.ccnt && !job.lcnt)
                         job.ccnt[(q0 + q) * job.n_rb + job.rb] = 0u;
+                    L.cnt[q] = 0u;
                 }
                 continue;
             }
@@ -686,11 +732,36 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
             if (lane == 0)
                 L.cnt[q] = n;
         }
+        if (FREE && job.lcnt) {
+            // dense lists: keep at most k keys (all of them are below the
+            // query's fixed bound); their place in the list is reserved below
+            if (L.cnt[q] > k) {
+                const PruneResult pr = prune_local<CAP>(L.buf + q * CAP, L.cnt[q], k, true);
+                if (lane == 0)
+                    L.cnt[q] = pr.count;
+            }
+            continue;
+        }
         write_local_topk<CAP, false>(L.buf + q * CAP, L.cnt[q], k, r0,
                                      job.cand + ((q0 + q) * job.n_rb + job.rb) * (int64_t)k,
                                      &job.gthr[q0 + q], L.bnd[q],
                                      job.ccnt ? job.ccnt + (q0 + q) * job.n_rb + job.rb : nullptr,
                                      job.hist ? job.hist + (q0 + q) * kHistBins : nullptr, job.hist_shift);
+    }
+    if (FREE && job.lcnt) {
+        // the keys of each query in one contiguous run at its reserved place
+        __syncthreads();
+        if (tid < nq && tid < QB)
+            L.bnd[tid] = list_at;
+        __syncthreads();
+        for (int q = wave; q < nq && q < QB; q += 4) {
+            const uint32_t n = L.cnt[q], at = L.bnd[q];
+            uint64_t *dst = job.cand + (q0 + q) * job.n_rb * (int64_t)k + at;
+            for (uint32_t j = lane; j < n; j += 64) {
+                const uint32_t lk = L.buf[q * CAP + j];
+                dst[j] = ((uint64_t)(lk >> 16) << 32) | (uint64_t)(r0 + (lk & 0xFFFFu));
+            }
+        }
     }
 }
 
@@ -925,6 +996,100 @@ __device__ __forceinline__ void copy_rows(const uint32_t (&a)[R][MM / 8], uint32
             b[r][v] = a[r][v];
 }
 
+// Exact local top-k of one query over rows [r0, r1) of codes (at most 65536
+// rows), one 256-thread workgroup: the pair tables of the query's tables
+// luts ([M][16]) are static LDS at a fixed address, so their offsets fold
+// into the reads; rows are loaded with a uniform base and 32-bit lane
+// offsets, unconditionally, so the next pass stays in flight while this one
+// is computed.  Keys below the bound (from *gthr, refreshed every 8 passes
+// and lowered by pruning, published to *gthr) go to an LDS buffer; the
+// kept keys (d << 32 | row) are written packed to dst with their count in
+// *cnt_dst and counted in hist (when cnt_dst is given), else as k padded
+// slots, or appended to the dense list dst with its count in *list_cnt
+// when list_cnt is given.  lds: one_query_lds_bytes(MM) bytes, 16-byte aligned (a static
+// array, so that the table offsets stay compile-time constants).  Wave 0
+// still writes the result when the other waves return: a caller that
+// reuses lds must synchronise first.
+// Rows per lane per pass of the one-query tile (its codes in flight per lane:
+// R M / 2 bytes; 128 at M = 32, measured 4% faster than 64 over 2.5e8 rows,
+// 64 at M = 16 where 96 was slower), a pass and the candidate buffer (a
+// pass plus room for k <= 256 and slack).
+__host__ __device__ constexpr int one_r(int M) { return M == 32 ? 8 : (M > 32 ? 4 : 8); }
+__host__ __device__ constexpr int one_pass(int M) { return 256 * one_r(M); }
+__host__ __device__ constexpr int one_cap(int M) { return one_pass(M) + 1024; }
+
+__host__ __device__ constexpr size_t one_query_lds_bytes(int M)
+{
+    return (size_t)(M / 2) * 256 * sizeof(uint16_t) + (size_t)one_cap(M) * sizeof(uint32_t);
+}
+
+template <int MM>
+__device__ __forceinline__ void one_query_tile(const uint8_t *__restrict__ codes, int64_t r0, int64_t r1,
+                                               const uint8_t *__restrict__ luts, uint32_t k, int largest,
+                                               uint64_t *__restrict__ dst, uint32_t *cnt_dst, uint32_t *hist,
+                                               uint32_t *gthr, char *lds, uint32_t *list_cnt = nullptr)
+{
+    constexpr int R = one_r(MM);
+    constexpr int PASS = one_pass(MM);
+    constexpr int CAP = one_cap(MM);
+    constexpr uint32_t SMAX = 255u * MM;
+    uint16_t *pt = reinterpret_cast<uint16_t *>(lds);
+    uint32_t *buf = reinterpret_cast<uint32_t *>(lds + (MM / 2) * 256 * sizeof(uint16_t));
+    __shared__ uint32_t s_cnt, s_bnd;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t cw[R][MM / 8], nx[R][MM / 8];
+    load_rows_clamped<MM, R>(codes, r0, r1, nx);
+    build_pair_tables<MM>(luts, 1, pt, reinterpret_cast<uint8_t *>(buf));
+    if (tid == 0) {
+        s_cnt = 0;
+        s_bnd = read_bound(gthr) + 1u;
+    }
+    __syncthreads();
+    int pass = 0;
+    for (int64_t base = r0; base < r1; base += PASS, ++pass) {
+        copy_rows<MM, R>(nx, cw);
+        if (base + PASS < r1)
+            load_rows_clamped<MM, R>(codes, base + PASS, r1, nx);
+        uint32_t s[R];
+        pair_sums<MM, R, true>(reinterpret_cast<const char *>(pt), cw, s);
+        const uint32_t bq = s_bnd;
+        const uint32_t loc = (uint32_t)(base - r0) + (uint32_t)tid;
+        const uint32_t lim = (uint32_t)((r1 - base) < PASS ? (r1 - base) : PASS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t d = largest ? SMAX - s[r] : s[r];
+            if (d < bq && (uint32_t)tid + 256u * r < lim) {
+                const uint32_t pos = atomicAdd(&s_cnt, 1u);
+                buf[pos] = local_key(d, loc + 256u * r);
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const uint32_t c = s_cnt;
+            uint32_t nb = 0xFFFFFFFFu;
+            if (c > CAP - PASS) {
+                PruneResult pr = prune_local_lds<CAP>(buf, c, k, false);
+                if (pr.count > CAP - PASS)
+                    pr = prune_local_lds<CAP>(buf, pr.count, k, true);
+                if (lane == 0) {
+                    s_cnt = pr.count;
+                    publish(gthr, pr.T, s_bnd);
+                }
+                nb = pr.T;
+            }
+            if (lane == 0 && (nb != 0xFFFFFFFFu || (pass & 7) == 7)) {
+                uint32_t b = s_bnd;
+                b = nb < b ? nb : b;
+                const uint32_t gb = read_bound(gthr) + 1u;
+                s_bnd = gb < b ? gb : b;
+            }
+        }
+        __syncthreads();
+    }
+    if (wave == 0)
+        write_local_topk<CAP, true>(buf, s_cnt, k, r0, dst, gthr, s_bnd, cnt_dst, hist, hist_shift(MM), list_cnt);
+}
+
 // LDS of a few-query tile: pair tables, then candidate buffers and counters.
 __host__ __device__ constexpr size_t few_tile_lds_bytes(int M, int nq)
 {
@@ -1001,12 +1166,17 @@ __device__ void few_tile_impl(const TileJob &job, char *lds)
         }
         __syncthreads();
     }
-    for (int q = wave; q < nq; q += 4)
-        write_local_topk<CAP, true>(buf + q * CAP, cnt[q], k, r0,
-                                    job.cand + ((job.q0 + q) * job.n_rb + job.rb) * (int64_t)k,
-                                    &gthr[q], bnd[q],
-                                    job.ccnt ? job.ccnt + (job.q0 + q) * job.n_rb + job.rb : nullptr,
-                                    job.hist ? job.hist + (job.q0 + q) * kHistBins : nullptr, job.hist_shift);
+    for (int q = wave; q < nq; q += 4) {
+        if (job.lcnt)
+            write_local_topk<CAP, true>(buf + q * CAP, cnt[q], k, r0, job.cand + (job.q0 + q) * job.n_rb * (int64_t)k,
+                                        &gthr[q], bnd[q], nullptr, nullptr, 0, job.lcnt + job.q0 + q);
+        else
+            write_local_topk<CAP, true>(buf + q * CAP, cnt[q], k, r0,
+                                        job.cand + ((job.q0 + q) * job.n_rb + job.rb) * (int64_t)k,
+                                        &gthr[q], bnd[q],
+                                        job.ccnt ? job.ccnt + (job.q0 + q) * job.n_rb + job.rb : nullptr,
+                                        job.hist ? job.hist + (job.q0 + q) * kHistBins : nullptr, job.hist_shift);
+    }
 }
 
 // A few-query tile; ONE requires job.nq == 1.
@@ -1170,6 +1340,31 @@ __device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int 
     const uint32_t edge = (((uint32_t)__shfl(bin, first) + 1u) << shift) - 1u;
     return edge < bound ? edge : bound;
 }
+
+// merge_collect over a query's dense candidate list src[0, n_keys), first
+// bounded by the list's own histogram of d (h: kHistBins words of LDS): the
+// first bin at which the count reaches k bounds the k-th smallest d, so
+// that only about k keys are collected and selected.
+__device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t *__restrict__ src, int64_t n_keys,
+                                      uint32_t k, int shift, uint32_t bound)
+{
+    __shared__ uint32_t s_bound;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kHistBins; i += 256)
+        h[i] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < n_keys; i += 256)
+        atomicAdd(&h[(uint32_t)(src[i] >> 32) >> shift], 1u);
+    __syncthreads();
+    if (tid < 64) {
+        const uint32_t b = hist_bound(h, k, shift, bound);
+        if (tid == 0)
+            s_bound = b;
+    }
+    __syncthreads();
+    return merge_collect(L, src, 0, n_keys, k, s_bound);
+}
+
 
 // Exact r-th smallest of the G uint16 values v[0, G) (G a multiple of 8, v
 // 16-byte aligned), by one workgroup of 256 threads: a histogram (h, LDS,
