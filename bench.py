@@ -129,22 +129,31 @@ def scan_roofline(kernel, Q, N, M, ms):
            "frac": round(ops / t / MFMA_I8_OPS, 4),
            "lookups_T_per_s": round(lookups / t / 1e12, 3)}
     if kernel.startswith("scan_topk_mfma"):
-        per = ONEHOT_MACS_PER_LOOKUP.get(kernel, 16)
-        out["onehot_macs_per_lookup"] = per
-        out["dense_equiv_TOPs"] = round(2.0 * per * lookups / t / 1e12, 1)
-        out["dense_equiv_frac"] = round(2.0 * per * lookups / t / MFMA_I8_OPS, 4)
-        out["onehot_ceiling_frac"] = round(per * ops / t / MFMA_I8_OPS, 4)
-        out["note"] = ("the lookups run as a one-hot int8 matrix product: %d multiply-adds per lookup, "
-                       "so the method's fraction of the int8 peak is capped at 1/%d; "
-                       "onehot_ceiling_frac is the fraction of that cap.  The LDS/VALU lookup ceilings "
-                       "do not bound a matrix-core kernel" % (per, per))
+        slots = matrix_slots_per_lookup(M)
+        out["onehot_macs_per_lookup"] = 16
+        out["matrix_slots_per_lookup"] = round(slots, 3)
+        out["dense_equiv_TOPs"] = round(2.0 * 16 * lookups / t / 1e12, 1)
+        out["matrix_ceiling_frac"] = round(slots * ops / t / MFMA_I8_OPS, 4)
+        out["note"] = ("the lookups run as a one-hot int8 matrix product (16 multiply-adds per lookup) on the "
+                       "4:2-structured sparse instruction, which issues 32 one-hot entries per dense "
+                       "multiply-add slot; with the first four subspaces of a pass on the dense instruction, "
+                       "a lookup occupies 8 (M + 4) / M dense slots (%.3g at M = %d), so the method's fraction "
+                       "of the dense int8 peak is capped at 1/%.3g; matrix_ceiling_frac is the fraction of that "
+                       "cap.  The peak is the dense one: the sparse instruction's doubled headline rate is "
+                       "never used as the denominator.  LDS/VALU lookup ceilings do not bound a matrix-core "
+                       "kernel" % (slots, M, slots))
     else:
         out["note"] = "a lookup-and-add on the vector ALU/LDS; frac against the int8 matrix-core peak"
     return out
 
 
-# int8 multiply-adds per table lookup of each matrix-core scan kernel
-ONEHOT_MACS_PER_LOOKUP = {"scan_topk_mfma": 16}
+def matrix_slots_per_lookup(M):
+    """Dense int8 multiply-add slots of the matrix cores one lookup occupies
+    in the matrix-core scan: per pass of 32 rows, two dense
+    v_mfma_i32_32x32x32_i8 for subspaces 0-3 and M / 4 - 1 sparse
+    v_smfmac_i32_32x32x64_i8, each 32 cycles, against M / 2 dense steps of
+    16 slots per lookup: 16 (M / 4 + 1) / (M / 2) = 8 (M + 4) / M."""
+    return 8.0 * (M + 4) / M
 
 
 def log(*a):
@@ -689,11 +698,10 @@ def run_batched(args, torch, B, W):
             # the method's work (one lookup and one add per query, vector and
             # subspace) against the dense int8 matrix-core peak
             "frac_of_int8_peak": round(2.0 * lookups / (t_graph * 1e-3) / MFMA_I8_OPS, 4),
-            # every lookup counted as the matrix cores' one-hot int8
-            # multiply-adds (most of this workload's lookups run there); the
-            # one-hot form caps the method's fraction at 1 / (multiply-adds per lookup)
-            "onehot_macs_per_lookup": ONEHOT_MACS_PER_LOOKUP["scan_topk_mfma"],
-            "dense_equiv_frac": round(2.0 * ONEHOT_MACS_PER_LOOKUP["scan_topk_mfma"] * lookups
+            # every lookup counted at the dense matrix-core slots it occupies
+            # in the one-hot form (most of this workload's lookups run there):
+            # the fraction of the matrix cores the lookups keep busy
+            "matrix_slot_frac": round(2.0 * sum(s.Q * s.N * s.M * matrix_slots_per_lookup(s.M) for s in specs)
                                       / (t_graph * 1e-3) / MFMA_I8_OPS, 4),
             "identical_to_per_query": bool(same)}
 

@@ -236,8 +236,8 @@ __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restric
     const uint32_t n =
         db.sdist ? bolt::merge_collect_list(L, h, src,
                                             (int64_t)db.lcnt[qq.q] < per_query ? (int64_t)db.lcnt[qq.q] : per_query, k,
-                                            bolt::hist_shift(db.M), db.gthr[qq.q])
-                 : bolt::merge_collect(L, src, 0, per_query, k, db.gthr[qq.q]);
+                                            bolt::hist_shift(db.M), db.gthr[qq.q], false)
+                 : bolt::merge_collect(L, src, 0, per_query, k, db.gthr[qq.q], false);
     if (db.sdist && (n < k || db.fail[qq.q])) {
         if (threadIdx.x == 0) {
             db.gthr[qq.q] = 0xFFFFu;
@@ -245,8 +245,8 @@ __global__ __launch_bounds__(256) void batch_merge_kernel(const DevDb *__restric
         }
         return;
     }
-    bolt::merge_emit(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
-                     db.idx + (int64_t)qq.q * db.k);
+    bolt::merge_finish(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
+                       db.idx + (int64_t)qq.q * db.k);
 }
 
 // Exact recomputation of the listed queries on the whole GPU: item i of the
@@ -258,11 +258,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     const DevDb *__restrict__ dbs, const DevQuery *__restrict__ queries, const uint32_t *__restrict__ redo_cnt,
     const uint32_t *__restrict__ redo, int64_t max_rb, int64_t rows_per_tile)
 {
-    __shared__ __attribute__((aligned(16))) char lds[bolt::one_query_lds_bytes(64)];
-    static_assert(bolt::one_query_lds_bytes(64) >= bolt::one_query_lds_bytes(32) &&
-                      bolt::one_query_lds_bytes(64) >= bolt::one_query_lds_bytes(16) &&
-                      bolt::one_query_lds_bytes(64) >= bolt::one_query_lds_bytes(8),
-                  "one LDS buffer for every code size");
+    constexpr size_t kL8 = bolt::one_query_lds_bytes(8), kL16 = bolt::one_query_lds_bytes(16),
+                     kL32 = bolt::one_query_lds_bytes(32), kL64 = bolt::one_query_lds_bytes(64);
+    constexpr size_t kA = kL8 > kL16 ? kL8 : kL16, kB = kL32 > kL64 ? kL32 : kL64;
+    __shared__ __attribute__((aligned(16))) char lds[kA > kB ? kA : kB];   // one buffer for every code size
     const int64_t items = (int64_t)*redo_cnt * max_rb;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const DevQuery qq = queries[redo[it / max_rb]];
@@ -301,9 +300,9 @@ __global__ __launch_bounds__(256) void batch_redo_merge_kernel(const DevDb *__re
         const int64_t per_query = db.n_rb * db.k;
         const uint32_t k = (uint32_t)db.k;
         const uint32_t n = bolt::merge_collect(L, db.cand + (int64_t)qq.q * per_query, 0, per_query, k,
-                                               db.gthr[qq.q]);
-        bolt::merge_emit(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
-                         db.idx + (int64_t)qq.q * db.k);
+                                               db.gthr[qq.q], false);
+        bolt::merge_finish(L, n, k, db.largest, 255u * (uint32_t)db.M, db.vals + (int64_t)qq.q * db.k,
+                           db.idx + (int64_t)qq.q * db.k);
         __syncthreads();
     }
 }

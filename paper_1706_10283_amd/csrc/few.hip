@@ -129,6 +129,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void o
     uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles,
     uint32_t *__restrict__ lcnt)
 {
+    // One tile per workgroup: a persistent grid of four workgroups per CU,
+    // each building its pair tables once for several tiles, measured 5-8%
+    // slower over 2.5e8 rows at M = 16 and 32.
     __shared__ __attribute__((aligned(16))) char lds[bolt::one_query_lds_bytes(MM)];
     const int64_t tile = blockIdx.x;
     const int64_t r0 = tiles ? tiles[2 * tile] : tile * tile_rows;

@@ -257,16 +257,16 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
     }
     __syncthreads();
     uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, s_lo, s_hi, k);
-    if (threadIdx.x < 64 && n > k)
-        bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
-    __syncthreads();
     if (gridDim.y == 1) {
         if (fail && (n < k || fail[q]))
             flag_redo(q, gthr, redo);
         else
-            bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
+            bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
         return;
     }
+    if (threadIdx.x < 64 && n > k)
+        bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
+    __syncthreads();
     n = n > k ? k : n;
     const int64_t slot = q * gridDim.y + blockIdx.y;
     for (uint32_t r = threadIdx.x; r < n; r += 256)
@@ -299,10 +299,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
         flag_redo(q, gthr, redo);
         return;
     }
-    if (tid < 64 && n > k)
-        bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
-    __syncthreads();
-    bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
+    bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
 }
 
 // Merge of the dense candidate lists (sampled bounds on the pair-table and
@@ -323,11 +320,11 @@ __global__ __launch_bounds__(256) void topk_list_merge_kernel(const uint64_t *__
     const int64_t q = blockIdx.x;
     const uint32_t c = lcnt[q];
     const int64_t n_keys = (int64_t)c < per_query ? (int64_t)c : per_query;
-    const uint32_t n = bolt::merge_collect_list(L, h, cand + q * per_query, n_keys, k, shift, gthr[q]);
+    const uint32_t n = bolt::merge_collect_list(L, h, cand + q * per_query, n_keys, k, shift, gthr[q], false);
     if (n < k || fail[q])
         flag_redo(q, gthr, redo);
     else
-        bolt::merge_emit(L, n, k, largest, smax, vals + q * k, idx + q * k);
+        bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
 }
 
 // Stage 3: exact recomputation of the listed queries (redo[0] of them, at
@@ -383,10 +380,7 @@ __global__ __launch_bounds__(256) void topk_redo_merge_kernel(const uint64_t *__
         }
         __syncthreads();
         const uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, 0, n_rb, k);
-        if (threadIdx.x < 64 && n > k)
-            bolt::prune_u64_fit<bolt::kMergeCap>(L.mb, n, k);
-        __syncthreads();
-        bolt::merge_emit(L, n > k ? k : n, k, largest, smax, vals + q * k, idx + q * k);
+        bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
         __syncthreads();
     }
 }

@@ -65,26 +65,34 @@ int topk_u16(const uint16_t *d, int64_t Q, int64_t N, int64_t ldd, int k, int la
              uint16_t *vals, int32_t *idx, hipStream_t s);
 
 // Load the M/2 code bytes of row n into dwords (MM/8 of them).
-template <int MM>
+// NT: non-temporal loads, for codes that one call streams exactly once
+// (one or a few queries): a plain streaming read of 4 GB on MI355X reaches
+// 7.1-7.2 TB/s with the non-temporal hint and 5.6-5.7 TB/s without it.
+template <int MM, bool NT = false>
 __device__ __forceinline__ void load_row(const uint8_t *__restrict__ codes, int64_t n, uint32_t *cw)
 {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     const uint8_t *p = codes + n * (MM / 2);
     if constexpr (MM / 2 >= 16) {
 #pragma unroll
         for (int v = 0; v < MM / 32; ++v) {
-            uint4 t = reinterpret_cast<const uint4 *>(p)[v];
+            const u32x4 *a = reinterpret_cast<const u32x4 *>(p) + v;
+            const u32x4 t = NT ? __builtin_nontemporal_load(a) : *a;
             cw[4 * v + 0] = t.x;
             cw[4 * v + 1] = t.y;
             cw[4 * v + 2] = t.z;
             cw[4 * v + 3] = t.w;
         }
     } else if constexpr (MM / 2 == 8) {
-        uint2 t = *reinterpret_cast<const uint2 *>(p);
+        const u32x2 *a = reinterpret_cast<const u32x2 *>(p);
+        const u32x2 t = NT ? __builtin_nontemporal_load(a) : *a;
         cw[0] = t.x;
         cw[1] = t.y;
     } else {
         static_assert(MM / 2 == 4, "rows of 4, 8 or a multiple of 16 bytes");
-        cw[0] = *reinterpret_cast<const uint32_t *>(p);
+        const uint32_t *a = reinterpret_cast<const uint32_t *>(p);
+        cw[0] = NT ? __builtin_nontemporal_load(a) : *a;
     }
 }
 

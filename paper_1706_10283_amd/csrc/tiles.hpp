@@ -889,6 +889,21 @@ __device__ __forceinline__ void pair_reads(const char *tq, const uint32_t (&cw)[
     }
 }
 
+// Table reads of code dword t of rows g G .. g G + G - 1 of cw.
+template <int MM, int R, int G>
+__device__ __forceinline__ void pair_reads_group(const char *tq, const uint32_t (&cw)[R][MM / 8], int g, int t,
+                                                 uint32_t (&v)[G][4])
+{
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+        const uint32_t w = cw[g * G + r][t];
+        v[r][0] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 0) * 512 + byte_x2<0>(w));
+        v[r][1] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 1) * 512 + byte_x2<1>(w));
+        v[r][2] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 2) * 512 + byte_x2<2>(w));
+        v[r][3] = *reinterpret_cast<const uint16_t *>(tq + (4 * t + 3) * 512 + byte_x2<3>(w));
+    }
+}
+
 // Sums of one query for the R rows held in cw; tq is the query's pair
 // tables (MM/2 tables of 256 uint16, 512 bytes each).  Every code byte is one
 // 16-bit LDS read at byte offset 512 * pair + 2 * byte.
@@ -907,17 +922,24 @@ __device__ __forceinline__ void pair_sums(const char *tq, const uint32_t (&cw)[R
     for (int r = 0; r < R; ++r)
         s[r] = 0;
     if constexpr (UNROLL) {
+        // steps of (group of G rows, code dword t): the reads of step i + 1
+        // are issued before the adds of step i, with 8 G registers of reads
+        // in flight whatever R is
         constexpr int T = MM / 8;
-        uint32_t v[2][R][4];
-        pair_reads<MM, R>(tq, cw, 0, v[0]);
+        constexpr int G = R < 4 ? R : 4;
+        constexpr int NS = (R / G) * T;
+        static_assert(R % G == 0, "whole row groups");
+        uint32_t v[2][G][4];
+        pair_reads_group<MM, R, G>(tq, cw, 0, 0, v[0]);
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            if (t + 1 < T)
-                pair_reads<MM, R>(tq, cw, t + 1, v[(t + 1) & 1]);
+        for (int st = 0; st < NS; ++st) {
+            if (st + 1 < NS)
+                pair_reads_group<MM, R, G>(tq, cw, (st + 1) / T, (st + 1) % T, v[(st + 1) & 1]);
+            const int g = st / T;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                s[r] = add3_ordered(s[r], v[t & 1][r][0], v[t & 1][r][1]);
-                s[r] = add3_ordered(s[r], v[t & 1][r][2], v[t & 1][r][3]);
+            for (int r = 0; r < G; ++r) {
+                s[g * G + r] = add3_ordered(s[g * G + r], v[st & 1][r][0], v[st & 1][r][1]);
+                s[g * G + r] = add3_ordered(s[g * G + r], v[st & 1][r][2], v[st & 1][r][3]);
             }
         }
     } else {
@@ -948,8 +970,10 @@ __device__ __forceinline__ void pair_sums(const char *tq, const uint32_t (&cw)[R
 }
 
 // Rows [base, min(r1, base + 256 R)) into cw (lane row tid + 256 r; zeros
-// past the end): a uniform base pointer and 32-bit lane offsets.
-template <int MM, int R>
+// past the end): a uniform base pointer and 32-bit lane offsets.  These
+// rows are streamed once per call (one or a few queries): non-temporal
+// loads unless NT is false.
+template <int MM, int R, bool NT = true>
 __device__ __forceinline__ void load_rows(const uint8_t *__restrict__ codes, int64_t base, int64_t r1,
                                           uint32_t (&cw)[R][MM / 8])
 {
@@ -960,7 +984,7 @@ __device__ __forceinline__ void load_rows(const uint8_t *__restrict__ codes, int
     for (int r = 0; r < R; ++r) {
         const uint32_t i = threadIdx.x + 256u * r;
         if (i < lim)
-            load_row<MM>(p, (int64_t)i, cw[r]);
+            load_row<MM, NT>(p, (int64_t)i, cw[r]);
         else
 #pragma unroll
             for (int v = 0; v < MM / 8; ++v)
@@ -972,7 +996,7 @@ __device__ __forceinline__ void load_rows(const uint8_t *__restrict__ codes, int
 // row of the range (row 0 of codes if the range is empty) and the caller
 // ignores it.  Unconditional loads keep the number of loads in flight known
 // to the compiler, so it waits only for the older batch, not for all.
-template <int MM, int R>
+template <int MM, int R, bool NT = true>
 __device__ __forceinline__ void load_rows_clamped(const uint8_t *__restrict__ codes, int64_t base, int64_t r1,
                                                   uint32_t (&cw)[R][MM / 8])
 {
@@ -982,7 +1006,7 @@ __device__ __forceinline__ void load_rows_clamped(const uint8_t *__restrict__ co
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t i = threadIdx.x + 256u * r;
-        load_row<MM>(p, (int64_t)(i < last ? i : last), cw[r]);
+        load_row<MM, NT>(p, (int64_t)(i < last ? i : last), cw[r]);
     }
 }
 
@@ -1006,7 +1030,8 @@ __device__ __forceinline__ void copy_rows(const uint32_t (&a)[R][MM / 8], uint32
 // kept keys (d << 32 | row) are written packed to dst with their count in
 // *cnt_dst and counted in hist (when cnt_dst is given), else as k padded
 // slots, or appended to the dense list dst with its count in *list_cnt
-// when list_cnt is given.  lds: one_query_lds_bytes(MM) bytes, 16-byte aligned (a static
+// when list_cnt is given.
+// lds: one_query_lds_bytes(MM) bytes, 16-byte aligned (a static
 // array, so that the table offsets stay compile-time constants).  Wave 0
 // still writes the result when the other waves return: a caller that
 // reuses lds must synchronise first.
@@ -1199,9 +1224,11 @@ struct MergeLds {
 };
 
 // Exact k smallest of the 48-bit keys src[lo, hi) with d <= bound (one
-// workgroup): left unsorted in L.mb[0, n), n <= k returned.
+// workgroup): left unsorted in L.mb[0, n), n <= k returned.  With fit
+// false the final selection is left to merge_finish: every collected key
+// stays (n may exceed k; the k smallest are among them).
 __device__ uint32_t merge_collect(MergeLds &L, const uint64_t *__restrict__ src, int64_t lo, int64_t hi,
-                                 uint32_t k, uint32_t bound)
+                                 uint32_t k, uint32_t bound, bool fit = true)
 {
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -1233,6 +1260,8 @@ __device__ uint32_t merge_collect(MergeLds &L, const uint64_t *__restrict__ src,
         __syncthreads();
     }
     uint32_t n = L.mcnt;
+    if (!fit)
+        return n;
     if (tid < 64 && n > k)
         prune_u64_fit<kMergeCap>(L.mb, n, k);
     __syncthreads();
@@ -1278,21 +1307,37 @@ __device__ void merge_emit(MergeLds &L, uint32_t n, uint32_t k, int largest, uin
     }
 }
 
-// Exact k smallest keys of src[lo, hi) with d <= bound.  out != NULL: the k
-// keys (unsorted, ~0 padded) are written to out; otherwise sorted values and
-// rows as merge_emit.
-__device__ void merge_keys(const uint64_t *__restrict__ src, int64_t lo, int64_t hi, uint32_t k,
-                           uint32_t bound, uint64_t *__restrict__ out, int largest, uint32_t smax,
-                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
+// The sorted k smallest of the n distinct keys in L.mb (any n up to
+// kMergeCap; the workgroup is synchronised on entry), written as merge_emit
+// writes them.  Up to 256 keys: every thread places one key at its rank
+// (the number of smaller keys), one pass with no barriers; more: the exact
+// k smallest are selected first, then sorted.
+__device__ void merge_finish(MergeLds &L, uint32_t n, uint32_t k, int largest, uint32_t smax,
+                             uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
 {
-    __shared__ MergeLds L;
-    const uint32_t n = merge_collect(L, src, lo, hi, k, bound);
-    if (out) {
-        for (uint32_t r = threadIdx.x; r < k; r += 256)
-            out[r] = r < n ? L.mb[r] : ~0ull;
+    const int tid = threadIdx.x;
+    if (n > 256) {
+        if (tid < 64)
+            prune_u64_fit<kMergeCap>(L.mb, n, k);
+        __syncthreads();
+        merge_emit(L, n > k ? k : n, k, largest, smax, vals, idx);
         return;
     }
-    merge_emit(L, n, k, largest, smax, vals, idx);
+    if ((uint32_t)tid < n) {
+        const uint64_t key = L.mb[tid];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < n; ++j)
+            rank += L.mb[j] < key ? 1u : 0u;
+        if (rank < k) {
+            const uint32_t d = (uint32_t)(key >> 32);
+            vals[rank] = (uint16_t)(largest ? smax - d : d);
+            idx[rank] = (int32_t)(key & 0xFFFFFFFFu);
+        }
+    }
+    for (uint32_t r = n + tid; r < k; r += 256) {
+        vals[r] = (uint16_t)(largest ? 0u : 0xFFFFu);
+        idx[r] = -1;
+    }
 }
 
 // The first histogram bin at which the running count of candidate keys
@@ -1341,15 +1386,18 @@ __device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int 
     return edge < bound ? edge : bound;
 }
 
-// merge_collect over a query's dense candidate list src[0, n_keys), first
-// bounded by the list's own histogram of d (h: kHistBins words of LDS): the
-// first bin at which the count reaches k bounds the k-th smallest d, so
-// that only about k keys are collected and selected.
+// merge_collect over a query's dense candidate list src[0, n_keys).  A
+// long list is first bounded by its own histogram of d (h: kHistBins words
+// of LDS): the first bin at which the count reaches k bounds the k-th
+// smallest d, so that only about k keys are collected and selected; a
+// short one (at most 256 keys) is collected whole.
 __device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t *__restrict__ src, int64_t n_keys,
-                                      uint32_t k, int shift, uint32_t bound)
+                                      uint32_t k, int shift, uint32_t bound, bool fit = true)
 {
     __shared__ uint32_t s_bound;
     const int tid = threadIdx.x;
+    if (n_keys <= 256)   // a short list: collected whole, placed by rank
+        return merge_collect(L, src, 0, n_keys, k, bound, fit);
     for (int i = tid; i < kHistBins; i += 256)
         h[i] = 0;
     __syncthreads();
@@ -1362,7 +1410,7 @@ __device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t 
             s_bound = b;
     }
     __syncthreads();
-    return merge_collect(L, src, 0, n_keys, k, s_bound);
+    return merge_collect(L, src, 0, n_keys, k, s_bound, fit);
 }
 
 

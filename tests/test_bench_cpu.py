@@ -61,18 +61,28 @@ def test_traffic_only_for_its_workload_and_code(bench, monkeypatch):
 
 def test_roofline_counts_the_methods_work(bench):
     """frac is one lookup and one add per (query, vector, subspace) against the
-    dense int8 peak; the one-hot multiply-adds are reported separately and cap
-    the method's fraction at 1/16 for the dense matrix-core kernel."""
+    dense int8 peak; the matrix-core slots the one-hot form occupies are
+    reported separately and cap the method's fraction at 1 / slots."""
     Q, N, M, ms = 1000, 1_000_000, 32, 0.4
     r = bench.scan_roofline("scan_topk_mfma", Q, N, M, ms)
     method = 2.0 * Q * N * M / (ms * 1e-3)
     assert r["frac"] == pytest.approx(method / 5.0e15, abs=1e-4)
     assert r["achieved"] == pytest.approx(method / 1e12, rel=1e-3)
-    assert r["dense_equiv_frac"] == pytest.approx(16 * method / 5.0e15, abs=1e-4)
-    assert r["onehot_ceiling_frac"] == pytest.approx(16 * r["frac"], rel=1e-3)
+    assert r["matrix_slots_per_lookup"] == pytest.approx(9.0)
+    assert r["matrix_ceiling_frac"] == pytest.approx(9.0 * r["frac"], rel=1e-3)
     assert r["bound"] == "mfma" and r["peak"] == 5000.0
     g = bench.scan_roofline("scan_topk_grouped", Q, N, M, ms)
-    assert g["frac"] == r["frac"] and "dense_equiv_frac" not in g
+    assert g["frac"] == r["frac"] and "matrix_ceiling_frac" not in g
+
+
+def test_matrix_slots_count_the_instruction_mix():
+    """Per pass of 32 rows: two dense 32x32x32 steps for subspaces 0-3 and one
+    sparse 32x32x64 step per further four subspaces, each 32 cycles; the
+    dense form would take M / 2 steps of the same length."""
+    import bench as b
+    for M in (8, 16, 32, 64):
+        steps = 2 + (M - 4) // 4
+        assert b.matrix_slots_per_lookup(M) == pytest.approx(16.0 * steps / (M / 2))
 
 
 def test_cpu_baseline_threads_give_the_oracle_result(bench):
