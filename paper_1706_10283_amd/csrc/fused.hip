@@ -139,12 +139,21 @@ __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
 
 // ------------------------------------------------------------------ merge
 
-// Lists query q for the exact recomputation (stage 3): its bound is opened
-// (every d passes) and q is appended to redo[2 ...] (redo[0] counts the
-// list).  Called by the one workgroup that finishes the query's merge.
-__device__ void flag_redo(int64_t q, uint32_t *gthr, uint32_t *redo)
+// Lists query q for the exact recomputation (stage 3): q is appended to
+// redo[2 ...] (redo[0] counts the list), its bound is opened, its histogram
+// and dense list emptied for stage 3a, and fail[q] becomes the count of its
+// tiles that stage 3a finished.  Every thread of the one workgroup that
+// finishes the query's merge calls it, after the workgroup's last read of
+// hist[q], lcnt[q] and fail[q].
+__device__ void flag_redo(int64_t q, uint32_t *gthr, uint32_t *hist, uint32_t *lcnt, uint32_t *fail,
+                          uint32_t *redo)
 {
+    __syncthreads();
+    for (int i = threadIdx.x; i < bolt::kHistBins; i += blockDim.x)
+        hist[q * bolt::kHistBins + i] = 0;
     if (threadIdx.x == 0) {
+        fail[q] = 0;
+        lcnt[q] = 0;
         gthr[q] = 0xFFFFu;
         const uint32_t pos = atomicAdd(&redo[0], 1u);
         redo[2 + pos] = (uint32_t)q;
@@ -233,12 +242,12 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
                                                          const uint32_t *__restrict__ ccnt, int64_t n_rb,
                                                          int64_t slots_per_chunk, uint32_t k,
                                                          uint32_t *__restrict__ gthr,
-                                                         const uint32_t *__restrict__ hist, int shift,
+                                                         uint32_t *__restrict__ hist, int shift,
                                                          int largest, uint32_t smax, uint64_t *__restrict__ dst,
                                                          uint32_t *__restrict__ dst_cnt,
                                                          uint16_t *__restrict__ vals,
-                                                         int32_t *__restrict__ idx, uint32_t *__restrict__ fail,
-                                                         uint32_t *__restrict__ redo)
+                                                         int32_t *__restrict__ idx, uint32_t *__restrict__ lcnt,
+                                                         uint32_t *__restrict__ fail, uint32_t *__restrict__ redo)
 {
     __shared__ bolt::MergeLds L;
     __shared__ uint32_t pre[257];
@@ -259,7 +268,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
     uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, s_lo, s_hi, k);
     if (gridDim.y == 1) {
         if (fail && (n < k || fail[q]))
-            flag_redo(q, gthr, redo);
+            flag_redo(q, gthr, hist, lcnt, fail, redo);
         else
             bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
         return;
@@ -282,6 +291,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
                                                           uint32_t k, uint32_t *__restrict__ gthr,
                                                           int largest, uint32_t smax,
                                                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx,
+                                                          uint32_t *__restrict__ hist, uint32_t *__restrict__ lcnt,
                                                           uint32_t *__restrict__ fail, uint32_t *__restrict__ redo)
 {
     __shared__ bolt::MergeLds L;
@@ -296,7 +306,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
     const uint32_t n = merge_walk(L, pre, src + q * (int64_t)n_chunks * k, src_cnt + q * (int64_t)n_chunks, 0,
                                   n_chunks, k);
     if (fail && (n < k || fail[q])) {
-        flag_redo(q, gthr, redo);
+        flag_redo(q, gthr, hist, lcnt, fail, redo);
         return;
     }
     bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
@@ -308,12 +318,12 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
 // k keys (its sampled bound failed) or whose barrier-free tile overflowed
 // is listed for the recomputation.
 __global__ __launch_bounds__(256) void topk_list_merge_kernel(const uint64_t *__restrict__ cand,
-                                                              const uint32_t *__restrict__ lcnt, int64_t per_query,
+                                                              uint32_t *__restrict__ lcnt, int64_t per_query,
                                                               uint32_t k, int shift, uint32_t *__restrict__ gthr,
                                                               int largest,
                                                               uint32_t smax, uint16_t *__restrict__ vals,
-                                                              int32_t *__restrict__ idx, uint32_t *__restrict__ fail,
-                                                              uint32_t *__restrict__ redo)
+                                                              int32_t *__restrict__ idx, uint32_t *__restrict__ hist,
+                                                              uint32_t *__restrict__ fail, uint32_t *__restrict__ redo)
 {
     __shared__ bolt::MergeLds L;
     __shared__ __attribute__((aligned(16))) uint32_t h[bolt::kHistBins];
@@ -322,64 +332,103 @@ __global__ __launch_bounds__(256) void topk_list_merge_kernel(const uint64_t *__
     const int64_t n_keys = (int64_t)c < per_query ? (int64_t)c : per_query;
     const uint32_t n = bolt::merge_collect_list(L, h, cand + q * per_query, n_keys, k, shift, gthr[q], false);
     if (n < k || fail[q])
-        flag_redo(q, gthr, redo);
+        flag_redo(q, gthr, hist, lcnt, fail, redo);
     else
         bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
 }
 
-// Stage 3: exact recomputation of the listed queries (redo[0] of them, at
-// redo[2 ...]) on the whole GPU.  Item i of the persistent loop is (listed
-// query i / n_rb, tile i % n_rb): a one-query tile over the tile's rows from
-// the query's open bound, publishing pruned bounds to the query's other
-// tiles and writing its local top-k to the query's own candidate slot
-// (free since the merge).  With an empty list every workgroup exits at
-// once.
-template <int MM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void topk_redo_scan_kernel(
-    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k, int largest,
-    int64_t n_rb, int64_t rpb, const int64_t *__restrict__ tiles, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
-    const uint32_t *__restrict__ redo)
+// Rows [r0, r1) of tile rb: the caller's list, else rpb rows each.
+__device__ __forceinline__ void tile_rows(const int64_t *__restrict__ tiles, int64_t rb, int64_t rpb, int64_t N,
+                                          int64_t &r0, int64_t &r1)
 {
-    __shared__ __attribute__((aligned(16))) char lds[bolt::one_query_lds_bytes(MM)];
-    const int64_t items = (int64_t)redo[0] * n_rb;
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const int64_t q = redo[2 + it / n_rb];
-        const int64_t rb = it % n_rb;
-        int64_t r0, r1;
-        if (tiles) {
-            r0 = tiles[2 * rb];
-            r1 = tiles[2 * rb + 1];
-        } else {
-            r0 = rb * rpb;
-            r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
-        }
-        bolt::one_query_tile<MM>(codes, r0, r1, luts + q * MM * 16, k, largest, cand + (q * n_rb + rb) * k,
-                                 ccnt + q * n_rb + rb, nullptr, gthr + q, lds);
-        __syncthreads();   // the tile's writer is done with lds
+    if (tiles) {
+        r0 = tiles[2 * rb];
+        r1 = tiles[2 * rb + 1];
+    } else {
+        r0 = rb * rpb;
+        r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
     }
 }
 
-// Stage 3, merge: workgroup w takes listed queries w, w + grid, ...: the
-// keys of all n_rb slots of the query at or below its published bound, the
-// exact k smallest, sorted.
+// Stage 3: exact recomputation of the listed queries (redo[0] of them, at
+// redo[2 ...]) on the whole GPU, in two launches whose workgroups all exit
+// at once when the list is empty.
+//
+// 3a, the scan: item i of the persistent loop is (listed query i / n_rb,
+// tile i % n_rb), a one-query tile from the query's open bound that
+// publishes its pruned bounds to the query's other tiles, appends its local
+// top-k to the query's dense list (cand[q], free since the merge) and adds
+// its d histogram to hist[q] (one_query_tile with HIST).  The workgroup
+// that finishes the query's last tile (fail[q] counts them) sets gthr[q] to
+// the upper edge of the first bin at which the sum reaches k: the query's
+// k-th smallest d lies in that bin, so the merge collects the k smallest
+// keys and at most that bin's other keys.
+template <int MM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void topk_redo_scan_kernel(
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k, int largest,
+    int64_t n_rb, int64_t rpb, const int64_t *__restrict__ tiles, uint64_t *cand, uint32_t *hist, uint32_t *gthr,
+    uint32_t *done, uint32_t *lcnt, const uint32_t *__restrict__ redo)
+{
+    constexpr size_t kTile = bolt::one_query_lds_bytes(MM);
+    __shared__ __attribute__((aligned(16))) char lds[kTile + bolt::kHistBins * sizeof(uint32_t)];
+    __shared__ uint32_t s_last;
+    uint32_t *hl = reinterpret_cast<uint32_t *>(lds + kTile);
+    const int64_t items = (int64_t)redo[0] * n_rb;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t q = redo[2 + it / n_rb];
+        int64_t r0, r1;
+        tile_rows(tiles, it % n_rb, rpb, N, r0, r1);
+        for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+            hl[i] = 0;   // the tile's first barrier orders these before the counts
+        uint32_t *hq = hist + q * bolt::kHistBins;
+        bolt::one_query_tile<MM, true>(codes, r0, r1, luts + q * MM * 16, k, largest, cand + q * n_rb * k, nullptr,
+                                       nullptr, gthr + q, lds, lcnt + q, hl, hq);
+        // The tile's bins, bound and list went out as device-scope atomics
+        // and stores: each wave waits for its own to complete before the
+        // tile is counted (a device-scope fence here would also write back
+        // the L2, once per tile: a separate histogram pass ran 3.4 times
+        // slower with one), and the last workgroup reads hq with atomics.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_last = atomicAdd(&done[q], 1u) == (uint32_t)(n_rb - 1) ? 1u : 0u;
+        __syncthreads();
+        if (s_last) {
+            uint32_t *h = reinterpret_cast<uint32_t *>(lds);
+            for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
+                h[i] = atomicAdd(&hq[i], 0u);
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                const uint32_t b = bolt::hist_bound(h, k, bolt::hist_shift(MM), 0xFFFFu);
+                if (threadIdx.x == 0) {
+                    atomicExch(&gthr[q], b);
+                    atomicExch(&done[q], 0u);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// 3b, the merge: workgroup w takes listed queries w, w + grid, ...: the
+// exact k smallest keys of the query's list at or below its bound, sorted
+// (the list holds every tile's local top-k, hundreds of thousands of keys
+// over 2.5e8 rows; the exact bound admits about k of them).
 __global__ __launch_bounds__(256) void topk_redo_merge_kernel(const uint64_t *__restrict__ cand,
-                                                              const uint32_t *__restrict__ ccnt, int64_t n_rb,
+                                                              const uint32_t *__restrict__ lcnt, int64_t n_rb,
                                                               uint32_t k, const uint32_t *__restrict__ gthr,
                                                               int largest, uint32_t smax,
                                                               const uint32_t *__restrict__ redo,
                                                               uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
 {
     __shared__ bolt::MergeLds L;
-    __shared__ uint32_t pre[257];
     const uint32_t n_redo = redo[0];
+    const int64_t per_query = n_rb * k;
     for (uint32_t j = blockIdx.x; j < n_redo; j += gridDim.x) {
         const int64_t q = redo[2 + j];
-        if (threadIdx.x == 0) {
-            L.mcnt = 0;
-            L.mbound = ((uint64_t)gthr[q] + 1u) << 32;   // keys with d <= bound
-        }
-        __syncthreads();
-        const uint32_t n = merge_walk(L, pre, cand + q * n_rb * k, ccnt + q * n_rb, 0, n_rb, k);
+        const int64_t c = lcnt[q];
+        const int64_t n_keys = c < per_query ? c : per_query;
+        const uint32_t n = bolt::merge_collect_wide(L, cand + q * per_query, n_keys, k, gthr[q]);
         bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
         __syncthreads();
     }
@@ -503,7 +552,7 @@ constexpr int ng_for()
 // exactly: a histogram locates its bin, a second count that bin's values.
 // The bound only selects candidates: the
 // final merge lists any query with fewer than k candidates and
-// topk_redo_kernel recomputes it exactly, so results never depend on it.
+// stage 3 recomputes it exactly, so results never depend on it.
 using bolt::kSpecSpan;
 using bolt::kSpecMinRows;
 using bolt::kSpecMinRowsForced;
@@ -591,9 +640,10 @@ FusedPlan plan_finish(FusedPlan p, int64_t Q, int k)
                                     : 0;
     if (p.n_chunks > 65535)
         return p;
-    // sample minima, overflow flags and (matrix-core tiles) dense list counts
+    // sample minima, overflow flags and dense list counts (the pair-table
+    // and matrix-core tiles' lists, and the recomputation's)
     p.spec_bytes = p.spec ? align256((size_t)Q * p.spec_nsc * bolt::kSpecGroups * sizeof(uint16_t)) +
-                                align256((size_t)Q * sizeof(uint32_t)) * (p.kind != 2 ? 2 : 1)
+                                align256((size_t)Q * sizeof(uint32_t)) * 2
                           : 0;
     p.redo_bytes = p.spec ? align256((size_t)(Q + 2) * sizeof(uint32_t)) : 0;
     p.ok = true;
@@ -688,14 +738,14 @@ constexpr int64_t kRedoGrid = 1024;
 constexpr int64_t kRedoMergeGrid = 64;
 
 void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k, int largest,
-                 const FusedPlan &p, const int64_t *tiles, uint64_t *cand, uint32_t *ccnt, uint32_t *gthr,
-                 const uint32_t *redo, uint16_t *vals, int32_t *idx, hipStream_t s)
+                 const FusedPlan &p, const int64_t *tiles, uint64_t *cand, uint32_t *gthr, uint32_t *hist,
+                 uint32_t *fail, uint32_t *lcnt, const uint32_t *redo, uint16_t *vals, int32_t *idx, hipStream_t s)
 {
     const int64_t items = (int64_t)p.n_rb * Q;
     const dim3 grid((unsigned)(items < kRedoGrid ? items : kRedoGrid));
 #define BOLT_REDO_M(MM)                                                                                          \
     hipLaunchKernelGGL(topk_redo_scan_kernel<MM>, grid, dim3(256), 0, s, codes, N, luts, (uint32_t)k, largest,   \
-                       (int64_t)p.n_rb, p.rpb, tiles, cand, ccnt, gthr, redo)
+                       (int64_t)p.n_rb, p.rpb, tiles, cand, hist, gthr, fail, lcnt, redo)
     switch (M) {
     case 8: BOLT_REDO_M(8); break;
     case 16: BOLT_REDO_M(16); break;
@@ -704,7 +754,7 @@ void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, in
     }
 #undef BOLT_REDO_M
     hipLaunchKernelGGL(topk_redo_merge_kernel, dim3((unsigned)(Q < kRedoMergeGrid ? Q : kRedoMergeGrid)), dim3(256),
-                       0, s, cand, ccnt, (int64_t)p.n_rb, (uint32_t)k, gthr, largest, 255u * (uint32_t)M, redo, vals,
+                       0, s, cand, lcnt, (int64_t)p.n_rb, (uint32_t)k, gthr, largest, 255u * (uint32_t)M, redo, vals,
                        idx);
 }
 
@@ -779,7 +829,8 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     // sampled bounds on the pair-table and matrix-core tiles: dense
     // per-query candidate lists
     const bool lists = p.spec && p.kind != 2;
-    uint32_t *lcnt = lists ? fail + align256((size_t)Q * sizeof(uint32_t)) / sizeof(uint32_t) : nullptr;
+    uint32_t *lcnt_all = p.spec ? fail + align256((size_t)Q * sizeof(uint32_t)) / sizeof(uint32_t) : nullptr;
+    uint32_t *lcnt = lists ? lcnt_all : nullptr;
     if (p.spec) {
         // sample group minima, then each query's starting bound (and cleared histogram)
         {
@@ -809,19 +860,22 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_list_merge_kernel, dim3((unsigned)Q), dim3(256), 0, s, cand, lcnt,
                            (int64_t)p.n_rb * k, (uint32_t)k, bolt::hist_shift(M), gthr, (int)largest, smax, vals, idx,
-                           fail, redo);
+                           hist, fail, redo);
     } else {
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand, ccnt,
                            (int64_t)p.n_rb, p.n_chunks > 1 ? p.chunk : (int64_t)p.n_rb, (uint32_t)k, gthr, hist,
-                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, fail, redo);
+                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, lcnt_all, fail,
+                           redo);
         if (p.n_chunks > 1)
             hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
-                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, fail, redo);
+                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, hist, lcnt_all, fail,
+                               redo);
     }
     if (p.spec) {
         bolt::ProfScope prof_("topk_redo", s);
-        launch_redo(M, codes, N, luts, Q, k, (int)largest, p, tiles, cand, ccnt, gthr, redo, vals, idx, s);
+        launch_redo(M, codes, N, luts, Q, k, (int)largest, p, tiles, cand, gthr, hist, fail, lcnt_all, redo, vals,
+                    idx, s);
     }
     return check_launch("bolt_scan_topk (fused)");
 }

@@ -1035,6 +1035,11 @@ __device__ __forceinline__ void copy_rows(const uint32_t (&a)[R][MM / 8], uint32
 // array, so that the table offsets stay compile-time constants).  Wave 0
 // still writes the result when the other waves return: a caller that
 // reuses lds must synchronise first.
+// The pair tables' random 16-bit reads conflict on LDS banks (about 60% of
+// the LDS cycles at M = 16 and 32, and the LDS is then the busiest unit):
+// one 16-byte table per subspace, which lies in one bank row, removes the
+// conflicts but doubles the reads and the address arithmetic, and measured
+// equal at M = 16 and 11% slower at M = 32.
 // Rows per lane per pass of the one-query tile (its codes in flight per lane:
 // R M / 2 bytes; 128 at M = 32, measured 4% faster than 64 over 2.5e8 rows,
 // 64 at M = 16 where 96 was slower), a pass and the candidate buffer (a
@@ -1048,19 +1053,29 @@ __host__ __device__ constexpr size_t one_query_lds_bytes(int M)
     return (size_t)(M / 2) * 256 * sizeof(uint16_t) + (size_t)one_cap(M) * sizeof(uint32_t);
 }
 
-template <int MM>
+//
+// HIST (the exact recomputation): the tile also counts, in the LDS
+// histogram hl (kHistBins words, zeroed by the caller), the d of every row
+// at or below the query's published bound (s_hlim: inclusive, lowered with
+// the tile's own pruned bound), and adds the bins up to that bound to the
+// query's histogram hq.  The published bound never drops below the query's
+// k-th smallest d, so every tile counts every row at or below it, and the
+// sum over the tiles is exact on every bin up to the one holding it.
+template <int MM, bool HIST = false>
 __device__ __forceinline__ void one_query_tile(const uint8_t *__restrict__ codes, int64_t r0, int64_t r1,
                                                const uint8_t *__restrict__ luts, uint32_t k, int largest,
                                                uint64_t *__restrict__ dst, uint32_t *cnt_dst, uint32_t *hist,
-                                               uint32_t *gthr, char *lds, uint32_t *list_cnt = nullptr)
+                                               uint32_t *gthr, char *lds, uint32_t *list_cnt = nullptr,
+                                               uint32_t *hl = nullptr, uint32_t *hq = nullptr)
 {
     constexpr int R = one_r(MM);
     constexpr int PASS = one_pass(MM);
     constexpr int CAP = one_cap(MM);
     constexpr uint32_t SMAX = 255u * MM;
+    constexpr int SHIFT = hist_shift(MM);
     uint16_t *pt = reinterpret_cast<uint16_t *>(lds);
     uint32_t *buf = reinterpret_cast<uint32_t *>(lds + (MM / 2) * 256 * sizeof(uint16_t));
-    __shared__ uint32_t s_cnt, s_bnd;
+    __shared__ uint32_t s_cnt, s_bnd, s_hlim;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t cw[R][MM / 8], nx[R][MM / 8];
     load_rows_clamped<MM, R>(codes, r0, r1, nx);
@@ -1068,6 +1083,7 @@ __device__ __forceinline__ void one_query_tile(const uint8_t *__restrict__ codes
     if (tid == 0) {
         s_cnt = 0;
         s_bnd = read_bound(gthr) + 1u;
+        s_hlim = s_bnd - 1u;
     }
     __syncthreads();
     int pass = 0;
@@ -1078,6 +1094,7 @@ __device__ __forceinline__ void one_query_tile(const uint8_t *__restrict__ codes
         uint32_t s[R];
         pair_sums<MM, R, true>(reinterpret_cast<const char *>(pt), cw, s);
         const uint32_t bq = s_bnd;
+        const uint32_t hlim = HIST ? s_hlim : 0u;
         const uint32_t loc = (uint32_t)(base - r0) + (uint32_t)tid;
         const uint32_t lim = (uint32_t)((r1 - base) < PASS ? (r1 - base) : PASS);
 #pragma unroll
@@ -1087,6 +1104,9 @@ __device__ __forceinline__ void one_query_tile(const uint8_t *__restrict__ codes
                 const uint32_t pos = atomicAdd(&s_cnt, 1u);
                 buf[pos] = local_key(d, loc + 256u * r);
             }
+            if constexpr (HIST)
+                if (d <= hlim && (uint32_t)tid + 256u * r < lim)
+                    atomicAdd(&hl[d >> SHIFT], 1u);
         }
         __syncthreads();
         if (wave == 0) {
@@ -1107,12 +1127,23 @@ __device__ __forceinline__ void one_query_tile(const uint8_t *__restrict__ codes
                 b = nb < b ? nb : b;
                 const uint32_t gb = read_bound(gthr) + 1u;
                 s_bnd = gb < b ? gb : b;
+                if constexpr (HIST) {   // inclusive: the pruned k-th d and the published bound
+                    uint32_t h = s_hlim;
+                    h = nb < h ? nb : h;
+                    s_hlim = gb - 1u < h ? gb - 1u : h;
+                }
             }
         }
         __syncthreads();
     }
     if (wave == 0)
         write_local_topk<CAP, true>(buf, s_cnt, k, r0, dst, gthr, s_bnd, cnt_dst, hist, hist_shift(MM), list_cnt);
+    if constexpr (HIST) {
+        const uint32_t top = s_hlim >> SHIFT;   // no row above this bin was counted in every pass
+        for (uint32_t i = tid; i <= top && i < (uint32_t)kHistBins; i += 256)
+            if (hl[i])
+                atomicAdd(&hq[i], hl[i]);
+    }
 }
 
 // LDS of a few-query tile: pair tables, then candidate buffers and counters.
@@ -1268,6 +1299,59 @@ __device__ uint32_t merge_collect(MergeLds &L, const uint64_t *__restrict__ src,
     return n > k ? k : n;
 }
 
+// merge_collect (fit false) for a long list whose bound is known to admit
+// few keys (at most kMergeCap): one pass with 16 keys per thread in flight
+// and no barrier inside, where merge_collect keeps 4 keys per thread in
+// flight and meets two barriers per 1024 keys.  If more than kMergeCap keys
+// pass the bound after all, it falls back to merge_collect.
+__device__ uint32_t merge_collect_wide(MergeLds &L, const uint64_t *__restrict__ src, int64_t n, uint32_t k,
+                                       uint32_t bound)
+{
+    constexpr int W = 8;   // 16-byte loads (two keys) per thread per round
+    const int tid = threadIdx.x;
+    if ((reinterpret_cast<uintptr_t>(src) & 15) != 0)
+        return merge_collect(L, src, 0, n, k, bound, false);
+    if (tid == 0)
+        L.mcnt = 0;
+    __syncthreads();
+    const uint64_t bnd = ((uint64_t)bound + 1u) << 32;
+    const uint4 *s2 = reinterpret_cast<const uint4 *>(src);
+    const int64_t n2 = n / 2;
+    for (int64_t p0 = 0; p0 < n2; p0 += 256 * W) {
+        uint4 v[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int64_t p = p0 + tid + 256 * w;
+            v[w] = p < n2 ? s2[p] : make_uint4(~0u, ~0u, ~0u, ~0u);
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t a = ((uint64_t)v[w].y << 32) | v[w].x, b = ((uint64_t)v[w].w << 32) | v[w].z;
+            if (a < bnd) {
+                const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                if (pos < kMergeCap)
+                    L.mb[pos] = a;
+            }
+            if (b < bnd) {
+                const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+                if (pos < kMergeCap)
+                    L.mb[pos] = b;
+            }
+        }
+    }
+    if (tid == 0 && (n & 1) && src[n - 1] < bnd) {
+        const uint32_t pos = atomicAdd(&L.mcnt, 1u);
+        if (pos < kMergeCap)
+            L.mb[pos] = src[n - 1];
+    }
+    __syncthreads();
+    const uint32_t c = L.mcnt;
+    __syncthreads();   // every thread has read the count before a fallback resets it
+    if (c > (uint32_t)kMergeCap)
+        return merge_collect(L, src, 0, n, k, bound, false);
+    return c;
+}
+
 // Sorts L.mb[0, n) and writes values (sums, converted back from d) and rows,
 // padded to k with 65535 / 0 and -1.
 __device__ void merge_emit(MergeLds &L, uint32_t n, uint32_t k, int largest, uint32_t smax,
@@ -1401,8 +1485,19 @@ __device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t 
     for (int i = tid; i < kHistBins; i += 256)
         h[i] = 0;
     __syncthreads();
-    for (int64_t i = tid; i < n_keys; i += 256)
-        atomicAdd(&h[(uint32_t)(src[i] >> 32) >> shift], 1u);
+    constexpr int B = 8;   // keys per thread in flight
+    for (int64_t i0 = 0; i0 < n_keys; i0 += 256 * B) {
+        uint64_t kk[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int64_t i = i0 + tid + 256 * b;
+            kk[b] = i < n_keys ? src[i] : ~0ull;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (i0 + tid + 256 * b < n_keys)
+                atomicAdd(&h[(uint32_t)(kk[b] >> 32) >> shift], 1u);
+    }
     __syncthreads();
     if (tid < 64) {
         const uint32_t b = hist_bound(h, k, shift, bound);
@@ -1410,6 +1505,8 @@ __device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t 
             s_bound = b;
     }
     __syncthreads();
+    if (!fit)   // the histogram's bound admits about k keys
+        return merge_collect_wide(L, src, n_keys, k, s_bound);
     return merge_collect(L, src, 0, n_keys, k, s_bound, fit);
 }
 
