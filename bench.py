@@ -54,20 +54,21 @@ MFMA_I8_OPS = 5.0e15                 # MI355X dense int8 matrix-core peak (ops/s
 HBM_PEAK_GBPS = 8000.0
 
 # HBM traffic of the dominant kernel, from two rocprofv3 --pmc runs of this
-# script's headline (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
-# scaled by what the counter reads for a 1 GiB device-to-device copy in the
-# same runs (FETCH_SIZE 524312.6 KiB for 1048576 KiB read: factor 2.0;
-# WRITE_SIZE 1048576.0 KiB for 1048576 KiB written: factor 1.0).  Valid only
-# for the workload and kernel sources they were taken on: the sources are
-# hashed, and any change reports traffic as null until measured again.
+# script's lean headline workload (--profile-kernels headline,single
+# --calib-copy: FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
+# what the counter reads for a 1 GiB device-to-device copy in the same runs
+# (FETCH_SIZE 524309.7 KiB for 1048576 KiB read: factor 2.0; WRITE_SIZE
+# 1048576.0 KiB for 1048576 KiB written: factor 1.0).  Valid only for the
+# workload and kernel sources they were taken on: the sources are hashed,
+# and any change reports traffic as null until measured again.
 FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC = {
     "scan_topk_mfma": {
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 9889.2,
-        "write_kib": 16355.1,
-        "sources_sha256": "d5818f1d08013063e93dff76829f15a97f5c0f31c0a01e25c8d6cb46c958e080",
+        "fetch_kib": 9890.3,
+        "write_kib": 5809.7,
+        "sources_sha256": "2d059a6222de3a88773f2e4eb66739c358bb24ea563eb72049ff136417f6564b",
     },
 }
 # the kernel's sources and the build flags (paper_1706_10283_amd/build.py)
@@ -297,6 +298,9 @@ def headline(args, torch, B, W, M=None, steps=None, warmup=None, extras=True):
             "traffic": None if traffic is None else round(traffic),
             "traffic_unit": "HBM bytes per launch (fetch + write)",
             "algorithmic_bytes": N * M // 2 + Q * M * 16,
+            "traffic_note": "fetch: the codes once and the query tables once per XCD (eight L2 caches: "
+                            "the row blocks, not the query blocks, are spread over them); writes: the "
+                            "candidate keys the sampled bound admits (8 bytes each, several times k per query)",
         }),
     }
     if extras:

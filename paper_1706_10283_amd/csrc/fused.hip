@@ -404,32 +404,105 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void t
                     atomicExch(&gthr[q], b);
                     atomicExch(&done[q], 0u);
                 }
+                if (threadIdx.x < 3)   // hq[0 .. 2]: the merge's counters (see 3b)
+                    atomicExch(&hq[threadIdx.x], 0u);
             }
         }
         __syncthreads();
     }
 }
 
-// 3b, the merge: workgroup w takes listed queries w, w + grid, ...: the
-// exact k smallest keys of the query's list at or below its bound, sorted
-// (the list holds every tile's local top-k, hundreds of thousands of keys
-// over 2.5e8 rows; the exact bound admits about k of them).
-__global__ __launch_bounds__(256) void topk_redo_merge_kernel(const uint64_t *__restrict__ cand,
-                                                              const uint32_t *__restrict__ lcnt, int64_t n_rb,
-                                                              uint32_t k, const uint32_t *__restrict__ gthr,
-                                                              int largest, uint32_t smax,
+// 3b, the merge.  The list holds every tile's local top-k (up to k keys per
+// tile: hundreds of thousands over 2.5e8 rows) and the exact bound admits
+// about k of them, so the list is filtered on the whole GPU first.  Item i
+// of the persistent loop is (listed query i / n_chunks, chunk i % n_chunks
+// of kRedoChunk list keys): the chunk's keys at or below the bound are
+// appended, as device-scope atomic stores, to an area of at most kMergeCap
+// keys past the list's end in the query's candidate region (hq[0] counts
+// them, hq[2] flags a chunk with more than kMergeCap); the workgroup that
+// finishes the query's last chunk (hq[1] counts them) reads the area back
+// with atomics and writes the sorted top k.  If the area overflowed (keys
+// massively tied at the bound) that workgroup collects from the whole list
+// instead.  hq: the query's histogram words, free since 3a.
+constexpr int64_t kRedoChunk = 16384;
+
+__global__ __launch_bounds__(256) void topk_redo_merge_kernel(uint64_t *cand, const uint32_t *__restrict__ lcnt,
+                                                              int64_t n_rb, uint32_t k,
+                                                              const uint32_t *__restrict__ gthr, int largest,
+                                                              uint32_t smax, uint32_t *hist,
                                                               const uint32_t *__restrict__ redo,
                                                               uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
 {
     __shared__ bolt::MergeLds L;
-    const uint32_t n_redo = redo[0];
+    __shared__ uint32_t s_n, s_at, s_last;
+    const int tid = threadIdx.x;
     const int64_t per_query = n_rb * k;
-    for (uint32_t j = blockIdx.x; j < n_redo; j += gridDim.x) {
-        const int64_t q = redo[2 + j];
+    const int64_t n_chunks = (per_query + kRedoChunk - 1) / kRedoChunk;
+    const int64_t items = (int64_t)redo[0] * n_chunks;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t q = redo[2 + it / n_chunks];
+        uint64_t *list = cand + q * per_query;
         const int64_t c = lcnt[q];
         const int64_t n_keys = c < per_query ? c : per_query;
-        const uint32_t n = bolt::merge_collect_wide(L, cand + q * per_query, n_keys, k, gthr[q]);
-        bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
+        const int64_t room = per_query - n_keys;
+        const int64_t cap = room < bolt::kMergeCap ? room : bolt::kMergeCap;
+        unsigned long long *area = reinterpret_cast<unsigned long long *>(list + per_query - cap);
+        uint32_t *hq = hist + q * bolt::kHistBins;
+        const uint64_t bnd = ((uint64_t)gthr[q] + 1u) << 32;
+        const int64_t lo = (it % n_chunks) * kRedoChunk;
+        const int64_t hi = (lo + kRedoChunk) < n_keys ? (lo + kRedoChunk) : n_keys;
+        if (tid == 0)
+            s_n = 0;
+        __syncthreads();
+        constexpr int B = 8;   // keys per thread in flight
+        for (int64_t i0 = lo; i0 < hi; i0 += 256 * B) {
+            uint64_t kk[B];
+#pragma unroll
+            for (int e = 0; e < B; ++e) {
+                const int64_t i = i0 + tid + 256 * e;
+                kk[e] = i < hi ? list[i] : ~0ull;
+            }
+#pragma unroll
+            for (int e = 0; e < B; ++e)
+                if (kk[e] < bnd) {
+                    const uint32_t pos = atomicAdd(&s_n, 1u);
+                    if (pos < (uint32_t)bolt::kMergeCap)
+                        L.mb[pos] = kk[e];
+                }
+        }
+        __syncthreads();
+        const uint32_t n = s_n;
+        if (tid == 0 && n > 0) {
+            if (n > (uint32_t)bolt::kMergeCap)
+                atomicOr(&hq[2], 1u);
+            else
+                s_at = atomicAdd(&hq[0], n);
+        }
+        __syncthreads();
+        if (n <= (uint32_t)bolt::kMergeCap)
+            for (uint32_t r = tid; r < n; r += 256)
+                if ((int64_t)s_at + r < cap)
+                    atomicExch(&area[s_at + r], (unsigned long long)L.mb[r]);
+        // the area's stores complete before the chunk is counted (as in 3a)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0)
+            s_last = atomicAdd(&hq[1], 1u) == (uint32_t)(n_chunks - 1) ? 1u : 0u;
+        __syncthreads();
+        if (s_last) {
+            const uint32_t total = atomicAdd(&hq[0], 0u);
+            const bool whole = atomicOr(&hq[2], 0u) != 0u || (int64_t)total > cap;
+            uint32_t m;
+            if (whole) {
+                m = bolt::merge_collect_wide(L, list, n_keys, k, gthr[q]);
+            } else {
+                for (uint32_t r = tid; r < total; r += 256)
+                    L.mb[r] = atomicAdd(&area[r], 0ull);
+                __syncthreads();
+                m = total;
+            }
+            bolt::merge_finish(L, m, k, largest, smax, vals + q * k, idx + q * k);
+        }
         __syncthreads();
     }
 }
@@ -732,10 +805,11 @@ void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_
 #undef BOLT_SAMPLE_M
 }
 
-// Stage 3 launches: a persistent scan grid of at most kRedoGrid workgroups
-// (the list's length is known only on the device), then the merge.
+// Stage 3 launches: persistent grids of at most kRedoGrid scan and
+// kRedoMergeGrid merge workgroups (the list's length is known only on the
+// device).
 constexpr int64_t kRedoGrid = 1024;
-constexpr int64_t kRedoMergeGrid = 64;
+constexpr int64_t kRedoMergeGrid = 256;
 
 void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k, int largest,
                  const FusedPlan &p, const int64_t *tiles, uint64_t *cand, uint32_t *gthr, uint32_t *hist,
@@ -753,8 +827,10 @@ void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, in
     case 64: BOLT_REDO_M(64); break;
     }
 #undef BOLT_REDO_M
-    hipLaunchKernelGGL(topk_redo_merge_kernel, dim3((unsigned)(Q < kRedoMergeGrid ? Q : kRedoMergeGrid)), dim3(256),
-                       0, s, cand, lcnt, (int64_t)p.n_rb, (uint32_t)k, gthr, largest, 255u * (uint32_t)M, redo, vals,
+    const int64_t merge_items = Q * (((int64_t)p.n_rb * k + kRedoChunk - 1) / kRedoChunk);
+    hipLaunchKernelGGL(topk_redo_merge_kernel,
+                       dim3((unsigned)(merge_items < kRedoMergeGrid ? merge_items : kRedoMergeGrid)), dim3(256), 0, s,
+                       cand, lcnt, (int64_t)p.n_rb, (uint32_t)k, gthr, largest, 255u * (uint32_t)M, hist, redo, vals,
                        idx);
 }
 

@@ -426,6 +426,9 @@ SPEC_CASES = [
     # 8 to 31 queries: one part-filled 32-query matrix-core tile is the only query block
     (32, 8, 140_000, 100, "rand"), (16, 9, 150_000, 64, "coarse"), (64, 17, 131_100, 100, "rand"),
     (8, 31, 160_000, 128, "coarse"),
+    # every d tied: a recomputed query's exact bound admits all of every
+    # tile's kept keys, more than the merge buffer holds at once
+    (32, 40, 140_000, 256, "const"),
 ]
 
 
@@ -496,6 +499,7 @@ SPEC_FEW_CASES = [
     # (M, Q, N, k, lut kind): the one- and few-query kernels from sampled bounds
     (32, 1, 200_000, 100, "rand"), (16, 1, 131_072, 1, "const"), (64, 3, 150_001, 256, "rand"),
     (8, 7, 140_000, 10, "coarse"), (32, 2, 300_000, 64, "coarse"),
+    (16, 1, 300_000, 256, "const"),   # every d tied (as in SPEC_CASES)
 ]
 
 
