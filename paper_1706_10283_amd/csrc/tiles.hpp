@@ -1475,6 +1475,8 @@ __device__ uint32_t hist_bound(const uint32_t *__restrict__ hq, uint32_t k, int 
 // of LDS): the first bin at which the count reaches k bounds the k-th
 // smallest d, so that only about k keys are collected and selected; a
 // short one (at most 256 keys) is collected whole.
+constexpr int64_t kWideListKeys = 4096;
+
 __device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t *__restrict__ src, int64_t n_keys,
                                       uint32_t k, int shift, uint32_t bound, bool fit = true)
 {
@@ -1485,8 +1487,16 @@ __device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t 
     for (int i = tid; i < kHistBins; i += 256)
         h[i] = 0;
     __syncthreads();
+    // Long lists (one query over a large database: thousands of keys) keep
+    // 8 keys per thread in flight here and take the wide collect below;
+    // short ones (hundreds of keys per query of a large batch) measured
+    // faster with the plain loops.
+    const bool wide = n_keys > kWideListKeys;
+    if (!wide)
+        for (int64_t i = tid; i < n_keys; i += 256)
+            atomicAdd(&h[(uint32_t)(src[i] >> 32) >> shift], 1u);
     constexpr int B = 8;   // keys per thread in flight
-    for (int64_t i0 = 0; i0 < n_keys; i0 += 256 * B) {
+    for (int64_t i0 = 0; wide && i0 < n_keys; i0 += 256 * B) {
         uint64_t kk[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -1505,7 +1515,7 @@ __device__ uint32_t merge_collect_list(MergeLds &L, uint32_t *h, const uint64_t 
             s_bound = b;
     }
     __syncthreads();
-    if (!fit)   // the histogram's bound admits about k keys
+    if (!fit && wide)   // the histogram's bound admits about k keys
         return merge_collect_wide(L, src, n_keys, k, s_bound);
     return merge_collect(L, src, 0, n_keys, k, s_bound, fit);
 }
