@@ -3,7 +3,7 @@
 // When enabled (bolt_prof_enable), every instrumented launch records a start
 // and a stop event around itself (only launches whose name starts with the
 // prefix given to bolt_prof_only, when one is given: each pair of events
-// costs a few microseconds of stream time); bolt_prof_read waits for the
+// costs stream time); bolt_prof_read waits for the
 // recorded events and returns, per kernel name, the number of launches and
 // their total duration.  Disabled, the instrumentation is a single branch per
 // launch.
@@ -35,8 +35,12 @@ hipEvent_t take_event()
         g_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence when the event is recorded (the
+    // default one writes back and invalidates the caches at every record,
+    // which slows the work that follows; results are read after a full
+    // synchronisation, never through these events)
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess)
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
         return nullptr;
     return e;
 }
