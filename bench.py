@@ -32,7 +32,8 @@ Sub-reports on the same line (each its own workload):
            saturation rate, against the plain one-query-per-launch FIFO server
 
 Per-kernel durations come from HIP events that the library records on each
-kernel's launch stream inside the timed region (bolt_prof_*).
+kernel's launch stream inside the timed region (bolt_prof_*).  The default
+50 warm-up steps let the GPU's clocks settle before the 50 timed steps.
 """
 from __future__ import annotations
 
@@ -164,8 +165,11 @@ def log(*a):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=50)
+    # the GPU's clocks settle within a few tens of steps after an idle
+    # period: 0.843 ms per step after 3 warm-up steps, 0.815 after 30, 0.811
+    # after 100 (the headline, measured)
+    p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--N", type=int, default=1_000_000)
     p.add_argument("--J", type=int, default=128)
     p.add_argument("--M", type=int, default=32)
@@ -414,7 +418,7 @@ def run_msweep(args, torch, B, W):
     """The single-database step at the other code sizes (M = 16 and 64)."""
     out = {}
     for M in (16, 64):
-        r = headline(args, torch, B, W, M=M, steps=10, warmup=2, extras=False)
+        r = headline(args, torch, B, W, M=M, steps=20, warmup=30, extras=False)
         out["M%d" % M] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
                           "encode_GBps": r["encode_GBps"],
                           "scan_topk_G_distances_per_s": r["scan_topk_G_distances_per_s"],
