@@ -54,6 +54,10 @@ __device__ __forceinline__ void store_codes(const uint8_t *cs, int cs_stride, in
 {
     const int bpr = M >> 1;
     const int tile_bytes = rows * bpr;
+    // bytes per row a power of two (every M the kernels are tuned for): a
+    // shift and a mask instead of a division per byte
+    const bool pow2 = (bpr & (bpr - 1)) == 0;
+    const int sh = pow2 ? __builtin_ctz((unsigned)bpr) : 0;
     if (!byte_store) {
         for (int e = threadIdx.x; 4 * e < tile_bytes; e += kThreads) {
             uint32_t w = 0;
@@ -61,7 +65,8 @@ __device__ __forceinline__ void store_codes(const uint8_t *cs, int cs_stride, in
             for (int b = 0; b < 4; ++b) {
                 int byte = 4 * e + b;
                 if (byte < tile_bytes) {
-                    int r = byte / bpr, t = byte - r * bpr;
+                    const int r = pow2 ? byte >> sh : byte / bpr;
+                    const int t = byte - r * bpr;
                     uint32_t v = cs[r * cs_stride + 2 * t] | (cs[r * cs_stride + 2 * t + 1] << 4);
                     w |= v << (8 * b);
                 }
@@ -106,7 +111,15 @@ __global__ __launch_bounds__(kThreads) void encode_lds_kernel(
         const int64_t j0 = (int64_t)m0 * SUB;
         if (m0)
             __syncthreads();
-        if (vec4) {
+        if (vec4 && dims == kChunkDims) {   // a full chunk: 16 float4 per row, no division
+            constexpr int d4 = kChunkDims / 4;
+            for (int e = tid; e < rows * d4; e += kThreads) {
+                const int r = e / d4, c4 = e % d4;
+                float4 v = __builtin_bit_cast(float4, __builtin_nontemporal_load(
+                    reinterpret_cast<const float __attribute__((ext_vector_type(4))) *>(X + (n0 + r) * ldx + j0 + 4 * c4)));
+                *reinterpret_cast<float4 *>(&xs[r * kStride + 4 * c4]) = v;
+            }
+        } else if (vec4) {
             const int d4 = dims >> 2;
             for (int e = tid; e < rows * d4; e += kThreads) {
                 int r = e / d4, c4 = e - r * d4;
