@@ -300,7 +300,7 @@ int bolt_topk_f32(const float *dists, int64_t Q, int64_t N, int64_t ldd, int32_t
  *   1 <= k <= 256.  Q = 0 databases are ignored; N = 0 gives padding.
  * bolt_batch_tuning (may be NULL for defaults): rows_per_tile (multiple of
  *   1024 in [1024, 65536], default 16384), few_max_q (databases with at most
- *   this many queries use the pair-table path, 0..7, default 4), blocks_per_cu
+ *   this many queries use the pair-table path, 0..7, default 2), blocks_per_cu
  *   (persistent workgroups per CU, 1..8, default 3).
  * bolt_batch_plan_create builds the tile list on the host, uploads it into
  *   the caller-owned DEVICE workspace ws (bolt_batch_ws_bytes bytes, 256-byte

@@ -18,11 +18,11 @@ import torch
 from . import bolt as B
 
 CANDIDATES = [
-    (16384, 4, 3),
+    (16384, 2, 3),
+    (32768, 2, 3),
+    (65536, 2, 2),
+    (8192, 2, 3),
     (32768, 4, 3),
-    (65536, 4, 2),
-    (8192, 4, 3),
-    (16384, 7, 2),
 ]
 
 

@@ -332,7 +332,7 @@ int64_t spec_chunks(const bolt_batch_db &d, int kind)
 int resolve(const bolt_batch_tuning *tuning, int32_t &rows, int32_t &few_max, int32_t &per_cu)
 {
     rows = tuning && tuning->rows_per_tile ? tuning->rows_per_tile : 16384;
-    few_max = tuning && tuning->few_max_q ? tuning->few_max_q : 4;
+    few_max = tuning && tuning->few_max_q ? tuning->few_max_q : 2;
     per_cu = tuning && tuning->blocks_per_cu ? tuning->blocks_per_cu : 3;
     if (rows < 1024 || rows > bolt::kTileRowsMax || rows % 1024)
         return bolt::fail(BOLT_ERR_INVALID, "rows_per_tile must be a multiple of 1024 in [1024, 65536]");
@@ -346,15 +346,16 @@ int resolve(const bolt_batch_tuning *tuning, int32_t &rows, int32_t &few_max, in
 // Pair-table tiles need their LDS to fit the persistent kernel's buffer.
 bool few_fits(int M, int nq) { return bolt::few_tile_lds_bytes(M, nq) <= kBatchLds; }
 
-// Tile kind of a database: 1 pair tables (few queries), 3 matrix cores
-// (M = 16, 32 or 64, 8 or more queries: a part-filled 32-query tile beats
-// the grouped kernel from 8; k within the tile's candidate buffer), else 2
-// grouped.
+// Tile kind of a database: 1 pair tables (at most few_max queries), 3
+// matrix cores (M = 16, 32 or 64, three or more queries: a part-filled
+// 32-query tile costs about what a full one costs and beats the pair-table
+// and grouped kernels from three; k within the tile's candidate buffer),
+// else 2 grouped.
 int tile_kind(const bolt_batch_db &d, int few_max)
 {
     if (d.Q <= few_max && few_fits(d.M, d.Q))
         return 1;
-    if (d.M >= 16 && d.Q >= 8 && d.k <= bolt::kMfmaCap - bolt::kMfmaPass)
+    if (d.M >= 16 && d.Q >= 3 && d.k <= bolt::kMfmaCap - bolt::kMfmaPass)
         return 3;
     return 2;
 }

@@ -8,9 +8,10 @@
 // as its starting bound.
 //
 // Stage 1, one workgroup per (row block, query block): the scan computes
-// the sums (one to seven queries: pair tables in LDS; 8 or more queries:
-// the one-hot codes times the tables on the int8 matrix cores; for
-// k > 128: query-interleaved tables in LDS); each sum is compared with
+// the sums (one or two queries, or up to seven at M = 8 or for k > 128:
+// pair tables in LDS; otherwise, with k <= 128, the one-hot codes times the
+// tables on the int8 matrix cores; for k > 128: query-interleaved tables in
+// LDS); each sum is compared with
 // its query's bound and the survivors are appended to that query's LDS
 // buffer.  Without sampled bounds the buffers that could overflow are pruned
 // between passes and a pruned bound is published to the other workgroups
@@ -53,8 +54,12 @@ using bolt::PruneResult;
 using bolt::hist_bound;
 
 constexpr int kRowsPerBlock = 16384;      // rows per workgroup (<= 65536: 16-bit local rows)
-constexpr int64_t kMfmaMinQ = 8;          // queries from which the matrix-core tiles are used (a part-filled
-                                           // 32-query tile beats the grouped kernel from 8)
+// Queries from which the matrix-core tiles are used.  A part-filled 32-query
+// tile costs about what a full one costs, while the few-query kernel's time
+// grows with every query: over 2.5e8 rows the tiles win from three queries
+// at M = 16, 32 and 64 (M = 32: 1.7 against 2.1 ms at three queries, 1.9
+// against 7.2 ms at seven).  M = 8 keeps the few-query kernel below eight.
+constexpr int64_t mfma_min_q(int M) { return M == 8 ? 8 : 3; }
 // 32-query tiles per matrix-core workgroup: with one, the tables take half
 // the registers of two and four waves per SIMD fit (beside 33 KB of LDS),
 // which more than pays for reading the one-hot operand once per instruction
@@ -651,16 +656,17 @@ bool plan_kind(int64_t N, int M, int64_t Q, int k, bool vec_ok, FusedPlan &p)
     const bool tuned_M = (M == 8 || M == 16 || M == 32 || M == 64);
     if (!tuned_M || !vec_ok || k > 256 || N <= 0 || Q <= 0)
         return false;
-    if (Q < bolt::kSmallQ && bolt::few_fused_lds_bytes(M, (int)Q) <= 160 * 1024) {
+    const int force = bolt::g_force_fused_kind;
+    const bool mfma_ok = k <= bolt::kMfmaCap - bolt::kMfmaPass;
+    if (force != 3 && Q < bolt::kSmallQ && bolt::few_fused_lds_bytes(M, (int)Q) <= 160 * 1024 &&
+        (Q < mfma_min_q(M) || !mfma_ok || force == 2)) {
         p.rpb = bolt::few_rows_per_block(N, M, (int)Q);
         p.kind = 1;
         p.n_qb = 1;
         p.qb_size = (int)Q;
     } else {
         p.rpb = kRowsPerBlock;
-        const bool mfma_ok = k <= bolt::kMfmaCap - bolt::kMfmaPass;
-        const int force = bolt::g_force_fused_kind;
-        if (mfma_ok && (force == 3 || (force != 2 && Q >= kMfmaMinQ))) {
+        if (mfma_ok && (force == 3 || (force != 2 && Q >= mfma_min_q(M)))) {
             p.kind = 3;
             p.qb_size = 32 * kMfmaNT;
         } else {

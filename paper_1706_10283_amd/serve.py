@@ -47,17 +47,19 @@ def scan_ws_reserve(rows: int, M: int, q: int, k: int) -> int:
     """Fused scan + top-k workspace to reserve for a request of q queries.
 
     Requests are grouped into one call, so the reservation must cover the
-    request's share of any group it can join.  Calls of 8 or more queries run
-    the matrix-core tiles, whose workspace per query is largest at 8 queries
-    and falls slowly after; calls of 1 to 7 run the pair-table kernels, whose
-    workspace per query falls as the call grows.  The larger of the
-    request's own workspace and q times the per-query workspace of an
-    8-query call therefore bounds its share in every group, up to the
-    alignment padding of the workspace's parts, which 64 KiB per request
-    covers."""
+    request's share of any group it can join.  Calls of three or more
+    queries run the matrix-core tiles (eight or more at M = 8 or for
+    k > 128, where the grouped kernel takes them), whose workspace per query
+    is largest at that smallest call and falls slowly after; smaller calls
+    run the pair-table kernels, whose workspace per query falls as the call
+    grows.  The larger of the request's own workspace and q times the
+    per-query workspace of the smallest such call therefore bounds its share
+    in every group, up to the alignment padding of the workspace's parts,
+    which 64 KiB per request covers."""
+    qmin = 8 if (M == 8 or k > 128) else 3
     alone = B.bolt_scan_topk_ws_bytes(rows, M, q, k)
-    per8 = B.bolt_scan_topk_ws_bytes(rows, M, 8, k)
-    return max(alone, -(-q * per8 // 8)) + 65536
+    per_min = B.bolt_scan_topk_ws_bytes(rows, M, qmin, k)
+    return max(alone, -(-q * per_min // qmin)) + 65536
 
 
 @dataclass

@@ -94,12 +94,12 @@ def test_serving_workspace_reservation_covers_any_group(lib):
     from paper_1706_10283_amd.serve import scan_ws_reserve
     rng = np.random.default_rng(7)
     for N in (60_000, 1_000_000, 250_000_000):
-        for M in (16, 32, 64):
+        for M in (8, 16, 32, 64):
             for _ in range(60):
                 sizes = rng.integers(1, 65, size=int(rng.integers(1, 7)))
                 if rng.random() < 0.3:
                     sizes = rng.integers(1, 8, size=int(rng.integers(2, 7)))
-                k = int(rng.choice([10, 100, 128]))
+                k = int(rng.choice([10, 100, 128, 256]))
                 group = lib.bolt_scan_topk_ws_bytes(N, M, int(sizes.sum()), k)
                 reserved = sum(scan_ws_reserve(N, M, int(q), k) for q in sizes)
                 assert group <= reserved, (N, M, sizes.tolist(), k, group, reserved)

@@ -417,6 +417,42 @@ def test_scan_topk_many_queries_parity(bolt, kernel, metric, M, Q, N, k, kind):
     assert np.array_equal(i.cpu().numpy(), ir)
 
 
+# three to seven queries take the matrix-core tiles by default (one
+# part-filled 32-query tile); with sampled bounds (mode 1), all of them
+# failing (mode 2) and without them (mode 0)
+FEW_MFMA_CASES = [
+    # (M, Q, N, k, lut kind)
+    (16, 3, 200_000, 100, "rand"), (32, 5, 300_001, 64, "coarse"), (64, 7, 150_000, 128, "rand"),
+    (32, 4, 131_072, 1, "const"), (16, 6, 170_000, 100, "coarse"), (32, 7, 16_385, 100, "rand"),
+]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("metric", ["l2", "dot"])
+@pytest.mark.parametrize("M,Q,N,k,kind", FEW_MFMA_CASES)
+def test_scan_topk_three_to_seven_queries_parity(bolt, mode, metric, M, Q, N, k, kind):
+    """The default path for three to seven queries (matrix-core tiles) equals
+    the oracle, whether the sampled bounds hold, all fail or are off."""
+    seed = 17 * M + 3 * Q + N + k
+    _say("three to seven queries mode", mode, metric, kind, "seed", seed, "M", M, "Q", Q, "N", N, "k", k)
+    codes = synth.random_codes(seed, N, M)
+    luts = synth.random_luts(seed + 1, Q, M)
+    if kind == "coarse":
+        luts = (luts // 64).astype(np.uint8)
+    elif kind == "const":
+        luts = np.full_like(luts, 3)
+    vr, ir = oracle.topk(oracle.scan(codes, luts), k, metric == "dot")
+    cd, ld = torch.from_numpy(codes).to(DEV), torch.from_numpy(luts).to(DEV)
+    bolt.debug_speculation(mode)
+    try:
+        v, i = bolt.bolt_scan_topk(cd, ld, metric, k)
+        torch.cuda.synchronize()
+    finally:
+        bolt.debug_speculation(-1)
+    assert np.array_equal(v.cpu().numpy(), vr)
+    assert np.array_equal(i.cpu().numpy(), ir)
+
+
 # speculative starting bounds from a row sample (mode 1), and the same with
 # every bound failing so that each query takes the exact recomputation (mode 2)
 SPEC_CASES = [
