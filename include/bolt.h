@@ -237,6 +237,32 @@ int bolt_scan_topk_ranges(const uint8_t *codes, int64_t N, int32_t M, const uint
                           size_t ws_bytes, void *stream);
 
 /*
+ * Scan + top-k of queries under two metrics in one call (Sec. 3.1 scan,
+ * Sec. 1.2 retrieval; Sec. 4.5 ranks by the smallest distance and the inner
+ * product search by the largest): queries [0, q_split) are ranked as
+ * bolt_scan_topk ranks them under metric_lo, and queries [q_split, Q) as
+ * under metric_hi.  Every result equals that of bolt_scan_topk over the
+ * query's own tables and metric.  Where the two metrics rank in opposite
+ * directions and the shape runs on the matrix-core tiles, one set of
+ * launches serves both sides (a distance and a similarity over the same
+ * database scan together); otherwise the call runs the two sides one after
+ * the other on the stream, with the same workspace.
+ *
+ *   luts_u8    device uint8 [Q][M][16], 16-byte aligned: rows [0, q_split)
+ *              built for metric_lo, rows [q_split, Q) for metric_hi
+ *   q_split    0 .. Q
+ *   ws         device workspace of bolt_scan_topk_split_ws_bytes(N, M, Q,
+ *              q_split, k) bytes, 256-byte aligned
+ * Other arguments, results and errors as for bolt_scan_topk
+ * (BOLT_ERR_INVALID also for q_split outside [0, Q]).
+ */
+size_t bolt_scan_topk_split_ws_bytes(int64_t N, int32_t M, int64_t Q, int64_t q_split, int32_t k);
+int bolt_scan_topk_split(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                         int64_t Q, int64_t q_split, int32_t metric_lo, int32_t metric_hi,
+                         int32_t k, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/*
  * Approximate matrix product (Sec. 4.4: rows of the first matrix are the
  * database, columns of the second are the queries).  With dot-product
  * tables for the K query columns, the product entry is the scan sum S

@@ -64,6 +64,9 @@ _SIGS = {
     "bolt_scan_topk": ([_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "bolt_amm": ([_P, _I64, _I32, _P, _I64, _F32, _F32, _P, _I64, _I32, _P], ctypes.c_int),
     "bolt_scan_f32": ([_P, _I64, _I32, _P, _I64, _P, _I64, _P], ctypes.c_int),
+    "bolt_scan_topk_split_ws_bytes": ([_I64, _I32, _I64, _I64, _I32], _SZ),
+    "bolt_scan_topk_split": ([_P, _I64, _I32, _P, _I64, _I64, _I32, _I32, _I32, _P, _P, _P, _SZ, _P],
+                             ctypes.c_int),
     "bolt_scan_topk_ranges_ws_bytes": ([_P, _I32, _I32, _I64, _I32], _SZ),
     "bolt_scan_topk_ranges": ([_P, _I64, _I32, _P, _I64, _I32, _I32, _P, _I32, _P, _P, _P, _SZ, _P],
                               ctypes.c_int),
@@ -315,6 +318,32 @@ def bolt_scan_topk(codes, luts_u8, metric, k, vals=None, idx=None, ws=None, stre
     wsb = ws.numel() * ws.element_size()
     _check(_lib.bolt_scan_topk(_ptr(codes), N, M, _ptr(luts_u8), Q, metric_id(metric), k,
                                _ptr(vals), _ptr(idx), _ptr(ws), wsb, _stream(stream)))
+    return vals, idx
+
+
+def bolt_scan_topk_split_ws_bytes(N, M, Q, q_split, k):
+    return int(_lib.bolt_scan_topk_split_ws_bytes(N, M, Q, q_split, k))
+
+
+def bolt_scan_topk_split(codes, luts_u8, q_split, metric_lo, metric_hi, k, vals=None, idx=None, ws=None,
+                         stream=None):
+    """Scan + top-k of queries [0, q_split) under metric_lo and [q_split, Q) under
+    metric_hi in one call: (vals, idx) as bolt_scan_topk gives each side."""
+    _dev(codes, torch.uint8, "codes")
+    _dev(luts_u8, torch.uint8, "luts_u8")
+    N = codes.shape[0]
+    Q, M = luts_u8.shape[0], luts_u8.shape[1]
+    if vals is None:
+        vals = torch.empty((Q, k), dtype=torch.uint16, device=codes.device)
+    if idx is None:
+        idx = torch.empty((Q, k), dtype=torch.int32, device=codes.device)
+    nws = bolt_scan_topk_split_ws_bytes(N, M, Q, q_split, k)
+    if ws is None:
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=codes.device)
+    wsb = ws.numel() * ws.element_size()
+    _check(_lib.bolt_scan_topk_split(_ptr(codes), N, M, _ptr(luts_u8), Q, q_split, metric_id(metric_lo),
+                                     metric_id(metric_hi), k, _ptr(vals), _ptr(idx), _ptr(ws), wsb,
+                                     _stream(stream)))
     return vals, idx
 
 

@@ -112,7 +112,7 @@ __device__ void run_tile(const DevDb &db, const DevTile &t, int64_t rows_per_til
     job.q0 = t.q0;
     job.nq = t.nq;
     job.k = (uint32_t)db.k;
-    job.largest = db.largest;
+    job.order = bolt::one_order(db.largest != 0);
     job.fail = db.fail;
     job.lcnt = MF && db.sdist ? db.lcnt : nullptr;
     if (MF) {
@@ -187,15 +187,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     const DevDb db = dbs[it.db];
     const int nq = (db.Q - it.q0) < 32 ? (db.Q - it.q0) : 32;
     const int64_t r0 = (int64_t)it.chunk * db.stride, g0 = (int64_t)it.chunk * bolt::kSpecGroups;
+    const bolt::RankOrder order = bolt::one_order(db.largest != 0);
     if (db.M == 16)
-        bolt::mfma_sample_tile<16, 1, true>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
-                                      gmin);
+        bolt::mfma_sample_tile<16, 1, true>(db.codes, db.luts, it.q0, nq, order, r0, db.sdist, db.G, g0, onehot,
+                                            gmin);
     else if (db.M == 32)
-        bolt::mfma_sample_tile<32, 1, true>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
-                                      gmin);
+        bolt::mfma_sample_tile<32, 1, true>(db.codes, db.luts, it.q0, nq, order, r0, db.sdist, db.G, g0, onehot,
+                                            gmin);
     else
-        bolt::mfma_sample_tile<64, 1, true>(db.codes, db.luts, it.q0, nq, db.largest, r0, db.sdist, db.G, g0, onehot,
-                                      gmin);
+        bolt::mfma_sample_tile<64, 1, true>(db.codes, db.luts, it.q0, nq, order, r0, db.sdist, db.G, g0, onehot,
+                                            gmin);
 }
 
 // Starting bound of each query of a speculative database: the r-th smallest

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void few_scan_kernel(const uint8_t *__restrict
 template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void few_scan_topk_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int nq, uint32_t k,
-    int largest, int64_t rows_per_block, int n_rb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
+    bolt::RankOrder order, int64_t rows_per_block, int n_rb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
     uint32_t *__restrict__ hist, uint32_t *__restrict__ gthr, const int64_t *__restrict__ tiles,
     uint32_t *__restrict__ lcnt)
 {
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     job.q0 = 0;
     job.nq = nq;
     job.k = k;
-    job.largest = largest;
+    job.order = order;
     bolt::few_tile<MM, false>(job, few_lds);
 }
 
@@ -165,16 +165,16 @@ void launch_few_scan(const uint8_t *codes, int64_t N, const uint8_t *luts, int n
 }
 
 template <int MM>
-void launch_few_scan_topk(const uint8_t *codes, int64_t N, const uint8_t *luts, int nq, int k, bool largest,
+void launch_few_scan_topk(const uint8_t *codes, int64_t N, const uint8_t *luts, int nq, int k, bolt::RankOrder order,
                           int64_t rpb, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
                           const int64_t *tiles, uint32_t *lcnt, hipStream_t s)
 {
     if (nq == 1)
         hipLaunchKernelGGL(one_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), 0, s, codes, N, luts, (uint32_t)k,
-                           (int)largest, rpb, cand, ccnt, hist, gthr, tiles, lcnt);
+                           (int)order.largest(0), rpb, cand, ccnt, hist, gthr, tiles, lcnt);
     else
         hipLaunchKernelGGL(few_scan_topk_kernel<MM>, dim3(n_rb), dim3(256), few_lds_bytes(MM, nq, true), s,
-                           codes, N, luts, nq, (uint32_t)k, (int)largest, rpb, n_rb, cand, ccnt, hist, gthr,
+                           codes, N, luts, nq, (uint32_t)k, order, rpb, n_rb, cand, ccnt, hist, gthr,
                            tiles, lcnt);
 }
 
@@ -281,20 +281,20 @@ int64_t few_rows_per_block(int64_t N, int M, int nq)
 // Stage 1 of the fused few-query path: candidates [Q][n_rb][k] (packed,
 // counts [Q][n_rb] in ccnt and histograms in hist, if given) and bounds.
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                  bool largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
+                  bolt::RankOrder order, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
                   const int64_t *tiles, uint32_t *lcnt, hipStream_t s)
 {
     const int nq = (int)Q;
     const int64_t rpb = few_rows_per_block(N, M, nq);
     bolt::ProfScope prof_("scan_topk_few", s);
     switch (M) {
-    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+    case 8: launch_few_scan_topk<8>(codes, N, luts, nq, k, order, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
                                     s); break;
-    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+    case 16: launch_few_scan_topk<16>(codes, N, luts, nq, k, order, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
                                     s); break;
-    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+    case 32: launch_few_scan_topk<32>(codes, N, luts, nq, k, order, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
                                     s); break;
-    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, largest, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
+    case 64: launch_few_scan_topk<64>(codes, N, luts, nq, k, order, rpb, n_rb, cand, ccnt, hist, gthr, tiles, lcnt,
                                     s); break;
     default: return fail(BOLT_ERR_UNSUPPORTED, "few-query scan takes M in {8, 16, 32, 64}");
     }

@@ -77,7 +77,7 @@ __device__ __forceinline__ void tile_of(int w, int n_qb, int &qb, int &rb)
 // caller's tile list, or span rows from rb * stride); false if the
 // workgroup has no tile (padding of the XCD placement).
 __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uint8_t *codes, int64_t N,
-                                         const uint8_t *luts, int64_t Q, uint32_t k, int largest, int n_rb,
+                                         const uint8_t *luts, int64_t Q, uint32_t k, bolt::RankOrder order, int n_rb,
                                          uint64_t *cand, uint32_t *ccnt, uint32_t *hist, int shift,
                                          uint32_t *fail, uint32_t *gthr, const int64_t *tiles, int64_t stride,
                                          int64_t span, uint32_t *lcnt, bolt::TileJob &job)
@@ -107,20 +107,20 @@ __device__ __forceinline__ bool tile_job(int w, int n_qb, int qb_size, const uin
     job.q0 = (int64_t)qb * qb_size;
     job.nq = (int)((Q - job.q0) < qb_size ? (Q - job.q0) : qb_size);
     job.k = k;
-    job.largest = largest;
+    job.order = order;
     return true;
 }
 
 template <int MM, int NG>
 __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
-    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
+    uint32_t k, bolt::RankOrder order, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
     uint32_t *__restrict__ hist, uint32_t *__restrict__ fail, uint32_t *__restrict__ gthr,
     const int64_t *__restrict__ tiles, int64_t stride, int64_t span)
 {
     __shared__ bolt::GroupedLds<MM, NG> L;
     bolt::TileJob job;
-    if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
+    if (tile_job(blockIdx.x, n_qb, 8 * NG, codes, N, luts, Q, k, order, n_rb, cand, ccnt, hist,
                  bolt::hist_shift(MM), fail, gthr, tiles, stride, span, nullptr, job))
         bolt::grouped_tile<MM, NG>(job, L);
 }
@@ -131,13 +131,13 @@ __global__ __launch_bounds__(256) void scan_topk_grouped_kernel(
 template <int MM, int NT, bool FREE, bool SP>
 __global__ __launch_bounds__(256) void scan_topk_mfma_kernel(
     const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, int64_t Q,
-    uint32_t k, int largest, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
+    uint32_t k, bolt::RankOrder order, int n_rb, int n_qb, uint64_t *__restrict__ cand, uint32_t *__restrict__ ccnt,
     uint32_t *__restrict__ hist, uint32_t *__restrict__ fail, uint32_t *__restrict__ gthr,
     const int64_t *__restrict__ tiles, int64_t stride, int64_t span, uint32_t *__restrict__ lcnt)
 {
     __shared__ bolt::MfmaLds<NT> L;
     bolt::TileJob job;
-    if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist,
+    if (tile_job(blockIdx.x, n_qb, 32 * NT, codes, N, luts, Q, k, order, n_rb, cand, ccnt, hist,
                  bolt::hist_shift(MM), fail, gthr, tiles, stride, span, lcnt, job))
         bolt::mfma_tile<MM, NT, FREE, SP>(job, L);
 }
@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
                                                          int64_t slots_per_chunk, uint32_t k,
                                                          uint32_t *__restrict__ gthr,
                                                          uint32_t *__restrict__ hist, int shift,
-                                                         int largest, uint32_t smax, uint64_t *__restrict__ dst,
+                                                         bolt::RankOrder order, uint32_t smax,
+                                                         uint64_t *__restrict__ dst,
                                                          uint32_t *__restrict__ dst_cnt,
                                                          uint16_t *__restrict__ vals,
                                                          int32_t *__restrict__ idx, uint32_t *__restrict__ lcnt,
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
         if (fail && (n < k || fail[q]))
             flag_redo(q, gthr, hist, lcnt, fail, redo);
         else
-            bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
+            bolt::merge_finish(L, n, k, order.largest(q), smax, vals + q * k, idx + q * k);
         return;
     }
     if (threadIdx.x < 64 && n > k)
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void topk_merge_kernel(const uint64_t *__restr
 __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__restrict__ src,
                                                           const uint32_t *__restrict__ src_cnt, int n_chunks,
                                                           uint32_t k, uint32_t *__restrict__ gthr,
-                                                          int largest, uint32_t smax,
+                                                          bolt::RankOrder order, uint32_t smax,
                                                           uint16_t *__restrict__ vals, int32_t *__restrict__ idx,
                                                           uint32_t *__restrict__ hist, uint32_t *__restrict__ lcnt,
                                                           uint32_t *__restrict__ fail, uint32_t *__restrict__ redo)
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
         flag_redo(q, gthr, hist, lcnt, fail, redo);
         return;
     }
-    bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
+    bolt::merge_finish(L, n, k, order.largest(q), smax, vals + q * k, idx + q * k);
 }
 
 // Merge of the dense candidate lists (sampled bounds on the pair-table and
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256) void topk_merge2_kernel(const uint64_t *__rest
 __global__ __launch_bounds__(256) void topk_list_merge_kernel(const uint64_t *__restrict__ cand,
                                                               uint32_t *__restrict__ lcnt, int64_t per_query,
                                                               uint32_t k, int shift, uint32_t *__restrict__ gthr,
-                                                              int largest,
+                                                              bolt::RankOrder order,
                                                               uint32_t smax, uint16_t *__restrict__ vals,
                                                               int32_t *__restrict__ idx, uint32_t *__restrict__ hist,
                                                               uint32_t *__restrict__ fail, uint32_t *__restrict__ redo)
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(256) void topk_list_merge_kernel(const uint64_t *__
     if (n < k || fail[q])
         flag_redo(q, gthr, hist, lcnt, fail, redo);
     else
-        bolt::merge_finish(L, n, k, largest, smax, vals + q * k, idx + q * k);
+        bolt::merge_finish(L, n, k, order.largest(q), smax, vals + q * k, idx + q * k);
 }
 
 // Rows [r0, r1) of tile rb: the caller's list, else rpb rows each.
@@ -370,7 +371,7 @@ __device__ __forceinline__ void tile_rows(const int64_t *__restrict__ tiles, int
 // keys and at most that bin's other keys.
 template <int MM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void topk_redo_scan_kernel(
-    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k, int largest,
+    const uint8_t *__restrict__ codes, int64_t N, const uint8_t *__restrict__ luts, uint32_t k, bolt::RankOrder order,
     int64_t n_rb, int64_t rpb, const int64_t *__restrict__ tiles, uint64_t *cand, uint32_t *hist, uint32_t *gthr,
     uint32_t *done, uint32_t *lcnt, const uint32_t *__restrict__ redo)
 {
@@ -386,8 +387,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void t
         for (int i = threadIdx.x; i < bolt::kHistBins; i += 256)
             hl[i] = 0;   // the tile's first barrier orders these before the counts
         uint32_t *hq = hist + q * bolt::kHistBins;
-        bolt::one_query_tile<MM, true>(codes, r0, r1, luts + q * MM * 16, k, largest, cand + q * n_rb * k, nullptr,
-                                       nullptr, gthr + q, lds, lcnt + q, hl, hq);
+        bolt::one_query_tile<MM, true>(codes, r0, r1, luts + q * MM * 16, k, order.largest(q), cand + q * n_rb * k,
+                                       nullptr, nullptr, gthr + q, lds, lcnt + q, hl, hq);
         // The tile's bins, bound and list went out as device-scope atomics
         // and stores: each wave waits for its own to complete before the
         // tile is counted (a device-scope fence here would also write back
@@ -433,7 +434,7 @@ constexpr int64_t kRedoChunk = 16384;
 
 __global__ __launch_bounds__(256) void topk_redo_merge_kernel(uint64_t *cand, const uint32_t *__restrict__ lcnt,
                                                               int64_t n_rb, uint32_t k,
-                                                              const uint32_t *__restrict__ gthr, int largest,
+                                                              const uint32_t *__restrict__ gthr, bolt::RankOrder order,
                                                               uint32_t smax, uint32_t *hist,
                                                               const uint32_t *__restrict__ redo,
                                                               uint16_t *__restrict__ vals, int32_t *__restrict__ idx)
@@ -506,18 +507,19 @@ __global__ __launch_bounds__(256) void topk_redo_merge_kernel(uint64_t *cand, co
                 __syncthreads();
                 m = total;
             }
-            bolt::merge_finish(L, m, k, largest, smax, vals + q * k, idx + q * k);
+            bolt::merge_finish(L, m, k, order.largest(q), smax, vals + q * k, idx + q * k);
         }
         __syncthreads();
     }
 }
 
-// Result padding when no row is scanned: 65535 / 0 and index -1.
-__global__ void pad_topk_kernel(uint16_t *vals, int32_t *idx, int64_t n, int largest)
+// Result padding when no row is scanned (n results, k per query): 65535 / 0
+// and index -1.
+__global__ void pad_topk_kernel(uint16_t *vals, int32_t *idx, int64_t n, int64_t k, bolt::RankOrder order)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) {
-        vals[i] = (uint16_t)(largest ? 0u : 0xFFFFu);
+        vals[i] = (uint16_t)(order.largest(i / k) ? 0u : 0xFFFFu);
         idx[i] = -1;
     }
 }
@@ -566,15 +568,15 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint64_t *__restri
 // to out[q][c * kSpecGroups ...] (G entries per query).
 template <int MM, int NT, bool SP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void spec_sample_kernel(
-    const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t Q, int largest, int64_t stride,
-    int64_t G, uint16_t *__restrict__ out)
+    const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t Q, bolt::RankOrder order,
+    int64_t stride, int64_t G, uint16_t *__restrict__ out)
 {
     __shared__ bolt::OneHot onehot;
     __shared__ __attribute__((aligned(16))) uint16_t gmin[32 * NT * bolt::kSpecGminStride];
     const int64_t q0 = (int64_t)blockIdx.x * 32 * NT;
     const int nq = (int)((Q - q0) < 32 * NT ? (Q - q0) : 32 * NT);
     const int64_t c = blockIdx.y;
-    bolt::mfma_sample_tile<MM, NT, SP>(codes, luts, q0, nq, largest, c * stride, out, G, c * bolt::kSpecGroups, onehot,
+    bolt::mfma_sample_tile<MM, NT, SP>(codes, luts, q0, nq, order, c * stride, out, G, c * bolt::kSpecGroups, onehot,
                                    gmin);
 }
 
@@ -743,19 +745,19 @@ FusedPlan plan_fused(int64_t N, int M, int64_t Q, int k, bool vec_ok)
 // list, or of span rows every stride rows; k candidates per tile and query.
 template <int MM>
 void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k,
-                 int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *fail,
+                 bolt::RankOrder order, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *fail,
                  uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, uint32_t *lcnt,
                  const char *prof_name, hipStream_t s)
 {
     if (p.kind == 1) {   // profiled inside under its own name
-        bolt::few_scan_topk(codes, N, MM, luts, Q, k, largest != 0, n_rb, cand, ccnt, hist, gthr, tiles, lcnt, s);
+        bolt::few_scan_topk(codes, N, MM, luts, Q, k, order, n_rb, cand, ccnt, hist, gthr, tiles, lcnt, s);
         return;
     }
     const unsigned grid = (unsigned)(p.n_qb * ((n_rb + 7) / 8 * 8));
     bolt::ProfScope prof_(prof_name, s);
 #define BOLT_MFMA_SCAN(FREE, SP)                                                                                  \
     hipLaunchKernelGGL((scan_topk_mfma_kernel<MM, kMfmaNT, FREE, SP>), dim3(grid), dim3(256), 0, s, codes, N,    \
-                       luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles, stride, \
+                       luts, Q, (uint32_t)k, order, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles, stride, \
                        span, FREE ? lcnt : nullptr)
     const bool sp = bolt::g_sparse_mfma != 0;
     if (p.kind == 3 && p.spec && sp)
@@ -769,17 +771,18 @@ void launch_scan(const FusedPlan &p, const uint8_t *codes, int64_t N, const uint
 #undef BOLT_MFMA_SCAN
     else
         hipLaunchKernelGGL((scan_topk_grouped_kernel<MM, ng_for<MM>()>), dim3(grid), dim3(256), 0, s, codes, N,
-                           luts, Q, (uint32_t)k, largest, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles,
+                           luts, Q, (uint32_t)k, order, n_rb, p.n_qb, cand, ccnt, hist, fail, gthr, tiles,
                            stride, span);
 }
 
 void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q,
-                   int k, int largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *fail,
-                   uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span, uint32_t *lcnt,
+                   int k, bolt::RankOrder order, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist,
+                   uint32_t *fail, uint32_t *gthr, const int64_t *tiles, int64_t stride, int64_t span,
+                   uint32_t *lcnt,
                    const char *prof_name, hipStream_t s)
 {
 #define BOLT_SCAN_M(MMV)                                                                                         \
-    launch_scan<MMV>(p, codes, N, luts, Q, k, largest, n_rb, cand, ccnt, hist, fail, gthr, tiles, stride, span,  \
+    launch_scan<MMV>(p, codes, N, luts, Q, k, order, n_rb, cand, ccnt, hist, fail, gthr, tiles, stride, span,  \
                      lcnt, prof_name, s)
     switch (M) {
     case 8: BOLT_SCAN_M(8); break;
@@ -790,17 +793,17 @@ void launch_scan_m(int M, const FusedPlan &p, const uint8_t *codes, int64_t N, c
 #undef BOLT_SCAN_M
 }
 
-void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_t Q, int largest, int64_t stride,
-                        int64_t G, int nsc, uint16_t *out, hipStream_t s)
+void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_t Q, bolt::RankOrder order,
+                        int64_t stride, int64_t G, int nsc, uint16_t *out, hipStream_t s)
 {
     const int nt = kMfmaNT;
     const dim3 grid((unsigned)((Q + 32 * nt - 1) / (32 * nt)), (unsigned)nsc);
 #define BOLT_SAMPLE_M(MM)                                                                                           \
     if (bolt::g_sparse_mfma)                                                                                        \
-        hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT, true>), grid, dim3(256), 0, s, codes, luts, Q, largest, \
+        hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT, true>), grid, dim3(256), 0, s, codes, luts, Q, order, \
                            stride, G, out);                                                                         \
     else                                                                                                            \
-        hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT, false>), grid, dim3(256), 0, s, codes, luts, Q, largest,\
+        hipLaunchKernelGGL((spec_sample_kernel<MM, kMfmaNT, false>), grid, dim3(256), 0, s, codes, luts, Q, order,\
                            stride, G, out)
     switch (M) {
     case 8: BOLT_SAMPLE_M(8); break;
@@ -817,14 +820,14 @@ void launch_spec_sample(int M, const uint8_t *codes, const uint8_t *luts, int64_
 constexpr int64_t kRedoGrid = 1024;
 constexpr int64_t kRedoMergeGrid = 256;
 
-void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k, int largest,
+void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, int64_t Q, int k, bolt::RankOrder order,
                  const FusedPlan &p, const int64_t *tiles, uint64_t *cand, uint32_t *gthr, uint32_t *hist,
                  uint32_t *fail, uint32_t *lcnt, const uint32_t *redo, uint16_t *vals, int32_t *idx, hipStream_t s)
 {
     const int64_t items = (int64_t)p.n_rb * Q;
     const dim3 grid((unsigned)(items < kRedoGrid ? items : kRedoGrid));
 #define BOLT_REDO_M(MM)                                                                                          \
-    hipLaunchKernelGGL(topk_redo_scan_kernel<MM>, grid, dim3(256), 0, s, codes, N, luts, (uint32_t)k, largest,   \
+    hipLaunchKernelGGL(topk_redo_scan_kernel<MM>, grid, dim3(256), 0, s, codes, N, luts, (uint32_t)k, order,   \
                        (int64_t)p.n_rb, p.rpb, tiles, cand, hist, gthr, fail, lcnt, redo)
     switch (M) {
     case 8: BOLT_REDO_M(8); break;
@@ -836,7 +839,7 @@ void launch_redo(int M, const uint8_t *codes, int64_t N, const uint8_t *luts, in
     const int64_t merge_items = Q * (((int64_t)p.n_rb * k + kRedoChunk - 1) / kRedoChunk);
     hipLaunchKernelGGL(topk_redo_merge_kernel,
                        dim3((unsigned)(merge_items < kRedoMergeGrid ? merge_items : kRedoMergeGrid)), dim3(256), 0, s,
-                       cand, lcnt, (int64_t)p.n_rb, (uint32_t)k, gthr, largest, 255u * (uint32_t)M, hist, redo, vals,
+                       cand, lcnt, (int64_t)p.n_rb, (uint32_t)k, gthr, order, 255u * (uint32_t)M, hist, redo, vals,
                        idx);
 }
 
@@ -879,6 +882,12 @@ static size_t plan_bytes(const FusedPlan &p)
            p.redo_bytes;
 }
 
+bool fused_on_matrix_cores(int64_t N, int M, int64_t Q, int k, bool vec_ok)
+{
+    const FusedPlan p = plan_fused(N, M, Q, k, vec_ok);
+    return p.ok && p.kind == 3;
+}
+
 size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
 {
     FusedPlan p = plan_fused(N, M, Q, k, true);
@@ -890,7 +899,7 @@ size_t fused_ws_bytes(int64_t N, int M, int64_t Q, int k)
 // Launches of a planned fused scan + top-k (tiles: null, or the caller's
 // row ranges cut into p.n_rb tiles, already in device memory).
 static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M, const uint8_t *luts,
-                     int64_t Q, int k, bool largest, uint16_t *vals, int32_t *idx, char *w,
+                     int64_t Q, int k, bolt::RankOrder order, uint16_t *vals, int32_t *idx, char *w,
                      const int64_t *tiles, hipStream_t s)
 {
     uint64_t *cand = reinterpret_cast<uint64_t *>(w);
@@ -917,7 +926,7 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
         // sample group minima, then each query's starting bound (and cleared histogram)
         {
             bolt::ProfScope prof_("spec_sample", s);
-            launch_spec_sample(M, codes, luts, Q, (int)largest, p.spec_stride, G, p.spec_nsc, gmins, s);
+            launch_spec_sample(M, codes, luts, Q, order, p.spec_stride, G, p.spec_nsc, gmins, s);
         }
         bolt::ProfScope prof_("spec_select", s);
         hipLaunchKernelGGL(spec_select_kernel, dim3((unsigned)Q), dim3(256), 0, s, gmins, G, (uint32_t)p.spec_r,
@@ -930,7 +939,7 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     // with speculative bounds (a few keys per tile and query) the tiles count
     // their kept keys into hist as they write them; otherwise a separate
     // kernel aggregates the counts per workgroup first
-    launch_scan_m(M, p, codes, N, luts, Q, k, (int)largest, p.n_rb, cand, ccnt, p.spec && !lists ? hist : nullptr,
+    launch_scan_m(M, p, codes, N, luts, Q, k, order, p.n_rb, cand, ccnt, p.spec && !lists ? hist : nullptr,
                   fail, gthr, tiles, kRowsPerBlock, kRowsPerBlock, lcnt, scan_prof_name(p.kind), s);
     if (!p.spec) {
         bolt::ProfScope prof_("cand_hist", s);
@@ -941,22 +950,22 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
     if (lists) {
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_list_merge_kernel, dim3((unsigned)Q), dim3(256), 0, s, cand, lcnt,
-                           (int64_t)p.n_rb * k, (uint32_t)k, bolt::hist_shift(M), gthr, (int)largest, smax, vals, idx,
+                           (int64_t)p.n_rb * k, (uint32_t)k, bolt::hist_shift(M), gthr, order, smax, vals, idx,
                            hist, fail, redo);
     } else {
         bolt::ProfScope prof_("topk_merge", s);
         hipLaunchKernelGGL(topk_merge_kernel, dim3((unsigned)Q, (unsigned)p.n_chunks), dim3(256), 0, s, cand, ccnt,
                            (int64_t)p.n_rb, p.n_chunks > 1 ? p.chunk : (int64_t)p.n_rb, (uint32_t)k, gthr, hist,
-                           bolt::hist_shift(M), (int)largest, smax, level2, level2_cnt, vals, idx, lcnt_all, fail,
+                           bolt::hist_shift(M), order, smax, level2, level2_cnt, vals, idx, lcnt_all, fail,
                            redo);
         if (p.n_chunks > 1)
             hipLaunchKernelGGL(topk_merge2_kernel, dim3((unsigned)Q), dim3(256), 0, s, level2, level2_cnt,
-                               p.n_chunks, (uint32_t)k, gthr, (int)largest, smax, vals, idx, hist, lcnt_all, fail,
+                               p.n_chunks, (uint32_t)k, gthr, order, smax, vals, idx, hist, lcnt_all, fail,
                                redo);
     }
     if (p.spec) {
         bolt::ProfScope prof_("topk_redo", s);
-        launch_redo(M, codes, N, luts, Q, k, (int)largest, p, tiles, cand, gthr, hist, fail, lcnt_all, redo, vals,
+        launch_redo(M, codes, N, luts, Q, k, order, p, tiles, cand, gthr, hist, fail, lcnt_all, redo, vals,
                     idx, s);
     }
     return check_launch("bolt_scan_topk (fused)");
@@ -965,8 +974,7 @@ static int run_fused(const FusedPlan &p, const uint8_t *codes, int64_t N, int M,
 
 // Fused scan + top-k; returns BOLT_ERR_UNSUPPORTED when the shape has no fused kernel.
 int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                    bool largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
-                    hipStream_t s)
+                    bolt::RankOrder order, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes, hipStream_t s)
 {
     const bool vec_ok = aligned(codes, 16) && aligned(luts, 16);
     FusedPlan p = plan_fused(N, M, Q, k, vec_ok);
@@ -975,7 +983,7 @@ int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts,
     const size_t need = plan_bytes(p);
     if (ws_bytes < need || !aligned(ws, 256))
         return fail(BOLT_ERR_NOMEM, "fused scan+top-k needs %zu workspace bytes", need);
-    return run_fused(p, codes, N, M, luts, Q, k, largest, vals, idx, reinterpret_cast<char *>(ws), nullptr, s);
+    return run_fused(p, codes, N, M, luts, Q, k, order, vals, idx, reinterpret_cast<char *>(ws), nullptr, s);
 }
 
 // Row ranges: the tiles of [start, end) ranges of at most p.rpb rows each.
@@ -1026,7 +1034,7 @@ int scan_topk_ranges(const uint8_t *codes, int64_t N, int M, const uint8_t *luts
     if (p.n_rb == 0 && p.kind != 0) {
         // no rows at all: the padding of an empty database
         hipLaunchKernelGGL(pad_topk_kernel, dim3((unsigned)((Q * k + 255) / 256)), dim3(256), 0, s, vals, idx,
-                           Q * k, (int)largest);
+                           Q * k, (int64_t)k, bolt::one_order(largest));
         return check_launch("bolt_scan_topk_ranges");
     }
     if (!p.ok)
@@ -1040,7 +1048,7 @@ int scan_topk_ranges(const uint8_t *codes, int64_t N, int M, const uint8_t *luts
     if (hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(int64_t), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return check_launch("bolt_scan_topk_ranges (tile list)");
-    return run_fused(p, codes, N, M, luts, Q, k, largest, vals, idx, w, dtiles, s);
+    return run_fused(p, codes, N, M, luts, Q, k, bolt::one_order(largest), vals, idx, w, dtiles, s);
 }
 
 }  // namespace bolt

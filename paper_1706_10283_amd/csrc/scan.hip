@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void scan_mfma_kernel(const uint8_t *__restric
     const int64_t r1 = (r0 + rpb) < N ? (r0 + rpb) : N;
     bolt::onehot_init(onehot);
     bolt::i32x4 tb[NT][MM / 2];
-    bolt::mfma_load_tables<MM, NT>(luts, q0, nq, 0, tb);
+    bolt::mfma_load_tables<MM, NT>(luts, q0, nq, bolt::one_order(false), tb);
     __syncthreads();
     uint32_t nxt[NW];
     {

@@ -7,6 +7,21 @@ namespace bolt {
 
 enum class OutMode { U16, F32, F32T };
 
+// Which sums a call's queries rank by: the smallest, or the largest (through
+// d = 255 M - sum).  Queries before `split` take order `lo` (1: largest) and
+// those at or beyond it the other order, so that one launch can serve a
+// distance metric and a similarity side by side; a call of one order has
+// split = kOneOrder.
+constexpr int64_t kOneOrder = INT64_MAX;
+
+struct RankOrder {
+    int64_t split;
+    int lo;
+    __host__ __device__ __forceinline__ bool largest(int64_t q) const { return (q >= split) != (lo != 0); }
+};
+
+__host__ __device__ __forceinline__ RankOrder one_order(bool largest) { return RankOrder{kOneOrder, largest ? 1 : 0}; }
+
 // Queries below this count use the few-query scan (tables as 16-byte rows).
 constexpr int kSmallQ = 8;
 
@@ -28,8 +43,10 @@ int scan_topk_ranges(const uint8_t *codes, int64_t N, int M, const uint8_t *luts
                      bool largest, const int64_t *ranges, int n_ranges, uint16_t *vals, int32_t *idx, void *ws,
                      size_t ws_bytes, hipStream_t s);
 int scan_topk_fused(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                    bool largest, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes,
-                    hipStream_t s);
+                    RankOrder order, uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes, hipStream_t s);
+// Whether the fused plan of the shape runs on the matrix-core tiles (the
+// only kind that serves queries of both orders in one launch).
+bool fused_on_matrix_cores(int64_t N, int M, int64_t Q, int k, bool vec_ok);
 
 // Few-query scans (few.hip).
 bool few_supported(int M, int64_t Q);
@@ -39,7 +56,7 @@ int few_scan(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_
 int64_t few_rows_per_block(int64_t N, int M, int nq);
 size_t few_fused_lds_bytes(int M, int nq);
 int few_scan_topk(const uint8_t *codes, int64_t N, int M, const uint8_t *luts, int64_t Q, int k,
-                  bool largest, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
+                  RankOrder order, int n_rb, uint64_t *cand, uint32_t *ccnt, uint32_t *hist, uint32_t *gthr,
                   const int64_t *tiles, uint32_t *lcnt, hipStream_t s);
 
 // Test hook: 1 forces the unfused scan-then-select path of bolt_scan_topk.

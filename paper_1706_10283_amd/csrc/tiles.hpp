@@ -60,7 +60,7 @@ struct TileJob {
     int64_t q0;             // first query of the tile
     int nq;                 // queries of the tile
     uint32_t k;
-    int largest;
+    RankOrder order;
 };
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -187,7 +187,8 @@ __device__ void grouped_tile(const TileJob &job, GroupedLds<MM, NG> &L)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nq = job.nq;
     const uint32_t k = job.k;
-    const int largest = job.largest;
+    // one order per grouped tile: calls that mix orders never plan grouped tiles
+    const int largest = job.order.largest(job.q0);
     const int64_t q0 = job.q0;
 
     uint16_t *tab16 = reinterpret_cast<uint16_t *>(L.tab);
@@ -424,13 +425,13 @@ extern int g_sparse_mfma;
 // all of them are in flight together.
 template <int MM, int NT>
 __device__ __forceinline__ void mfma_load_tables(const uint8_t *__restrict__ luts, int64_t q0, int nq,
-                                                 int largest, i32x4 (&tb)[NT][MM / 2])
+                                                 RankOrder order, i32x4 (&tb)[NT][MM / 2])
 {
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
-    const uint32_t flip = largest ? 0x7F7F7F7Fu : 0x80808080u;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int q = 32 * t + col;
+        const uint32_t flip = order.largest(q0 + q) ? 0x7F7F7F7Fu : 0x80808080u;
         const uint32_t keep = q < nq ? 0xFFFFFFFFu : 0u;
         const uint8_t *src = luts + ((q0 + (q < nq ? q : nq - 1)) * MM + half) * 16;
 #pragma unroll
@@ -548,7 +549,7 @@ __device__ void mfma_tile(const TileJob &job, MfmaLds<NT> &L)
     }
     // absent queries: zero tables and bound 0
     i32x4 tb[NT][KS];
-    mfma_load_tables<MM, NT>(job.luts, q0, nq, job.largest, tb);
+    mfma_load_tables<MM, NT>(job.luts, q0, nq, job.order, tb);
     __syncthreads();
 
     const int64_t r0 = job.r0, r1 = job.r1;
@@ -775,7 +776,7 @@ constexpr int kSpecGminStride = kSpecGroups + 8;   // uint16 per query row in LD
 
 template <int MM, int NT, bool SP>
 __device__ void mfma_sample_tile(const uint8_t *__restrict__ codes, const uint8_t *__restrict__ luts, int64_t q0,
-                                 int nq, int largest, int64_t r0, uint16_t *__restrict__ out, int64_t G,
+                                 int nq, RankOrder order, int64_t r0, uint16_t *__restrict__ out, int64_t G,
                                  int64_t g0, OneHot &oh, uint16_t *gmin)
 {
     constexpr int NW = MM / 8;
@@ -784,7 +785,7 @@ __device__ void mfma_sample_tile(const uint8_t *__restrict__ codes, const uint8_
     const int half = lane >> 5, col = lane & 31;
     onehot_init(oh);
     i32x4 tb[NT][MM / 2];
-    mfma_load_tables<MM, NT>(luts, q0, nq, largest, tb);
+    mfma_load_tables<MM, NT>(luts, q0, nq, order, tb);
     __syncthreads();
     // codes one pass ahead (the last pass re-reads its own rows)
     uint32_t nxt[NW];
@@ -1163,7 +1164,6 @@ __device__ void few_tile_impl(const TileJob &job, char *lds)
     constexpr int CAP = few_cap(MM);
     const int nq = ONE ? 1 : job.nq;
     const uint32_t k = job.k;
-    const int largest = job.largest;
     uint16_t *pt = reinterpret_cast<uint16_t *>(lds);                         // [nq][MM/2][256]
     uint32_t *buf = reinterpret_cast<uint32_t *>(pt + nq * (MM / 2) * 256);  // [nq][CAP]
     uint32_t *cnt = buf + nq * CAP;
@@ -1188,6 +1188,7 @@ __device__ void few_tile_impl(const TileJob &job, char *lds)
             uint32_t s[R];
             pair_sums<MM, R, ONE>(reinterpret_cast<const char *>(pt + q * (MM / 2) * 256), cw, s);
             const uint32_t bq = bnd[q];
+            const bool largest = job.order.largest(job.q0 + q);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t n = base + tid + 256 * r;

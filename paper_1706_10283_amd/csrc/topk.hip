@@ -11,6 +11,7 @@
 // block-wide prefix sum over contiguous per-thread runs.  The k survivors are
 // sorted by key with a bitonic network in LDS.  One workgroup per row.
 // For the largest-k direction every value v is replaced by 65535 - v.
+#include <algorithm>
 #include <mutex>
 
 #include "common.hpp"
@@ -383,7 +384,7 @@ static int scan_topk_impl(const uint8_t *codes, int64_t N, int32_t M, const uint
     hipStream_t s = as_stream(stream);
     const bool largest = mt.largest;
     if (N > 0 && !g_force_unfused_topk) {
-        const int st = scan_topk_fused(codes, N, M, luts_u8, Q, k, largest, vals, idx, ws, ws_bytes, s);
+        const int st = scan_topk_fused(codes, N, M, luts_u8, Q, k, one_order(largest), vals, idx, ws, ws_bytes, s);
         if (st != BOLT_ERR_UNSUPPORTED)
             return st;
     }
@@ -391,6 +392,56 @@ static int scan_topk_impl(const uint8_t *codes, int64_t N, int32_t M, const uint
     if (N > 0)
         BOLT_TRY(scan_u16(codes, N, M, luts_u8, Q, d, N, s));
     return topk_u16(d, Q, N, N, k, largest, vals, idx, s);
+}
+
+extern "C" size_t bolt_scan_topk_split_ws_bytes(int64_t N, int32_t M, int64_t Q, int64_t q_split, int32_t k)
+{
+    if (Q <= 0 || q_split < 0 || q_split > Q)
+        return 0;
+    // enough for one set of launches over all Q queries and for either side alone
+    size_t need = scan_topk_need(N, M, Q, k, true);
+    if (q_split > 0)
+        need = std::max(need, scan_topk_need(N, M, q_split, k, true));
+    if (q_split < Q)
+        need = std::max(need, scan_topk_need(N, M, Q - q_split, k, true));
+    return need;
+}
+
+extern "C" int bolt_scan_topk_split(const uint8_t *codes, int64_t N, int32_t M, const uint8_t *luts_u8,
+                                    int64_t Q, int64_t q_split, int32_t metric_lo, int32_t metric_hi, int32_t k,
+                                    uint16_t *vals, int32_t *idx, void *ws, size_t ws_bytes, void *stream)
+{
+    using namespace bolt;
+    BOLT_TRY(check_M(M));
+    BOLT_TRY(validate_topk(Q, N, k));
+    Metric lo, hi;
+    BOLT_TRY(decode_metric(metric_lo, &lo));
+    BOLT_TRY(decode_metric(metric_hi, &hi));
+    if (q_split < 0 || q_split > Q)
+        return fail(BOLT_ERR_INVALID, "q_split must be in [0, Q] (got %lld, Q = %lld)", (long long)q_split,
+                    (long long)Q);
+    if (Q == 0)
+        return BOLT_OK;
+    if (!vals || !idx || (N > 0 && (!codes || !luts_u8)))
+        return fail(BOLT_ERR_INVALID, "bolt_scan_topk_split: null pointer");
+    if (N > 0 && !(aligned(codes, 16) && aligned(luts_u8, 16)))
+        return fail(BOLT_ERR_INVALID, "bolt_scan_topk_split: codes and luts_u8 must be 16-byte aligned");
+    const size_t need = bolt_scan_topk_split_ws_bytes(N, M, Q, q_split, k);
+    if (ws_bytes < need || (need && !ws))
+        return fail(BOLT_ERR_NOMEM, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+    if (need && !aligned(ws, 256))
+        return fail(BOLT_ERR_INVALID, "workspace must be 256-byte aligned");
+    // the result depends on the metric only through the direction
+    if (lo.largest == hi.largest || q_split == Q)
+        return scan_topk_impl(codes, N, M, luts_u8, Q, metric_lo, k, vals, idx, ws, ws_bytes, stream);
+    if (q_split == 0)
+        return scan_topk_impl(codes, N, M, luts_u8, Q, metric_hi, k, vals, idx, ws, ws_bytes, stream);
+    if (N > 0 && !g_force_unfused_topk && fused_on_matrix_cores(N, M, Q, k, true))
+        return scan_topk_fused(codes, N, M, luts_u8, Q, k, RankOrder{q_split, lo.largest ? 1 : 0}, vals, idx, ws,
+                               ws_bytes, as_stream(stream));
+    BOLT_TRY(scan_topk_impl(codes, N, M, luts_u8, q_split, metric_lo, k, vals, idx, ws, ws_bytes, stream));
+    return scan_topk_impl(codes, N, M, luts_u8 + q_split * M * 16, Q - q_split, metric_hi, k, vals + q_split * k,
+                          idx + q_split * k, ws, ws_bytes, stream);
 }
 
 static int validate_ranges(const int64_t *ranges, int32_t n_ranges, int64_t N)

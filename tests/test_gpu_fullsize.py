@@ -5,7 +5,8 @@ configuration the benchmark times, through the C ABI.
   Q = 1000 queries, L2 and dot, top-100.  Every code and every uint8 table
   entry is compared with the oracle; the scan + top-k of all 1000 queries
   runs as one call and a seeded sample of queries is compared with the
-  oracle's full scan and top-k over all N rows.
+  oracle's full scan and top-k over all N rows; both metrics' queries then
+  run as one two-metric call, as the benchmark step runs them.
 * Matrix product: A 200000 x 256, M = 32, K = 1024 dot tables; the full
   [K][N] fp32 output is computed and a sample of its rows is compared with
   the oracle bit for bit.
@@ -93,6 +94,7 @@ def test_single_database_full_size(bolt, mixture, M):
 
     codes_d = torch.from_numpy(ref_codes).to(DEV)
     sample = synth.permutation_prefix(synth.seed_for(2, 6) + M, Q1, 12)
+    tables, results = [], []
     for metric in ("l2", "dot"):
         a, offs, _, _ = oracle.learn_quantizer(Qtrain, oracle.encode(Xtrain, C, M), C, metric)
         # a2: all 1000 queries' tables
@@ -107,6 +109,17 @@ def test_single_database_full_size(bolt, mixture, M):
         vr, ir = oracle.topk(S, K1, metric == "dot")
         assert np.array_equal(v[sample], vr)
         assert np.array_equal(i[sample], ir)
+        tables.append(l8)
+        results.append((v, i, vr, ir))
+    # both metrics' 2000 queries as one two-metric call: each side equals its
+    # one-metric call over all queries, and the sampled queries the oracle
+    v2, i2 = bolt.bolt_scan_topk_split(codes_d, torch.from_numpy(np.concatenate(tables)).to(DEV), Q1, "l2", "dot",
+                                       K1)
+    v2, i2 = v2.cpu().numpy(), i2.cpu().numpy()
+    for side, (v, i, vr, ir) in enumerate(results):
+        vs, is_ = v2[side * Q1:(side + 1) * Q1], i2[side * Q1:(side + 1) * Q1]
+        assert np.array_equal(vs, v) and np.array_equal(is_, i)
+        assert np.array_equal(vs[sample], vr) and np.array_equal(is_[sample], ir)
 
 
 def test_matrix_product_full_size(bolt):
