@@ -58,7 +58,7 @@ HBM_PEAK_GBPS = 8000.0
 # script's lean headline workload (--profile-kernels headline,single
 # --calib-copy: FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
 # what the counter reads for a 1 GiB device-to-device copy in the same runs
-# (FETCH_SIZE 524311.8 KiB for 1048576 KiB read: factor 2.0; WRITE_SIZE
+# (FETCH_SIZE 524310.2 KiB for 1048576 KiB read: factor 2.0; WRITE_SIZE
 # 1048576.0 KiB for 1048576 KiB written: factor 1.0).  Valid only for the
 # workload and kernel sources they were taken on: the sources are hashed,
 # and any change reports traffic as null until measured again.
@@ -66,10 +66,11 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC = {
     "scan_topk_mfma": {
-        "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 1000, "k": 100},
-        "fetch_kib": 9890.6,
-        "write_kib": 5810.6,
-        "sources_sha256": "01d5a0d15b40e8d8ba6d262aec409605992425f987d89fb212965c1df63ebee7",
+        # Q: queries per launch (both metrics' 1000 each)
+        "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 2000, "k": 100},
+        "fetch_kib": 11912.6,
+        "write_kib": 11624.8,
+        "sources_sha256": "7fe08542c32db10de3a313c140634f250f8673cc5dac53ea61997506d8355a3a",
     },
 }
 # the kernel's sources and the build flags (paper_1706_10283_amd/build.py)

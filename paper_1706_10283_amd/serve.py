@@ -6,8 +6,8 @@ little latency as possible.  This server keeps encoded databases resident in
 HBM and serves a stream of two request kinds:
 
 * query batches (q queries of J dimensions, one database, one metric, top k):
-  tables (bolt_build_luts) then scan + top-k (bolt_scan_topk) over the rows
-  committed when the request is admitted (its snapshot);
+  tables (bolt_build_luts) then scan + top-k over the rows committed when
+  the request is admitted (its snapshot);
 * inserts (n fp32 vectors): copied from host memory, encoded (bolt_encode)
   into the database's preallocated rows on their own stream, and made
   visible by advancing the database's committed-row watermark once encoded.
@@ -18,8 +18,11 @@ in arrival order until their reservation fits, and a request that could
 never fit (or an insert beyond the database's capacity) is refused.
 
 Continuous batching: whenever the GPU has free slots, every admitted query
-request is grouped by (database, metric, snapshot) and each group runs as
-one scan; groups go to several streams, so work admitted while earlier
+request is grouped by (database, snapshot, k) and each group runs as one
+scan per pair of metrics: a metric ranked by the smallest sums (L2) and one
+ranked by the largest (dot) share one two-metric call
+(bolt_scan_topk_split), so their queries read the codes once; groups go to
+several streams, so work admitted while earlier
 groups still run overlaps with them on the device, and inserts overlap with
 queries.  Results are bit-identical to running each request alone: sums are
 exact integers and top-k keys are totally ordered.
@@ -55,11 +58,31 @@ def scan_ws_reserve(rows: int, M: int, q: int, k: int) -> int:
     grows.  The larger of the request's own workspace and q times the
     per-query workspace of the smallest such call therefore bounds its share
     in every group, up to the alignment padding of the workspace's parts,
-    which 64 KiB per request covers."""
+    which 64 KiB per request covers.  A two-metric call needs the larger of
+    the workspaces of its whole and of either side, and each of those is
+    covered by the shares of the requests it holds."""
     qmin = 8 if (M == 8 or k > 128) else 3
     alone = B.bolt_scan_topk_ws_bytes(rows, M, q, k)
     per_min = B.bolt_scan_topk_ws_bytes(rows, M, qmin, k)
     return max(alone, -(-q * per_min // qmin)) + 65536
+
+
+def metric_calls(reqs):
+    """The scan calls of one group: [[(metric, [request indices])], ...],
+    each call one metric or two (a smallest-sums metric first, then a
+    largest-sums one: one two-metric call); metrics in order of first
+    appearance within each direction, leftovers of one direction paired
+    among themselves (a two-metric call of one direction is one scan)."""
+    parts = {}
+    for i, r in enumerate(reqs):
+        parts.setdefault(r.metric, []).append(i)
+    lo = [(m, ix) for m, ix in parts.items() if not B.metric_largest(m)]
+    hi = [(m, ix) for m, ix in parts.items() if B.metric_largest(m)]
+    calls = [[a, b] for a, b in zip(lo, hi)]
+    n = min(len(lo), len(hi))
+    rest = lo[n:] + hi[n:]
+    calls += [rest[j:j + 2] for j in range(0, len(rest), 2)]
+    return calls
 
 
 @dataclass
@@ -116,28 +139,49 @@ class GpuExecutor:
         return int(req.X.shape[0] * self.dbs[req.db].J * 4) + 4096
 
     # -- work
-    def launch_queries(self, reqs, db_i: int, metric: str, rows: int, k: int):
+    def launch_queries(self, reqs, db_i: int, rows: int, k: int):
+        """One group (one database, snapshot and k; any metrics): the queries
+        stacked metric by metric, one scan call per pair of metrics."""
         db = self.dbs[db_i]
         s = self.streams[self._next % len(self.streams)]
         self._next += 1
-        sizes = [r.Qv.shape[0] for r in reqs]
+        calls = metric_calls(reqs)
+        order = [i for call in calls for _, ix in call for i in ix]
+        sizes = [reqs[i].Qv.shape[0] for i in order]
         Q = sum(sizes)
         host_q = torch.empty((Q, db.J), dtype=torch.float32, pin_memory=True)
         o = 0
-        for r in reqs:
-            host_q[o:o + r.Qv.shape[0]] = torch.from_numpy(np.ascontiguousarray(r.Qv, dtype=np.float32))
-            o += r.Qv.shape[0]
+        for i in order:
+            n = reqs[i].Qv.shape[0]
+            host_q[o:o + n] = torch.from_numpy(np.ascontiguousarray(reqs[i].Qv, dtype=np.float32))
+            o += n
         with torch.cuda.stream(s):
             qd = host_q.to(self.device, non_blocking=True)
-            luts = db.luts(qd, metric, stream=s)
-            vals, idx = B.bolt_scan_topk(db.codes[:rows], luts, metric, k, stream=s)
+            luts = torch.empty((Q, db.M, 16), dtype=torch.uint8, device=self.device)
+            vals = torch.empty((Q, k), dtype=torch.uint16, device=self.device)
+            idx = torch.empty((Q, k), dtype=torch.int32, device=self.device)
+            o = 0
+            for call in calls:
+                a = o
+                for metric, ix in call:
+                    n = sum(reqs[i].Qv.shape[0] for i in ix)
+                    db.luts(qd[o:o + n], metric, out=luts[o:o + n], stream=s)
+                    o += n
+                codes = db.codes[:rows]
+                if len(call) == 1:
+                    B.bolt_scan_topk(codes, luts[a:o], call[0][0], k, vals=vals[a:o], idx=idx[a:o], stream=s)
+                else:
+                    n_lo = sum(reqs[i].Qv.shape[0] for i in call[0][1])
+                    B.bolt_scan_topk_split(codes, luts[a:o], n_lo, call[0][0], call[1][0], k, vals=vals[a:o],
+                                           idx=idx[a:o], stream=s)
             hv = torch.empty(vals.shape, dtype=torch.uint16, pin_memory=True)
             hi = torch.empty(idx.shape, dtype=torch.int32, pin_memory=True)
             hv.copy_(vals, non_blocking=True)
             hi.copy_(idx, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"event": ev, "keep": (host_q, qd, luts, vals, idx), "hv": hv, "hi": hi, "sizes": sizes}
+        return {"event": ev, "keep": (host_q, qd, luts, vals, idx), "hv": hv, "hi": hi, "sizes": sizes,
+                "order": order}
 
     def launch_insert(self, req: Request, row0: int):
         db = self.dbs[req.db]
@@ -155,10 +199,11 @@ class GpuExecutor:
         return handle["event"].query()
 
     def query_results(self, handle):
+        """Per request of the group, in the order launch_queries was given them."""
         hv, hi = handle["hv"].numpy(), handle["hi"].numpy()
-        out, o = [], 0
-        for q in handle["sizes"]:
-            out.append((hv[o:o + q].copy(), hi[o:o + q].copy()))
+        out, o = [None] * len(handle["order"]), 0
+        for i, q in zip(handle["order"], handle["sizes"]):
+            out[i] = (hv[o:o + q].copy(), hi[o:o + q].copy())
             o += q
         return out
 
@@ -325,7 +370,7 @@ class Server:
                     self.budget_stalls += 1
                     break
                 if r.kind == "query":
-                    key = (r.db, r.metric, self.committed[r.db], r.k)
+                    key = (r.db, self.committed[r.db], r.k)
                     if key not in groups and n_groups + len(groups) >= self.max_groups:
                         self.group_stalls += 1
                         break
@@ -353,10 +398,10 @@ class Server:
                     insert_queue.setdefault(r.db, deque()).append(r)
                     inflight.append(("insert", h, [r], fp))
                 self.peak = max(self.peak, self.in_use)
-            for (db_i, metric, rows, k), reqs in groups.items():
+            for (db_i, rows, k), reqs in groups.items():
                 fp = sum(r.reserved for r in reqs)
                 try:
-                    h = self.ex.launch_queries(reqs, db_i, metric, rows, k)
+                    h = self.ex.launch_queries(reqs, db_i, rows, k)
                 except Exception as e:
                     for r in reqs:
                         r.status, r.error, r.done = "failed", str(e), self.clock() - t0

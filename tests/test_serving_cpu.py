@@ -42,13 +42,13 @@ class FakeExecutor:
         _, _, l8 = oracle.luts(Qv, db.C, db.M, metric, db.a, db.offs)
         return oracle.topk(oracle.scan(db.codes[:rows], l8), k, metric == "dot")
 
-    def launch_queries(self, reqs, db_i, metric, rows, k):
+    def launch_queries(self, reqs, db_i, rows, k):
         self.launches.append(("query", db_i, len(reqs)))
         if len(self.launches) in self.fail_on:
             raise RuntimeError("injected failure")
         db = self.dbs[db_i]
-        Qv = np.concatenate([r.Qv for r in reqs])
-        v, i = self._alone(db, Qv, metric, k, rows)
+        out = [self._alone(db, r.Qv, r.metric, k, rows) for r in reqs]
+        v, i = np.concatenate([o[0] for o in out]), np.concatenate([o[1] for o in out])
         sizes = [r.Qv.shape[0] for r in reqs]
         return {"left": self.delay, "v": v, "i": i, "sizes": sizes}
 
@@ -96,7 +96,8 @@ def _requests(dbs, n=40, seed=3):
         else:
             q = int(rng.integers(1, 6))
             off = int(rng.integers(0, 400))
-            reqs.append(Request(i, "query", d, 0.0, metric="l2", k=7, Qv=pool[off:off + q]))
+            metric = "l2" if i % 3 else "dot"
+            reqs.append(Request(i, "query", d, 0.0, metric=metric, k=7, Qv=pool[off:off + q]))
     return reqs
 
 
@@ -209,3 +210,30 @@ def test_insert_failing_on_the_device_blocks_the_watermark():
     srv.run(reqs, realtime=False)
     assert [r.status for r in reqs] == ["done", "failed"]
     assert srv.committed[0] == srv.reserved[0] == N + 30
+
+
+def test_metric_calls_pairs_directions():
+    """A group's scan calls: a smallest-sums metric and a largest-sums one
+    share a call (smallest first); the rest pair up within their direction;
+    every request lands in exactly one call."""
+    from paper_1706_10283_amd.serve import metric_calls
+
+    def reqs(metrics):
+        return [Request(i, "query", 0, 0.0, metric=m, k=5, Qv=np.zeros((1, 4))) for i, m in enumerate(metrics)]
+
+    def names(calls):
+        return [[m for m, _ in c] for c in calls]
+
+    assert names(metric_calls(reqs(["l2"]))) == [["l2"]]
+    assert names(metric_calls(reqs(["dot", "l2", "dot", "l2"]))) == [["l2", "dot"]]
+    assert metric_calls(reqs(["dot", "l2", "dot", "l2"])) == [[("l2", [1, 3]), ("dot", [0, 2])]]
+    assert names(metric_calls(reqs(["l2", "l1", "dot"]))) == [["l2", "dot"], ["l1"]]
+    assert names(metric_calls(reqs(["l2", "l1", "lp3", "cosine"]))) == [["l2", "cosine"], ["l1", "lp3"]]
+    assert names(metric_calls(reqs(["dot", "cosine", "dot"]))) == [["dot", "cosine"]]
+    for ms in (["l2", "dot", "l1", "cosine", "lp4", "dot"], ["dot"] * 3 + ["l2"]):
+        calls = metric_calls(reqs(ms))
+        got = sorted(i for c in calls for _, ix in c for i in ix)
+        assert got == list(range(len(ms)))
+        for c in calls:
+            assert 1 <= len(c) <= 2
+
