@@ -13,9 +13,11 @@
 // (ties to the lowest index) is reproducible; the expanded form
 // |x|^2 - 2 x.c + |c|^2 would cancel badly.  Codes are gathered per row in
 // LDS (M bytes per row, dynamic) and written back as packed bytes with
-// coalesced dword stores.  Rows are staged 64 dimensions at a time, so a
-// workgroup holds about 19 KB of LDS and 39 registers per lane: eight
-// workgroups per CU keep the VALU busy.
+// coalesced dword stores.  Rows are staged 32 dimensions at a time (64 for
+// subspaces wider than 8), and the next chunk's loads are issued into
+// registers before the current chunk is computed, so a workgroup waits for
+// HBM once (its first chunk) instead of once per chunk; it holds about 11 KB
+// of LDS (J = 128, M = 32) and eight workgroups per CU keep the VALU busy.
 #include "common.hpp"
 
 namespace {
@@ -23,8 +25,11 @@ namespace {
 constexpr int kRows = 64;                 // rows per tile = lanes per wave
 constexpr int kWaves = 4;
 constexpr int kThreads = kRows * kWaves;
-constexpr int kChunkDims = 64;            // dimensions staged per pass (17 KB of rows: eight workgroups per CU)
-constexpr int kStride = kChunkDims + 4;   // LDS row stride in floats (4 mod 64 banks)
+
+// Dimensions staged per pass: 32 (9 KB of rows) while that holds at least
+// four subspaces, one per wave; 64 for wider subspaces.
+template <int SUB>
+constexpr int chunk_dims() { return SUB <= 8 ? 32 : 64; }
 
 template <int SUB>
 __device__ __forceinline__ int nearest(const float *x, const float *__restrict__ c)
@@ -94,6 +99,8 @@ __global__ __launch_bounds__(kThreads) void encode_lds_kernel(
     uint8_t *__restrict__ codes, int vec4, int byte_store)
 {
     constexpr int G = SUB >= 4 ? 1 : 4 / SUB;
+    constexpr int kChunkDims = chunk_dims<SUB>();
+    constexpr int kStride = kChunkDims + 4;   // LDS row stride in floats (4 mod 64 banks)
     constexpr int kChunkM = kChunkDims / SUB;
     static_assert(kChunkM >= 1 && kChunkM % G == 0, "chunk must hold whole lane steps");
     __shared__ __attribute__((aligned(16))) float xs[kRows * kStride];
@@ -105,24 +112,46 @@ __global__ __launch_bounds__(kThreads) void encode_lds_kernel(
     const int64_t n0 = (int64_t)blockIdx.x * kRows;
     const int rows = (int)((N - n0) < kRows ? (N - n0) : kRows);
 
+    constexpr int d4 = kChunkDims / 4;
+    constexpr int PF = kRows * d4 / kThreads;   // float4 per thread of a full chunk
+    float4 pf[PF];
+    bool have_pf = false;
+    // the float4 loads of a full chunk into registers (rows clamped: unconditional)
+    auto prefetch = [&](int64_t jj) {
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int e = tid + p * kThreads;
+            const int r0 = e / d4, c4 = e % d4;
+            const int r = r0 < rows ? r0 : rows - 1;
+            pf[p] = __builtin_bit_cast(float4, __builtin_nontemporal_load(
+                reinterpret_cast<const float __attribute__((ext_vector_type(4))) *>(X + (n0 + r) * ldx + jj + 4 * c4)));
+        }
+    };
     for (int m0 = 0; m0 < M; m0 += kChunkM) {
         const int mc = (M - m0) < kChunkM ? (M - m0) : kChunkM;
         const int dims = mc * SUB;
         const int64_t j0 = (int64_t)m0 * SUB;
         if (m0)
             __syncthreads();
-        if (vec4 && dims == kChunkDims) {   // a full chunk: 16 float4 per row, no division
-            constexpr int d4 = kChunkDims / 4;
-            for (int e = tid; e < rows * d4; e += kThreads) {
+        if (vec4 && dims == kChunkDims) {   // a full chunk: d4 float4 per row, no division
+            if (!have_pf)
+                prefetch(j0);
+#pragma unroll
+            for (int p = 0; p < PF; ++p) {
+                const int e = tid + p * kThreads;
                 const int r = e / d4, c4 = e % d4;
-                float4 v = __builtin_bit_cast(float4, __builtin_nontemporal_load(
-                    reinterpret_cast<const float __attribute__((ext_vector_type(4))) *>(X + (n0 + r) * ldx + j0 + 4 * c4)));
-                *reinterpret_cast<float4 *>(&xs[r * kStride + 4 * c4]) = v;
+                if (r < rows)
+                    *reinterpret_cast<float4 *>(&xs[r * kStride + 4 * c4]) = pf[p];
             }
+            // the next full chunk's loads fly while this one is computed
+            const int mn = m0 + kChunkM;
+            have_pf = mn < M && (M - mn) * SUB >= kChunkDims;
+            if (have_pf)
+                prefetch((int64_t)mn * SUB);
         } else if (vec4) {
-            const int d4 = dims >> 2;
-            for (int e = tid; e < rows * d4; e += kThreads) {
-                int r = e / d4, c4 = e - r * d4;
+            const int dq = dims >> 2;
+            for (int e = tid; e < rows * dq; e += kThreads) {
+                int r = e / dq, c4 = e - r * dq;
                 // streamed once: non-temporal loads (about 4% faster here)
                 float4 v = __builtin_bit_cast(float4, __builtin_nontemporal_load(
                     reinterpret_cast<const float __attribute__((ext_vector_type(4))) *>(X + (n0 + r) * ldx + j0 + 4 * c4)));
