@@ -45,7 +45,7 @@ struct DevDb {
     int32_t Q;
     int32_t k;
     int32_t largest;
-    // speculative starting bounds (matrix-core databases from kSpecMinRows rows)
+    // speculative starting bounds (matrix-core databases from kBatchSpecMinRows rows)
     uint16_t *sdist;   // sample group minima [Q][G], or null: no speculation
     int64_t G;         // group minima per query: G / kSpecGroups chunks at a stride of `stride` rows
     int64_t stride;
@@ -316,8 +316,8 @@ struct Layout {
     int64_t n_tiles, n_queries, n_samples, max_rb;
 };
 
-// Batched databases sample their starting bounds from 2^16 rows, a quarter
-// of the one-database threshold: without a bound, the tiles of a database
+// Batched databases sample their starting bounds from 2^16 rows, half the
+// one-database threshold: without a bound, the tiles of a database
 // too small to sample append and prune most passes.  Over 256 databases of
 // 1e3 to 2e6 rows (log-uniform) the whole batch took 11.0 ms sampling from
 // 2^19 rows, 9.0 from 2^17, 8.8 from 2^16 and 9.0-9.3 from 2^15, where a few
