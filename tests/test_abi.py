@@ -87,7 +87,8 @@ def test_train_host_matches_oracle_definition(lib):
 def test_serving_workspace_reservation_covers_any_group(lib):
     """The serving admission reserves scan_ws_reserve(q) per request of q
     queries; admitted requests of one database run as one call, so the call's
-    workspace must not exceed the sum of its members' reservations.  Checked
+    workspace must not exceed the sum of its members' reservations, also when
+    the group's requests form the two sides of a two-metric call.  Checked
     over the serving shapes (one to 64 queries per request: the few-query,
     part-filled matrix-core and many-query paths, with and without sampled
     bounds)."""
@@ -103,3 +104,9 @@ def test_serving_workspace_reservation_covers_any_group(lib):
                 group = lib.bolt_scan_topk_ws_bytes(N, M, int(sizes.sum()), k)
                 reserved = sum(scan_ws_reserve(N, M, int(q), k) for q in sizes)
                 assert group <= reserved, (N, M, sizes.tolist(), k, group, reserved)
+                # the same requests as the two sides of one two-metric call
+                cut = int(rng.integers(0, len(sizes) + 1))
+                q_lo, Q = int(sizes[:cut].sum()), int(sizes.sum())
+                split = lib.bolt_scan_topk_split_ws_bytes(N, M, Q, q_lo, k)
+                assert split >= group
+                assert split <= reserved, (N, M, sizes.tolist(), cut, k, split, reserved)
