@@ -58,7 +58,7 @@ HBM_PEAK_GBPS = 8000.0
 # script's lean headline workload (--profile-kernels headline,single
 # --calib-copy: FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
 # what the counter reads for a 1 GiB device-to-device copy in the same runs
-# (FETCH_SIZE 524310.6 KiB for 1048576 KiB read: factor 2.0; WRITE_SIZE
+# (FETCH_SIZE 524309.7 KiB for 1048576 KiB read: factor 2.0; WRITE_SIZE
 # 1048576.0 KiB for 1048576 KiB written: factor 1.0).  Valid only for the
 # workload and kernel sources they were taken on: the sources are hashed,
 # and any change reports traffic as null until measured again.
@@ -68,9 +68,9 @@ TRAFFIC = {
     "scan_topk_mfma": {
         # Q: queries per launch (both metrics' 1000 each)
         "workload": {"N": 1_000_000, "J": 128, "M": 32, "Q": 2000, "k": 100},
-        "fetch_kib": 11912.7,
-        "write_kib": 11625.9,
-        "sources_sha256": "3f23329587a0a0a84f1a47ea8a33f06286710fc48d519aa9e554e9f0f69f3721",
+        "fetch_kib": 11912.6,
+        "write_kib": 11624.9,
+        "sources_sha256": "a11b11cd921198ba83ae22c1efb39d0fab8c7f3b8cc61833923dcfc7216e3494",
     },
 }
 # the kernel's sources and the build flags (paper_1706_10283_amd/build.py)

@@ -497,10 +497,10 @@ int bolt_debug_force_unfused_topk(int32_t on);
 int bolt_debug_force_fused_kind(int32_t kind);
 /*
  * Test hook: speculative starting bounds of fused scans with many queries
- * over a whole database (-1 automatic and 1 on, both from 2^17 rows; 0 off;
- * 2 as 1 with every bound made to fail, so that every query takes the exact
- * recomputation; the databases of a batched plan sample from 2^16 rows under
- * -1, 1 and 2).  Results are the same in every mode.
+ * over a whole database (-1 automatic and 1 on, both from 2^16 rows, also
+ * for the databases of a batched plan; 0 off; 2 as 1 with every bound made
+ * to fail, so that every query takes the exact recomputation).  Results are
+ * the same in every mode.
  */
 int bolt_debug_speculation(int32_t mode);
 /*

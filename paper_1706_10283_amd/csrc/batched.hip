@@ -45,7 +45,7 @@ struct DevDb {
     int32_t Q;
     int32_t k;
     int32_t largest;
-    // speculative starting bounds (matrix-core databases from kBatchSpecMinRows rows)
+    // speculative starting bounds (matrix-core databases from kSpecMinRows rows)
     uint16_t *sdist;   // sample group minima [Q][G], or null: no speculation
     int64_t G;         // group minima per query: G / kSpecGroups chunks at a stride of `stride` rows
     int64_t stride;
@@ -316,22 +316,12 @@ struct Layout {
     int64_t n_tiles, n_queries, n_samples, max_rb;
 };
 
-// Batched databases sample their starting bounds from 2^16 rows, half the
-// one-database threshold: without a bound, the tiles of a database
-// too small to sample append and prune most passes.  Over 256 databases of
-// 1e3 to 2e6 rows (log-uniform) the whole batch took 11.0 ms sampling from
-// 2^19 rows, 9.0 from 2^17, 8.8 from 2^16 and 9.0-9.3 from 2^15, where a few
-// sampled bounds failed and were recomputed.
-constexpr int64_t kBatchSpecMinRows = 1 << 16;
-
 // Speculative bounds of a matrix-core database (as the one-database path
-// decides them, from kBatchSpecMinRows rows): the number of sample chunks,
-// or 0 for none.
+// decides them): the number of sample chunks, or 0 for none.
 int64_t spec_chunks(const bolt_batch_db &d, int kind)
 {
     const int mode = bolt::g_spec_mode;
-    const int64_t min_rows = mode > 0 ? std::min(bolt::kSpecMinRowsForced, kBatchSpecMinRows) : kBatchSpecMinRows;
-    if (kind != 3 || mode == 0 || d.N < min_rows)
+    if (kind != 3 || mode == 0 || d.N < (mode > 0 ? bolt::kSpecMinRowsForced : bolt::kSpecMinRows))
         return 0;
     int64_t nsc = d.N / 32 / bolt::kSpecSpan;
     nsc = nsc < 16 ? 16 : (nsc > 256 ? 256 : nsc);

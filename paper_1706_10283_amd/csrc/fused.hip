@@ -1,7 +1,7 @@
 // Scan fused with top-k selection (Sec. 3.1 scan; Sec. 1.2 the k closest
 // vectors) for gfx950: the [Q][N] sums are never written to memory.
 //
-// Stage 0 (a whole database of 2^17 rows or more): sampled starting bounds.
+// Stage 0 (a whole database of 2^16 rows or more): sampled starting bounds.
 // A sample launch takes the d of every query over chunks of rows at a
 // regular stride on the matrix cores and keeps one minimum per 16 rows; a
 // selection launch gives each query the exact r-th smallest of its minima

@@ -72,11 +72,15 @@ extern int g_spec_mode;           // speculative bounds: -1 automatic, 0 off, 1 
 constexpr int64_t kSpecSpan = 1024;
 constexpr int kSpecGroup = 16;
 constexpr int kSpecGroups = (int)kSpecSpan / kSpecGroup;   // group minima per chunk
-// From 2^17 rows: at 1.5e5 to 5e5 rows, M = 16 and 32, 1 to 1000 queries, a
-// sampled call took 0.19-0.30 of the time of one without (whose tiles keep
-// slots of candidates for every row block and merge them all).
-constexpr int64_t kSpecMinRows = 1 << 17;
-constexpr int64_t kSpecMinRowsForced = 1 << 17;
+// From 2^16 rows: at 7e4 to 5e5 rows, M = 16 and 32, 1 to 1000 queries, a
+// sampled call took 0.19-0.31 of the time of one without (whose tiles keep
+// slots of candidates for every row block and merge them all).  Over 256
+// batched databases of 1e3 to 2e6 rows the whole batch took 11.0 ms
+// sampling from 2^19 rows, 9.0 from 2^17, 8.8 from 2^16 and 9.0-9.3 from
+// 2^15, where a few sampled bounds (a sample of half the rows in
+// 1024-row chunks) failed and were recomputed.
+constexpr int64_t kSpecMinRows = 1 << 16;
+constexpr int64_t kSpecMinRowsForced = 1 << 16;
 constexpr int64_t kSpecMaxDists = 1 << 26;
 int spec_rank(int k, double pr);
 

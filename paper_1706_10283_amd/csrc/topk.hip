@@ -497,7 +497,7 @@ extern "C" int bolt_debug_force_unfused_topk(int32_t on)
 }
 
 // Test hook: speculative bounds of many-query scans (-1 automatic, 0 off,
-// 1 on from 2^17 rows (as -1), 2 as 1 with every bound failing: all queries are
+// 1 on from 2^16 rows (as -1), 2 as 1 with every bound failing: all queries are
 // recomputed by the exact fallback).
 extern "C" int bolt_debug_speculation(int32_t mode)
 {

@@ -50,7 +50,7 @@ def _ordered(codes, luts, M, metric, order):
     return np.ascontiguousarray(codes[perm])
 
 
-# (M, Q, N, k, metric, order): whole databases of 2^17 rows or more (sampled
+# (M, Q, N, k, metric, order): whole databases of 2^16 rows or more (sampled
 # bounds by default) on the one-query, few-query and matrix-core kernels
 CASES = [
     (32, 40, 600_000, 100, "l2", "sorted"), (16, 33, 530_000, 128, "dot", "sorted"),

@@ -106,7 +106,7 @@ def test_batched_rejects_bad_input(bolt):
         bolt.BatchPlan([{"codes": codes, "luts": luts, "k": 300}])
 
 
-# databases large enough for speculative bounds under test mode 1 (2^17 rows),
+# databases large enough for speculative bounds (2^16 rows),
 # with matrix-core tiles (M = 16, 32 or 64, 8 or more queries), beside others
 SPEC_DBS = [
     (32, 140000, 40, 100, "l2", "rand"), (16, 150000, 70, 64, "dot", "coarse"), (32, 131072, 33, 1, "dot", "const"),

@@ -569,7 +569,7 @@ def test_scan_topk_speculation_few_parity(bolt, mode, metric, M, Q, N, k, kind):
 @pytest.mark.parametrize("M,Q,N,k,kind", [(32, 12, 600_000, 100, "rand"), (16, 31, 524_288, 128, "coarse"),
                                           (64, 8, 530_000, 100, "rand")])
 def test_scan_topk_default_large_part_filled_tile(bolt, metric, M, Q, N, k, kind):
-    """The automatic path at 2^17 rows or more with 8 to 31 queries: sampled
+    """The automatic path at 5e5 rows or more with 8 to 31 queries: sampled
     bounds and one part-filled 32-query matrix-core tile (what groups of a
     served workload mostly take); equal to the oracle."""
     seed = 19 * M + 3 * Q + N + k
