@@ -54,6 +54,16 @@ def test_validation_without_gpu(lib):
     for good in (0, 1, 2, 4, lib.metric_lp(1), lib.metric_lp(16)):
         assert L.bolt_build_luts(None, 0, 32, 32, None, 8, good, 1.0, None, None, None, None) == lib.BOLT_OK
     assert lib.metric_id("lp3") == 3 + 256 * 3 and lib.metric_largest("cosine") and not lib.metric_largest("lp2")
+    # two-metric scan + top-k: split index, metrics and shape checked first
+    split = lambda N, M, Q, q_split, lo, hi, k: L.bolt_scan_topk_split(
+        None, N, M, None, Q, q_split, lo, hi, k, None, None, None, 0, None)
+    assert split(10, 32, 4, 5, 0, 1, 3) == lib.BOLT_ERR_INVALID
+    assert "q_split" in lib.last_error()
+    assert split(10, 32, 4, -1, 0, 1, 3) == lib.BOLT_ERR_INVALID
+    assert split(10, 32, 4, 2, 0, 5, 3) == lib.BOLT_ERR_INVALID
+    assert split(10, 31, 4, 2, 0, 1, 3) == lib.BOLT_ERR_SHAPE
+    assert split(10, 32, 0, 0, 0, 1, 3) == lib.BOLT_OK
+    assert split(10, 32, 4, 2, 0, 1, 3) == lib.BOLT_ERR_INVALID   # null pointers with work
     # misaligned codes or tables are rejected before anything is enqueued (the
     # pointers are never dereferenced on the host)
     P = ctypes.c_void_p
